@@ -1,0 +1,143 @@
+/*
+ * eik.h -- C ABI of the MI355X (gfx950) Eikonal solver.
+ *
+ * Solves the first-order upwind discretisation of |grad u| F = 1 on a uniform 3D grid
+ * (Chacon & Vladimirsky, "A parallel Heap-Cell Method for Eikonal equations", Section 1.1,
+ * eq. (2)): at every node outside the exit set,
+ *     sum over axes of max(D^-U, -D^+U, 0)^2 = 1 / F^2,
+ * with U = q on the exit nodes and U = +inf beyond the grid (the exit set Q of eq. (1); the rest
+ * of the boundary is non-inflow).  The solver follows the Heap-Cell Method (Section 4,
+ * Algorithms 1 and 3) and its parallel form (Section 5, Algorithm 2): the grid is split into
+ * cubic cells of `cell` nodes per side, cells are swept with Gauss-Seidel / locking-sweeping
+ * updates, and a cell-priority worklist (cell values, eq. (5)) decides which cells are swept.
+ * The discrete solution is unique, so the result does not depend on cell size, schedule or
+ * processing order (Section 4, "Assigning Cell Values") beyond rounding.
+ *
+ * Conventions
+ *   grid    dims = {nx, ny, nz}; node (i, j, k) lies at (i h, j h, k h).  Every node array is
+ *           row-major with i fastest: index = i + nx * (j + ny * k), i.e. C order [nz][ny][nx].
+ *   memory  Pointers marked "device" must be device memory of the current HIP device (or
+ *           managed memory).  The caller owns every buffer it passes; the library owns only
+ *           its per-stream workspace, which it allocates on first use, grows when a larger
+ *           problem arrives on the same stream, and frees in eik_release().
+ *   streams All GPU work of a call is enqueued on `stream` (NULL = the default stream) and the
+ *           call returns once it is enqueued.  Calls on different streams may run concurrently;
+ *           each stream has its own workspace.  Calls on one stream are ordered by the stream.
+ *   errors  A negative return value is a synchronous error: nothing was enqueued and u_out is
+ *           untouched.  Conditions found on the device (invalid speeds, a cap on rounds) are
+ *           recorded in the stream's workspace and returned by eik_stream_status(); u_out then
+ *           holds an upper bound of the solution (values only decrease during the solve).
+ */
+#ifndef EIK_H_
+#define EIK_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define EIK_OK 0
+#define EIK_EINVAL (-1)     /* invalid argument                                              */
+#define EIK_ENOMEM (-2)     /* device or pinned-host allocation failed                       */
+#define EIK_EHIP (-3)       /* a HIP runtime call failed                                     */
+#define EIK_ENOCONV (-4)    /* the round cap was reached before the worklist emptied         */
+#define EIK_ECANCELLED (-5) /* the solve was stopped by the device watchdog                  */
+
+/* Element types of F. */
+#define EIK_F64 0
+#define EIK_F32 1
+
+/* Arithmetic modes (eik_options.mode). */
+#define EIK_MODE_FP64 0  /* all storage and arithmetic in FP64                            */
+
+/* Exit set Q' and its values q (Section 4 notation: Q' = X intersect Q, values prescribed). */
+typedef struct eik_sources {
+    int64_t n;            /* number of exit nodes, >= 0 (0: every value is +inf)            */
+    const int64_t* idx3;  /* n x 3 node indices (i, j, k), 0 <= i < nx etc.                 */
+    const double* q;      /* n exit values, finite and >= 0; a node listed twice keeps min q */
+    int on_device;        /* 0: idx3 and q are host memory (validated synchronously);
+                             1: device memory (validated on the device, see errors above)   */
+} eik_sources;
+
+/* Optional knobs; zero-initialise for the defaults. */
+typedef struct eik_options {
+    int mode;             /* EIK_MODE_*; default EIK_MODE_FP64                               */
+    double delta;         /* width of the cell-value band swept per round (the lowest bucket
+                             of the priority worklist): cells with value < min + delta are
+                             swept, the rest wait.  0 = default (+inf: every queued cell)    */
+    int64_t max_rounds;   /* cap on worklist rounds; 0 = default (1 << 20)                    */
+    int max_sweeps;       /* cap on sweeps per cell visit before the cell is re-queued;
+                             0 = default (512)                                              */
+    int workers;          /* persistent workgroups; 0 = as many as fit on the device         */
+    uint64_t shuffle;     /* 0 = natural order; otherwise seed of a pseudo-random permutation
+                             of the order in which queued cells are taken (order tests)     */
+} eik_options;
+
+/* Per-solve counters, filled by eik_stream_status(). */
+typedef struct eik_stats {
+    int64_t rounds;       /* worklist rounds executed                                        */
+    int64_t visits;       /* cell visits (one pop-and-sweep of one cell)                     */
+    int64_t sweeps;       /* directional sweeps over all visits                              */
+    int64_t updates;      /* local solves evaluated (grid-node updates)                      */
+    int64_t deferred;     /* queued cells left for a later round by the priority band       */
+    int64_t requeued;     /* visits that hit max_sweeps and re-queued their cell             */
+    int64_t cells;        /* cells in the decomposition                                      */
+    int64_t status;       /* same as the return value of eik_stream_status()                 */
+} eik_stats;
+
+/*
+ * eik_solve -- solve eq. (2) on one grid.
+ *   dims     host array {nx, ny, nz}, each >= 2, product < 2^31.
+ *   h        grid step, finite and > 0.
+ *   F        device array of nx*ny*nz speeds of type f_dtype, each finite and > 0 (checked on
+ *            the device; a violation yields EIK_EINVAL from eik_stream_status()).
+ *   f_dtype  EIK_F64 or EIK_F32.  Speeds are widened exactly to FP64; s = h / F is formed in FP64.
+ *   sources  exit nodes and values (see eik_sources).
+ *   u_out    device array of nx*ny*nz doubles; receives U (+inf where no exit node is reachable,
+ *            q at exit nodes).  May not alias F.
+ *   cell     cell side r in nodes: 4 or 8.  Cells are anchored at node 0; the last layer of
+ *            cells along an axis is partial when r does not divide the node count.
+ *   tol      kappa >= 0, the early-termination threshold of the "early sweep termination"
+ *            subsection: sweeping inside a cell stops after a sweep whose largest decrease is
+ *            <= tol.  0 runs every cell to an exact floating-point fixed point.  Neighbour
+ *            cells are re-queued on any strict decrease of a border value regardless of tol.
+ *   stream   hipStream_t to enqueue on.
+ * Returns EIK_OK or a negative code (nothing enqueued).
+ */
+int eik_solve(const int64_t dims[3], double h, const void* F, int f_dtype,
+              const eik_sources* sources, double* u_out, int cell, double tol,
+              hipStream_t stream);
+
+/* eik_solve with options (NULL options = defaults). */
+int eik_solve_ex(const int64_t dims[3], double h, const void* F, int f_dtype,
+                 const eik_sources* sources, double* u_out, int cell, double tol,
+                 hipStream_t stream, const eik_options* options);
+
+/* Device bytes of the workspace one solve of this size needs (for admission control).
+ * f_dtype as in eik_solve.  Returns EIK_OK or EIK_EINVAL. */
+int eik_query_workspace(const int64_t dims[3], int cell, int f_dtype, int mode, size_t* bytes);
+
+/* Waits for all work on `stream`, then returns the device-side status of the last solve
+ * enqueued on it (EIK_OK, EIK_EINVAL, EIK_ENOCONV, EIK_ECANCELLED) and, if stats != NULL,
+ * its counters.  Returns EIK_EINVAL if no solve was ever enqueued on the stream. */
+int eik_stream_status(hipStream_t stream, eik_stats* stats);
+
+/* Human-readable name of a status code (static storage). */
+const char* eik_strerror(int code);
+
+/* Frees every workspace (waits for their streams first). */
+void eik_release(void);
+
+/* Library version string (static storage). */
+const char* eik_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIK_H_ */

@@ -1,0 +1,61 @@
+// eik_internal.h -- types shared by the kernels and the host API of libeik (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/eik.h"
+
+namespace eik {
+
+// Cell flag word (one per cell and round parity).
+constexpr uint32_t FL_FACES = 0x3Fu;      // bit f: face f received new inflow (0 -x ... 5 +z)
+constexpr uint32_t FL_ALL = 1u << 6;      // every node active (first visit / re-queue)
+constexpr uint32_t FL_QUEUED = 1u << 7;   // already in that round's list
+constexpr int FL_DIR_SHIFT = 8;           // bits 8..15: preferred sweep directions
+
+// Device status values are the public codes.
+constexpr int EIK_EINVAL_DEV = EIK_EINVAL;
+constexpr int EIK_ENOCONV_DEV = EIK_ENOCONV;
+constexpr int EIK_ECANCELLED_DEV = EIK_ECANCELLED;
+
+// Persistent workers per workgroup (each wave64 is one worker).
+constexpr int kWavesPerGroup = 4;
+
+// Counter slots.
+enum { ST_ROUNDS = 0, ST_VISITS, ST_SWEEPS, ST_UPDATES, ST_DEFERRED, ST_REQUEUED, ST_COUNT = 8 };
+
+// Per-round control block: list length, pop cursor, smallest cell value in the list.
+struct RoundCtl {
+    uint32_t count;
+    uint32_t cursor;
+    uint64_t minkey;
+};
+
+struct SolveParams {
+    int nx, ny, nz;        // grid nodes per axis
+    int ncx, ncy, ncz;     // cells per axis
+    int ncell;             // ncx * ncy * ncz
+    int max_rounds;
+    int max_sweeps;
+    double h, tol, delta;
+    uint64_t shuffle;
+    uint64_t watchdog_polls;  // polls of the barrier word before a wait is abandoned
+    double* u;             // [ncell][r^3] cell-blocked values
+    void* fw;              // [ncell][r^3] cell-blocked speeds (F dtype); 0 padding, <0 exit
+    const void* f;         // same pointer, read-only view used by the sweeps
+    double* faces;         // [ncell][6][r^2] border layers
+    uint64_t* key[2];      // cell values (FP64 bit patterns, all >= +0)
+    uint32_t* flags[2];
+    int32_t* list[2];
+    RoundCtl* ctl;         // [4] control blocks, slot = round & 3
+    uint32_t* bar;         // [2] grid barrier: arrivals, generation
+    int* status;           // device status word
+    unsigned long long* stats;  // [ST_COUNT]
+};
+
+hipError_t launch_solve(const SolveParams& P, int cell, int f_dtype, const void* F, int64_t nsrc,
+                        const int64_t* idx3, const double* q, double* u_out, hipStream_t s,
+                        int workers, int* used);
+
+}  // namespace eik

@@ -1,0 +1,722 @@
+// eik_kernels.hip -- gfx950 kernels of the cell-scheduled Eikonal solver.
+//
+// Method: Chacon & Vladimirsky, "A parallel Heap-Cell Method for Eikonal equations".
+//   * local solve of eq. (2) (Section 1.1) at one node from its three upwind axis values;
+//   * modified locking-sweeping update inside a cell (Algorithm 3): active flags, strict
+//     decrease, activation of larger neighbours, tagging of "currently downwind" cells;
+//   * cell values of eq. (5) with the reset to +inf on removal (Section 4) and the initial
+//     cell values of the exit cells;
+//   * preferred sweep directions set by the tagging neighbour (Section 4, "Processing cells");
+//   * the parallel main loop of Algorithm 2, re-designed for one GPU: every wave64 is a
+//     worker that pops cells; cells are popped in rounds from a device worklist, and each
+//     round takes the cells whose value lies in the lowest band [min, min + delta) -- a
+//     bucketed priority queue in place of the per-thread heaps of Algorithms 2, 4 and 5.
+//
+// GPU design notes (what differs from the paper's shared-memory CPU design):
+//   * The grid is stored cell-blocked (each r^3 cell contiguous) and every cell also keeps a
+//     copy of its six border layers ("faces"), so the one-node halo of a cell is read as six
+//     contiguous r^2 runs and the cell as one r^3 run.
+//   * A visit stages the cell, its halo and s = h/F in LDS and runs the in-cell sweeps there;
+//     a sweep in direction d visits the planes x'+y'+z' = p of the reflected cell coordinates
+//     in increasing p (the Cuthill-McKee plane order of Section 3 used inside one cell): nodes
+//     of one plane do not depend on each other, so one wave updates a whole plane per step
+//     and the result equals a lexicographic Gauss-Seidel sweep in direction d.
+//   * Active flags never cross a cell boundary.  Instead the tagging cell sets a dirty bit for
+//     the face it changed; the tagged cell activates the layer next to every dirty face.
+//   * Rounds are separated by a grid barrier inside one persistent cooperative launch.  The
+//     cell state (value, flags, membership) is double-buffered by round parity: a visit in round
+//     t only consumes state produced in round t-1, whose data the barrier made visible across
+//     the eight XCD-local L2 caches; state produced in round t is consumed in round t+1.
+//     Halo values read during a round may be older than a concurrent neighbour's writes; values
+//     only decrease, so they are upper bounds, and the neighbour's tag re-queues the cell.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <cstdlib>
+
+#include "eik_internal.h"
+
+namespace eik {
+
+// ------------------------------------------------------------------------------------------
+// Constant tables.
+
+// Nodes of a cell of side R grouped by diagonal plane p = x + y + z (canonical direction +++),
+// packed as x | y << 5 | z << 10; 0xFFFF marks an unused (plane, lane) slot.  Planes with more
+// than 64 nodes (R > 8) are spread over several 64-lane passes: slot = (p * passes + pass) * 64.
+template <int R>
+struct PlaneTable {
+    static constexpr int NP = 3 * R - 2;
+    static constexpr int MAXP = (R <= 4) ? 12 : (R <= 8 ? 48 : 192);
+    static constexpr int PASSES = (MAXP + 63) / 64;
+    uint16_t slot[NP * PASSES * 64];
+    constexpr PlaneTable() : slot() {
+        for (int i = 0; i < NP * PASSES * 64; ++i) slot[i] = 0xFFFF;
+        for (int p = 0; p < NP; ++p) {
+            int n = 0;
+            for (int z = 0; z < R; ++z)
+                for (int y = 0; y < R; ++y) {
+                    int x = p - y - z;
+                    if (x < 0 || x >= R) continue;
+                    slot[p * PASSES * 64 + n] = (uint16_t)(x | (y << 5) | (z << 10));
+                    ++n;
+                }
+        }
+    }
+};
+
+__constant__ PlaneTable<4> kPlanes4 = PlaneTable<4>();
+__constant__ PlaneTable<8> kPlanes8 = PlaneTable<8>();
+
+template <int R>
+__device__ __forceinline__ const uint16_t* plane_slots();
+template <>
+__device__ __forceinline__ const uint16_t* plane_slots<4>() { return kPlanes4.slot; }
+template <>
+__device__ __forceinline__ const uint16_t* plane_slots<8>() { return kPlanes8.slot; }
+
+// Gray-code order of the 8 sweep directions; bit a of a direction set = descending along axis a.
+__constant__ int kGray[8] = {0, 1, 3, 2, 6, 7, 5, 4};
+
+// Directions preferred by a cell whose face g received new inflow: sweep away from that face.
+__device__ __forceinline__ uint32_t pref_mask_for_face(int g) {
+    // g: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z
+    const uint32_t m[6] = {0x55u, 0xAAu, 0x33u, 0xCCu, 0x0Fu, 0xF0u};
+    return m[g];
+}
+
+// ------------------------------------------------------------------------------------------
+// Small helpers.
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t dbits(double d) { return (uint64_t)__double_as_longlong(d); }
+__device__ __forceinline__ double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
+
+__device__ __forceinline__ uint32_t ld_acquire_u32(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_relaxed_u64(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------------------------------------
+// Local solve of eq. (2): the smallest U with sum_k max(U - m_k, 0)^2 = s^2 given the upwind
+// axis values m_k (+inf when absent).  Sorted a <= b <= c, one, two or three terms are tried;
+// the discriminants are in difference form (no cancellation of O(U^2) quantities).  Each
+// branch is taken only when its guard holds, so +inf never meets +inf in a subtraction.
+
+__device__ __forceinline__ double local_solve(double m0, double m1, double m2, double s) {
+    const double t1 = fmin(m0, m1), t2 = fmax(m0, m1);
+    const double t3 = fmin(t2, m2), c = fmax(t2, m2);
+    const double a = fmin(t1, t3), b = fmax(t1, t3);
+    double u = a + s;
+    if (u > b) {
+        const double dab = a - b;
+        u = 0.5 * (a + b + sqrt(fma(2.0 * s, s, -dab * dab)));
+        if (u > c) {
+            const double dac = a - c, dbc = b - c;
+            double d3 = 3.0 * s * s - dab * dab - dac * dac - dbc * dbc;
+            d3 = fmax(d3, 0.0);
+            u = (a + b + c + sqrt(d3)) * (1.0 / 3.0);
+        }
+    }
+    return u;
+}
+
+// ------------------------------------------------------------------------------------------
+// Geometry.
+
+struct CellXYZ {
+    int x, y, z;
+};
+
+__device__ __forceinline__ CellXYZ cell_coords(const SolveParams& P, int c) {
+    CellXYZ r;
+    r.x = c % P.ncx;
+    r.y = (c / P.ncx) % P.ncy;
+    r.z = c / (P.ncx * P.ncy);
+    return r;
+}
+
+// Neighbour cell across face f (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z); -1 beyond the grid.
+__device__ __forceinline__ int cell_neighbour(const SolveParams& P, int c, CellXYZ cc, int f) {
+    switch (f) {
+        case 0: return cc.x > 0 ? c - 1 : -1;
+        case 1: return cc.x + 1 < P.ncx ? c + 1 : -1;
+        case 2: return cc.y > 0 ? c - P.ncx : -1;
+        case 3: return cc.y + 1 < P.ncy ? c + P.ncx : -1;
+        case 4: return cc.z > 0 ? c - P.ncx * P.ncy : -1;
+        default: return cc.z + 1 < P.ncz ? c + P.ncx * P.ncy : -1;
+    }
+}
+
+// Interior node of face f given in-plane coordinates (a, b): x-faces use (y, z), y-faces use
+// (x, z), z-faces use (x, y).
+template <int R>
+__device__ __forceinline__ void face_node(int f, int a, int b, int& x, int& y, int& z) {
+    const int side = (f & 1) ? R - 1 : 0;
+    switch (f >> 1) {
+        case 0: x = side; y = a; z = b; break;
+        case 1: x = a; y = side; z = b; break;
+        default: x = a; y = b; z = side; break;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Per-wave LDS of one cell visit.
+
+template <int R>
+struct WaveLds {
+    static constexpr int B = R + 2;
+    static constexpr int BOX = B * B * B;
+    double U[BOX];             // cell values with a one-node halo (edges/corners unused)
+    double S[R * R * R];       // s = h/F; -1 marks an exit node, 0 a padding node
+    uint8_t act[(BOX + 7) & ~7];  // active flags (halo slots are write-only scratch)
+    uint8_t chg[R * R * R];    // decreased during this visit
+};
+
+template <int R>
+__device__ __forceinline__ int box_index(int x, int y, int z) {
+    constexpr int B = R + 2;
+    return (x + 1) + B * ((y + 1) + B * (z + 1));
+}
+
+// ------------------------------------------------------------------------------------------
+// Tagging a neighbour cell for the next round (Algorithm 2 "for each c_k in DN", with Set Cell
+// Value = atomic min of the cell value and Add Cell = append to the next round's list unless
+// already queued).
+
+__device__ __forceinline__ void tag_cell(const SolveParams& P, RoundCtl* ctl_next, int nxt,
+                                         int nb, uint32_t bits, double value) {
+    const uint64_t kb = dbits(value);
+    atomicMin((unsigned long long*)&P.key[nxt][nb], (unsigned long long)kb);
+    const uint32_t old = atomicOr(&P.flags[nxt][nb], bits | FL_QUEUED);
+    if (!(old & FL_QUEUED)) {
+        const uint32_t i = atomicAdd(&ctl_next->count, 1u);
+        P.list[nxt][i] = nb;
+    }
+    atomicMin((unsigned long long*)&ctl_next->minkey, (unsigned long long)kb);
+}
+
+// ------------------------------------------------------------------------------------------
+// One visit of cell c by one wave: stage in, locking sweeps until no change, write back,
+// tag currently-downwind neighbours.  Returns counters through *cnt.
+
+struct VisitCounters {
+    unsigned long long sweeps, updates, requeued;
+};
+
+template <int R, typename FT>
+__device__ void visit_cell(const SolveParams& P, int c, uint32_t fl, double popped_key,
+                           WaveLds<R>& L, int lane, RoundCtl* ctl_next, int nxt,
+                           VisitCounters& cnt) {
+    constexpr int R2 = R * R, R3 = R * R * R, B = R + 2, NP = 3 * R - 2;
+    constexpr int PASSES = PlaneTable<R>::PASSES;
+    const double INF = __builtin_inf();
+    const CellXYZ cc = cell_coords(P, c);
+    const double* __restrict__ ug = P.u + (size_t)c * R3;
+    const FT* __restrict__ fg = reinterpret_cast<const FT*>(P.f) + (size_t)c * R3;
+
+    // Stage in: cell values, s = h/F, cleared flags.
+    for (int l = lane; l < R3; l += 64) {
+        const int x = l % R, y = (l / R) % R, z = l / R2;
+        L.U[box_index<R>(x, y, z)] = ug[l];
+        const FT fv = fg[l];
+        L.S[l] = fv > FT(0) ? P.h / (double)fv : (fv < FT(0) ? -1.0 : 0.0);
+        L.chg[l] = 0;
+    }
+    for (int b = lane; b < WaveLds<R>::BOX; b += 64) L.act[b] = 0;
+    // Halo: the neighbour's opposite face copy, +inf beyond the grid.
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int nb = cell_neighbour(P, c, cc, f);
+        const double* src = nb >= 0 ? P.faces + ((size_t)nb * 6 + (f ^ 1)) * R2 : nullptr;
+        for (int e = lane; e < R2; e += 64) {
+            const int a = e % R, bb = e / R;
+            int x, y, z;
+            face_node<R>(f, a, bb, x, y, z);
+            const int axis = f >> 1, dir = (f & 1) ? 1 : -1;
+            if (axis == 0) x += dir; else if (axis == 1) y += dir; else z += dir;
+            L.U[box_index<R>(x, y, z)] = src ? src[e] : INF;
+        }
+    }
+    wave_sync();
+    // Initial active set: all nodes on a first (seeded / re-queued) visit, otherwise the layer
+    // next to each face that received new inflow.
+    if (fl & FL_ALL) {
+        for (int l = lane; l < R3; l += 64) {
+            const int x = l % R, y = (l / R) % R, z = l / R2;
+            L.act[box_index<R>(x, y, z)] = 1;
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (!(fl & (1u << f))) continue;
+            for (int e = lane; e < R2; e += 64) {
+                int x, y, z;
+                face_node<R>(f, e % R, e / R, x, y, z);
+                L.act[box_index<R>(x, y, z)] = 1;
+            }
+        }
+    }
+    wave_sync();
+
+    // Sweeps: preferred directions first (Gray order), then the default Gray cycle.
+    const uint32_t pref = (fl >> FL_DIR_SHIFT) & 0xFFu;
+    const uint16_t* slots = plane_slots<R>();
+    int pi = 0, ci = 0;
+    bool visit_changed = false, requeue = false;
+    unsigned long long upd = 0;
+    int nsweeps = 0;
+    for (;;) {
+        int d = -1;
+        while (pi < 8) {
+            const int cand = kGray[pi++];
+            if (pref & (1u << cand)) { d = cand; break; }
+        }
+        if (d < 0) d = kGray[(ci++) & 7];
+        bool changed = false;
+        double maxdec = 0.0;
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int pass = 0; pass < PASSES; ++pass) {
+                const uint16_t raw = slots[(p * PASSES + pass) * 64 + lane];
+                const bool valid = raw != 0xFFFF;
+                const int e = valid ? raw : 0;  // unused slots decode to node (0,0,0), inactive
+                int x = e & 31, y = (e >> 5) & 31, z = (e >> 10) & 31;
+                if (d & 1) x = R - 1 - x;
+                if (d & 2) y = R - 1 - y;
+                if (d & 4) z = R - 1 - z;
+                const int b = box_index<R>(x, y, z);
+                const bool go = valid && L.act[b] != 0;
+                if (__any(go)) {
+                    if (go) {
+                        L.act[b] = 0;
+                        const int l = x + R * (y + R * z);
+                        const double s = L.S[l];
+                        if (s > 0.0) {
+                            const double xm = L.U[b - 1], xp = L.U[b + 1];
+                            const double ym = L.U[b - B], yp = L.U[b + B];
+                            const double zm = L.U[b - B * B], zp = L.U[b + B * B];
+                            const double old = L.U[b];
+                            const double g = local_solve(fmin(xm, xp), fmin(ym, yp), fmin(zm, zp), s);
+                            ++upd;
+                            if (g < old) {
+                                L.U[b] = g;
+                                L.chg[l] = 1;
+                                changed = true;
+                                maxdec = fmax(maxdec, old - g);
+                                if (xm > g) L.act[b - 1] = 1;
+                                if (xp > g) L.act[b + 1] = 1;
+                                if (ym > g) L.act[b - B] = 1;
+                                if (yp > g) L.act[b + B] = 1;
+                                if (zm > g) L.act[b - B * B] = 1;
+                                if (zp > g) L.act[b + B * B] = 1;
+                            }
+                        }
+                    }
+                }
+                wave_sync();
+            }
+        }
+        ++nsweeps;
+        const bool any_changed = __any(changed);
+        visit_changed |= any_changed;
+        if (!any_changed) break;
+        if (P.tol > 0.0 && wave_max(maxdec) <= P.tol) break;
+        if (nsweeps >= P.max_sweeps) { requeue = true; break; }
+    }
+    cnt.sweeps += (unsigned long long)nsweeps;
+    cnt.updates += wave_sum(upd);
+
+    // Write back the cell and the faces that changed; tag downwind neighbours (eq. (5) value:
+    // the smallest newly decreased border value below the neighbour's value across the face).
+    if (visit_changed) {
+        double* __restrict__ uw = P.u + (size_t)c * R3;
+        for (int l = lane; l < R3; l += 64) {
+            const int x = l % R, y = (l / R) % R, z = l / R2;
+            uw[l] = L.U[box_index<R>(x, y, z)];
+        }
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int nb = cell_neighbour(P, c, cc, f);
+            bool face_changed = false, inflow = false;
+            double cand = INF;
+            for (int e = lane; e < R2; e += 64) {
+                int x, y, z;
+                face_node<R>(f, e % R, e / R, x, y, z);
+                const int l = x + R * (y + R * z);
+                const int b = box_index<R>(x, y, z);
+                const double v = L.U[b];
+                const int axis = f >> 1, dir = (f & 1) ? 1 : -1;
+                const int hb = b + dir * (axis == 0 ? 1 : (axis == 1 ? B : B * B));
+                const bool ch = L.chg[l] != 0;
+                face_changed |= ch;
+                if (ch && v < L.U[hb]) { inflow = true; cand = fmin(cand, v); }
+            }
+            if (__any(face_changed)) {
+                double* fw = P.faces + ((size_t)c * 6 + f) * R2;
+                for (int e = lane; e < R2; e += 64) {
+                    int x, y, z;
+                    face_node<R>(f, e % R, e / R, x, y, z);
+                    fw[e] = L.U[box_index<R>(x, y, z)];
+                }
+            }
+            if (nb >= 0 && __any(inflow)) {
+                const double kv = wave_min(cand);
+                if (lane == 0) {
+                    const int g = f ^ 1;
+                    tag_cell(P, ctl_next, nxt, nb, (1u << g) | (pref_mask_for_face(g) << FL_DIR_SHIFT), kv);
+                }
+            }
+        }
+    }
+    if (requeue) {
+        if (lane == 0) tag_cell(P, ctl_next, nxt, c, FL_ALL, popped_key);
+        cnt.requeued += 1;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Grid barrier for the persistent cooperative launch.  All workgroups are co-resident (the
+// launch is cooperative), so every arrival is eventually followed by the last one.  A spin
+// that outlives the watchdog (a bounded number of polls) sets the status to EIK_ECANCELLED and
+// returns, so a broken invariant ends the kernel instead of hanging it.
+
+__device__ bool grid_barrier(const SolveParams& P) {
+    __syncthreads();
+    __shared__ int s_abort;
+    if (threadIdx.x == 0) {
+        s_abort = 0;
+        uint32_t* count = &P.bar[0];
+        uint32_t* gen = &P.bar[1];
+        const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const uint32_t arrived = atomicAdd(count, 1u);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            atomicAdd(gen, 1u);
+        } else {
+            uint64_t polls = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++polls > P.watchdog_polls) {
+                    atomicCAS(P.status, 0, EIK_ECANCELLED_DEV);
+                    s_abort = 1;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    return s_abort == 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// The solver.  Each wave is an independent worker; each workgroup holds `W` workers.  One
+// launch runs every round (persistent, grid barrier between rounds).
+
+template <int R, typename FT, int W>
+__global__ void __launch_bounds__(64 * W)
+k_solve(SolveParams P) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    WaveLds<R>& L = reinterpret_cast<WaveLds<R>*>(lds_raw)[wave];
+    VisitCounters cnt{0, 0, 0};
+    unsigned long long visits = 0, deferred = 0;
+    int rounds_done = 0;
+
+    for (int t = 0;; ++t) {
+        const int cur = t & 1, nxt = cur ^ 1;
+        RoundCtl* ctl_cur = &P.ctl[t & 3];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            RoundCtl* r2 = &P.ctl[(t + 2) & 3];
+            r2->count = 0;
+            r2->cursor = 0;
+            r2->minkey = dbits(__builtin_inf());
+        }
+        const uint32_t n = __hip_atomic_load(&ctl_cur->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double minkey = bitsd(ld_relaxed_u64(&ctl_cur->minkey));
+        const double thr = P.delta > 0.0 ? minkey + P.delta : __builtin_inf();
+        RoundCtl* ctl_next = &P.ctl[(t + 1) & 3];
+        for (;;) {
+            uint32_t i = 0;
+            if (lane == 0) i = atomicAdd(&ctl_cur->cursor, 1u);
+            i = __shfl(i, 0, 64);
+            if (i >= n) break;
+            uint32_t idx = i;
+            if (P.shuffle) {
+                const uint64_t mix = P.shuffle * 0x9E3779B97F4A7C15ull + (uint64_t)t * 0xBF58476D1CE4E5B9ull;
+                idx = (uint32_t)(((uint64_t)i * 2654435761ull + (mix >> 17)) % n);
+            }
+            const int c = P.list[cur][idx];
+            uint32_t fl = 0;
+            unsigned long long kb = 0;
+            if (lane == 0) {
+                fl = atomicExch(&P.flags[cur][c], 0u);
+                kb = atomicExch((unsigned long long*)&P.key[cur][c], (unsigned long long)dbits(__builtin_inf()));
+            }
+            fl = __shfl(fl, 0, 64);
+            kb = __shfl(kb, 0, 64);
+            const double key = bitsd(kb);
+            if (!(key < thr)) {
+                // Not in the lowest band: carry the cell, its flags and value to the next round.
+                if (lane == 0) tag_cell(P, ctl_next, nxt, c, fl & ~FL_QUEUED, key);
+                ++deferred;
+                continue;
+            }
+            ++visits;
+            visit_cell<R, FT>(P, c, fl, key, L, lane, ctl_next, nxt, cnt);
+        }
+        ++rounds_done;
+        if (!grid_barrier(P)) break;
+        const uint32_t nnext = __hip_atomic_load(&P.ctl[(t + 1) & 3].count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int st = __hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (nnext == 0 || st != 0) break;
+        if (t + 1 >= P.max_rounds) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(P.status, 0, EIK_ENOCONV_DEV);
+            break;
+        }
+    }
+    // Counters.
+    if (lane == 0) {
+        atomicAdd(&P.stats[ST_VISITS], visits);
+        atomicAdd(&P.stats[ST_SWEEPS], cnt.sweeps);
+        atomicAdd(&P.stats[ST_UPDATES], cnt.updates);
+        atomicAdd(&P.stats[ST_DEFERRED], deferred);
+        atomicAdd(&P.stats[ST_REQUEUED], cnt.requeued);
+        if (blockIdx.x == 0 && wave == 0) atomicAdd(&P.stats[ST_ROUNDS], (unsigned long long)rounds_done);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Stage inputs (a1): row-major F -> cell-blocked F with padding marked 0, u <- +inf, faces <- +inf.
+// Speeds that are not finite and positive set the status to EIK_EINVAL.
+
+template <int R, typename FT>
+__global__ void k_init_nodes(SolveParams P, const FT* __restrict__ F) {
+    constexpr int R3 = R * R * R;
+    const size_t total = (size_t)P.ncell * R3;
+    const double INF = __builtin_inf();
+    FT* fb = reinterpret_cast<FT*>(P.fw);
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < total;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(g / R3), l = (int)(g % R3);
+        const int x = l % R, y = (l / R) % R, z = l / (R * R);
+        const CellXYZ cc = cell_coords(P, c);
+        const int i = cc.x * R + x, j = cc.y * R + y, k = cc.z * R + z;
+        FT fv = FT(0);
+        if (i < P.nx && j < P.ny && k < P.nz) {
+            fv = F[(size_t)i + (size_t)P.nx * ((size_t)j + (size_t)P.ny * k)];
+            const double dv = (double)fv;
+            if (!(dv > 0.0) || !(dv <= 1.7976931348623157e308)) {
+                atomicCAS(P.status, 0, EIK_EINVAL_DEV);
+                fv = FT(1);
+            }
+        }
+        fb[g] = fv;
+        P.u[g] = INF;
+    }
+}
+
+template <int R>
+__global__ void k_init_cells(SolveParams P) {
+    constexpr int R2 = R * R;
+    const size_t nf = (size_t)P.ncell * 6 * R2;
+    const double INF = __builtin_inf();
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t g0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    for (size_t g = g0; g < nf; g += stride) P.faces[g] = INF;
+    for (size_t g = g0; g < (size_t)P.ncell; g += stride) {
+        P.key[0][g] = dbits(INF);
+        P.key[1][g] = dbits(INF);
+        P.flags[0][g] = 0;
+        P.flags[1][g] = 0;
+    }
+    if (g0 < 4) {
+        P.ctl[g0].count = 0;
+        P.ctl[g0].cursor = 0;
+        P.ctl[g0].minkey = dbits(INF);
+    }
+    if (g0 < 2) P.bar[g0] = 0;
+    if (g0 == 0) *P.status = 0;  // first kernel of the solve; later kernels may set it
+    if (g0 < ST_COUNT) P.stats[g0] = 0;
+}
+
+// Seed (a2): exit nodes fixed at q (min over duplicates), marked as exits in the blocked speed
+// array, copied into their cell's face layers; their cells and the cells of their six grid
+// neighbours are queued for round 0 with every node active and cell value q (the initial cell
+// values of Section 4).
+template <int R, typename FT>
+__global__ void k_seed(SolveParams P, int64_t nsrc, const int64_t* __restrict__ idx3,
+                       const double* __restrict__ q) {
+    constexpr int R2 = R * R, R3 = R * R * R;
+    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nsrc) return;
+    const int64_t i = idx3[3 * n], j = idx3[3 * n + 1], k = idx3[3 * n + 2];
+    const double qv = q[n] + 0.0;  // -0.0 -> +0.0 so that bit order is value order
+    if (i < 0 || i >= P.nx || j < 0 || j >= P.ny || k < 0 || k >= P.nz || !(qv >= 0.0) ||
+        !(qv <= 1.7976931348623157e308)) {
+        atomicCAS(P.status, 0, EIK_EINVAL_DEV);
+        return;
+    }
+    const int cx = (int)(i / R), cy = (int)(j / R), cz = (int)(k / R);
+    const int x = (int)(i % R), y = (int)(j % R), z = (int)(k % R);
+    const int c = cx + P.ncx * (cy + P.ncy * cz);
+    const int l = x + R * (y + R * z);
+    atomicMin((unsigned long long*)&P.u[(size_t)c * R3 + l], (unsigned long long)dbits(qv));
+    reinterpret_cast<FT*>(P.fw)[(size_t)c * R3 + l] = FT(-1);
+    // Face copies of the exit node.
+    const int fx[6] = {x == 0, x == R - 1, y == 0, y == R - 1, z == 0, z == R - 1};
+    for (int f = 0; f < 6; ++f) {
+        if (!fx[f]) continue;
+        const int a = (f >> 1) == 0 ? y : x;
+        const int b = (f >> 1) == 2 ? y : z;
+        atomicMin((unsigned long long*)&P.faces[((size_t)c * 6 + f) * R2 + a + R * b],
+                  (unsigned long long)dbits(qv));
+    }
+    // Round 0 uses control slot 0 and parity buffer 0.
+    tag_cell(P, &P.ctl[0], 0, c, FL_ALL, qv);
+    const int64_t nbr[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
+                               {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+    for (int t = 0; t < 6; ++t) {
+        const int64_t a = nbr[t][0], b = nbr[t][1], e = nbr[t][2];
+        if (a < 0 || a >= P.nx || b < 0 || b >= P.ny || e < 0 || e >= P.nz) continue;
+        const int nc = (int)(a / R) + P.ncx * ((int)(b / R) + P.ncy * (int)(e / R));
+        if (nc != c) tag_cell(P, &P.ctl[0], 0, nc, FL_ALL, qv);
+    }
+}
+
+// Output (a8): cell-blocked u -> row-major u_out.
+template <int R>
+__global__ void k_output(SolveParams P, double* __restrict__ out) {
+    constexpr int R3 = R * R * R;
+    const size_t total = (size_t)P.nx * P.ny * P.nz;
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < total;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(g % P.nx);
+        const int j = (int)((g / P.nx) % P.ny);
+        const int k = (int)(g / ((size_t)P.nx * P.ny));
+        const int c = i / R + P.ncx * (j / R + P.ncy * (k / R));
+        const int l = i % R + R * (j % R + R * (k % R));
+        out[g] = P.u[(size_t)c * R3 + l];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Host-side launchers.
+
+template <int R, int W>
+constexpr size_t solve_lds_bytes() { return sizeof(WaveLds<R>) * W; }
+
+template <int R, typename FT, int W>
+static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int workers, int* used) {
+    const size_t lds = solve_lds_bytes<R, W>();
+    auto kern = k_solve<R, FT, W>;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int ncu = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * W, lds);
+    if (e != hipSuccess) return e;
+    // The grid barrier needs every workgroup resident at once.  The occupancy query does not
+    // round LDS up to the allocation granularity, so bound it again with a 2 KiB granule.
+    int lds_cu = 0;
+    e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    if (e != hipSuccess) return e;
+    const size_t granule = 2048;
+    const size_t lds_alloc = (lds + 256 + granule - 1) / granule * granule;
+    const int per_cu_lds = (int)((size_t)lds_cu / lds_alloc);
+    if (per_cu_lds < per_cu) per_cu = per_cu_lds;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    int grid = per_cu * ncu;
+    if (workers > 0) grid = workers < grid ? workers : grid;
+    *used = grid;
+    if (std::getenv("EIK_DEBUG")) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            std::fprintf(stderr,
+                         "[eik] %s cu=%d lds/block=%zu lds/cu=%zu regs/cu=%d coop=%d | kernel R=%d "
+                         "W=%d lds=%zu per_cu=%d grid=%d\n",
+                         prop.gcnArchName, ncu, (size_t)prop.sharedMemPerBlock,
+                         (size_t)prop.maxSharedMemoryPerMultiProcessor, prop.regsPerMultiprocessor,
+                         prop.cooperativeLaunch, R, W, lds, per_cu, grid);
+    }
+    SolveParams Pc = P;
+    void* args[] = {&Pc};
+    return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(64 * W), args, lds, s);
+}
+
+template <int R, typename FT>
+static hipError_t launch_all_t(const SolveParams& P, const void* F, int64_t nsrc,
+                               const int64_t* idx3, const double* q, double* u_out,
+                               hipStream_t s, int workers, int* used) {
+    const int threads = 256;
+    const size_t nodes = (size_t)P.ncell * R * R * R;
+    int blocks = (int)((nodes + threads - 1) / threads);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((k_init_cells<R>), dim3(blocks), dim3(threads), 0, s, P);
+    hipLaunchKernelGGL((k_init_nodes<R, FT>), dim3(blocks), dim3(threads), 0, s, P,
+                       reinterpret_cast<const FT*>(F));
+    if (nsrc > 0) {
+        const int sb = (int)((nsrc + 63) / 64);
+        hipLaunchKernelGGL((k_seed<R, FT>), dim3(sb), dim3(64), 0, s, P, nsrc, idx3, q);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (nsrc > 0) {
+        e = launch_solve_t<R, FT, kWavesPerGroup>(P, s, workers, used);
+        if (e != hipSuccess) return e;
+    }
+    const size_t out_nodes = (size_t)P.nx * P.ny * P.nz;
+    int ob = (int)((out_nodes + threads - 1) / threads);
+    if (ob > 65536) ob = 65536;
+    hipLaunchKernelGGL((k_output<R>), dim3(ob), dim3(threads), 0, s, P, u_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveParams& P, int cell, int f_dtype, const void* F,
+                        int64_t nsrc, const int64_t* idx3, const double* q, double* u_out,
+                        hipStream_t s, int workers, int* used) {
+    if (cell == 8) {
+        return f_dtype == 1 ? launch_all_t<8, float>(P, F, nsrc, idx3, q, u_out, s, workers, used)
+                            : launch_all_t<8, double>(P, F, nsrc, idx3, q, u_out, s, workers, used);
+    }
+    if (cell == 4) {
+        return f_dtype == 1 ? launch_all_t<4, float>(P, F, nsrc, idx3, q, u_out, s, workers, used)
+                            : launch_all_t<4, double>(P, F, nsrc, idx3, q, u_out, s, workers, used);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace eik

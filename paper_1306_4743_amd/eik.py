@@ -1,0 +1,188 @@
+"""Python binding of libeik (include/eik.h): argument marshalling only.
+
+Every step of the solve runs in the HIP kernels of ``libeik.so``; this module converts torch
+device tensors and numpy source lists into the C ABI's plain pointers and sizes.  It never
+computes values itself and has no CPU fallback: if the library is missing it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeik.so")
+
+EIK_OK, EIK_EINVAL, EIK_ENOMEM, EIK_EHIP, EIK_ENOCONV, EIK_ECANCELLED = 0, -1, -2, -3, -4, -5
+EIK_F64, EIK_F32 = 0, 1
+EIK_MODE_FP64 = 0
+
+
+class EikError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}{strerror(code)} ({code})")
+
+
+class Sources(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("idx3", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("on_device", ctypes.c_int)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("delta", ctypes.c_double),
+                ("max_rounds", ctypes.c_int64), ("max_sweeps", ctypes.c_int),
+                ("workers", ctypes.c_int), ("shuffle", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("rounds", "visits", "sweeps", "updates", "deferred", "requeued", "cells",
+                 "status")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+_lib = None
+
+# Every symbol declared in include/eik.h.
+EXPORTS = ("eik_solve", "eik_solve_ex", "eik_query_workspace", "eik_stream_status",
+           "eik_strerror", "eik_release", "eik_version")
+
+
+def load():
+    """Load libeik.so (built in-tree by __graft_entry__.build()); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(the solver has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    lib.eik_solve.argtypes = [vp, dbl, vp, i32, ctypes.POINTER(Sources), vp, i32, dbl, vp]
+    lib.eik_solve.restype = i32
+    lib.eik_solve_ex.argtypes = [vp, dbl, vp, i32, ctypes.POINTER(Sources), vp, i32, dbl, vp,
+                                 ctypes.POINTER(Options)]
+    lib.eik_solve_ex.restype = i32
+    lib.eik_query_workspace.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.eik_query_workspace.restype = i32
+    lib.eik_stream_status.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.eik_stream_status.restype = i32
+    lib.eik_strerror.argtypes = [i32]
+    lib.eik_strerror.restype = ctypes.c_char_p
+    lib.eik_release.argtypes = []
+    lib.eik_release.restype = None
+    lib.eik_version.argtypes = []
+    lib.eik_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return load().eik_strerror(int(code)).decode()
+    except RuntimeError:
+        return f"code {code}"
+
+
+def version() -> str:
+    return load().eik_version().decode()
+
+
+def _dims_array(dims):
+    return (ctypes.c_int64 * 3)(*[int(d) for d in dims])
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def query_workspace(dims, cell: int = 8, f_dtype: int = EIK_F64, mode: int = EIK_MODE_FP64) -> int:
+    out = ctypes.c_size_t(0)
+    rc = load().eik_query_workspace(ctypes.cast(_dims_array(dims), ctypes.c_void_p), int(cell),
+                                    int(f_dtype), int(mode), ctypes.byref(out))
+    if rc != EIK_OK:
+        raise EikError(rc, "eik_query_workspace: ")
+    return int(out.value)
+
+
+class _HostSources:
+    """Keeps host copies alive for the duration of the (synchronous) staging in eik_solve."""
+
+    def __init__(self, idx3, q):
+        self.idx3 = np.ascontiguousarray(np.asarray(idx3, dtype=np.int64).reshape(-1, 3))
+        self.q = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
+        if self.q.shape[0] != self.idx3.shape[0]:
+            raise ValueError("one q value per source node")
+        self.struct = Sources(self.idx3.shape[0],
+                              self.idx3.ctypes.data if self.idx3.size else None,
+                              self.q.ctypes.data if self.q.size else None, 0)
+
+
+def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, stream=None,
+          delta: float = 0.0, max_rounds: int = 0, max_sweeps: int = 0, workers: int = 0,
+          shuffle: int = 0, check: bool = True):
+    """Enqueue one solve of eq. (2) on ``stream`` (torch stream; default: current stream).
+
+    F: torch CUDA tensor [nz, ny, nx] of float32 or float64 speeds (contiguous).
+    idx3, q: host arrays of exit nodes (i, j, k) and their values, or torch CUDA tensors
+    (int64 [n, 3] and float64 [n]).  Returns u_out (allocated if None), a float64 CUDA tensor
+    of F's shape.  The call returns after enqueueing; use ``status()`` to wait and read the
+    device-side status and counters.
+    """
+    import torch
+    lib = load()
+    if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dim() == 3 and F.is_contiguous()):
+        raise ValueError("F must be a contiguous 3-D CUDA tensor [nz, ny, nx]")
+    if F.dtype == torch.float32:
+        f_dtype = EIK_F32
+    elif F.dtype == torch.float64:
+        f_dtype = EIK_F64
+    else:
+        raise ValueError("F must be float32 or float64")
+    nz, ny, nx = F.shape
+    if u_out is None:
+        u_out = torch.empty(F.shape, dtype=torch.float64, device=F.device)
+    elif not (u_out.is_cuda and u_out.dtype == torch.float64 and u_out.shape == F.shape
+              and u_out.is_contiguous()):
+        raise ValueError("u_out must be a contiguous float64 CUDA tensor shaped like F")
+    keep = None
+    if isinstance(idx3, torch.Tensor) and idx3.is_cuda:
+        idx3_t = idx3.to(torch.int64).contiguous()
+        q_t = torch.as_tensor(q, dtype=torch.float64, device=F.device).contiguous()
+        src = Sources(idx3_t.shape[0], idx3_t.data_ptr(), q_t.data_ptr(), 1)
+        if stream is not None:
+            idx3_t.record_stream(stream)
+            q_t.record_stream(stream)
+        keep = (idx3_t, q_t)
+    else:
+        keep = _HostSources(idx3, q)
+        src = keep.struct
+    opts = Options(EIK_MODE_FP64, float(delta), int(max_rounds), int(max_sweeps), int(workers),
+                   int(shuffle))
+    dims = _dims_array((nx, ny, nz))
+    rc = lib.eik_solve_ex(ctypes.cast(dims, ctypes.c_void_p), float(h),
+                          ctypes.c_void_p(F.data_ptr()), f_dtype, ctypes.byref(src),
+                          ctypes.c_void_p(u_out.data_ptr()), int(cell), float(tol),
+                          _stream_handle(stream), ctypes.byref(opts))
+    del keep
+    if rc != EIK_OK and check:
+        raise EikError(rc, "eik_solve: ")
+    return u_out
+
+
+def status(stream=None):
+    """Wait for ``stream`` and return (status code, counters dict) of its last solve."""
+    st = Stats()
+    rc = load().eik_stream_status(_stream_handle(stream), ctypes.byref(st))
+    return rc, st.as_dict()
+
+
+def release():
+    load().eik_release()

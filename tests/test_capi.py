@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every symbol that
+include/eik.h declares, and rejects invalid arguments synchronously before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1306_4743_amd import eik
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "eik.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eik_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    assert _declared_symbols() == sorted(eik.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = eik.load()
+    for name in _declared_symbols():
+        assert hasattr(lib, name), name
+    out = os.popen(f"nm -D --defined-only {eik.LIB_PATH}").read()
+    for name in _declared_symbols():
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def test_strerror_and_version():
+    assert eik.strerror(0) == "EIK_OK"
+    for code in (-1, -2, -3, -4, -5):
+        assert eik.strerror(code).startswith("EIK_E")
+    assert "gfx950" in eik.version()
+
+
+def test_query_workspace_sizes():
+    b8 = eik.query_workspace((513, 513, 513), 8, eik.EIK_F32)
+    ncell = 65 ** 3
+    # values + FP32 speeds + six face layers, at least
+    assert b8 >= ncell * 512 * (8 + 4) + ncell * 384 * 8
+    assert b8 < ncell * 512 * 30
+    b4 = eik.query_workspace((65, 65, 65), 4, eik.EIK_F64)
+    assert b4 > 0
+    with pytest.raises(eik.EikError):
+        eik.query_workspace((65, 65, 65), 5, eik.EIK_F64)
+    with pytest.raises(eik.EikError):
+        eik.query_workspace((1, 65, 65), 8, eik.EIK_F64)
+
+
+def _call(dims, h=0.1, F=1, f_dtype=0, n=1, idx=None, q=None, u=1, cell=8, tol=0.0):
+    lib = eik.load()
+    idx = np.array([[0, 0, 0]] * max(n, 1), dtype=np.int64) if idx is None else idx
+    q = np.zeros(max(n, 1)) if q is None else q
+    src = eik.Sources(n, idx.ctypes.data, q.ctypes.data, 0)
+    d = (ctypes.c_int64 * 3)(*dims)
+    return lib.eik_solve(ctypes.cast(d, ctypes.c_void_p), h, ctypes.c_void_p(F), f_dtype,
+                         ctypes.byref(src), ctypes.c_void_p(u), cell, tol, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dims=(1, 8, 8)), dict(dims=(8, 8, 8), h=0.0), dict(dims=(8, 8, 8), h=float("nan")),
+    dict(dims=(8, 8, 8), F=0), dict(dims=(8, 8, 8), u=0), dict(dims=(8, 8, 8), f_dtype=7),
+    dict(dims=(8, 8, 8), cell=5), dict(dims=(8, 8, 8), cell=2), dict(dims=(8, 8, 8), tol=-1.0),
+    dict(dims=(8, 8, 8), n=-1),
+    dict(dims=(8, 8, 8), idx=np.array([[8, 0, 0]], dtype=np.int64)),
+    dict(dims=(8, 8, 8), idx=np.array([[0, -1, 0]], dtype=np.int64)),
+    dict(dims=(8, 8, 8), q=np.array([-1.0])), dict(dims=(8, 8, 8), q=np.array([np.inf])),
+    dict(dims=(8, 8, 8), q=np.array([np.nan])),
+    dict(dims=(2048, 2048, 1024)),
+])
+def test_invalid_arguments_rejected_synchronously(kw):
+    """Each of these is refused with EIK_EINVAL before any device work (F and u_out are fake
+    non-null pointers that are never dereferenced)."""
+    assert _call(**kw) == eik.EIK_EINVAL
+
+
+def test_stream_status_without_solve():
+    lib = eik.load()
+    st = eik.Stats()
+    # a stream handle that never had a solve: no workspace -> EIK_EINVAL, no device access
+    assert lib.eik_stream_status(ctypes.c_void_p(0x1234), ctypes.byref(st)) in (eik.EIK_EINVAL,
+                                                                                  eik.EIK_EHIP)

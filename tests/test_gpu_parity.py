@@ -1,0 +1,252 @@
+"""GPU parity: the HIP solver (through the C ABI) against the serial FP64 oracle.
+
+The discrete solution of eq. (2) is unique and the Heap-Cell Method reaches it whatever the
+cell size, heuristic or processing order (Section 4, "Assigning Cell Values"), so every
+configuration below is compared node by node with the oracle's FMM: identical +inf masks,
+exit nodes equal to q exactly, and max relative error <= 1e-10 elsewhere (the tolerance the
+FP64 path is held to).  At the largest size the full FMM is replaced by properties that hold
+at any size: eq. (2) itself at every node (the residual), exits and finiteness.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1306_4743_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1306_4743_amd import eik
+    eik.load()
+    return torch.device("cuda:0")
+
+
+def run_gpu(dev, p, cell=None, tol=None, **kw):
+    import torch
+    from paper_1306_4743_amd import eik
+    F = torch.from_numpy(np.ascontiguousarray(p.F)).to(dev)
+    u = eik.solve(F, p.h, p.src, p.q, cell=cell or p.cell, tol=p.tol if tol is None else tol, **kw)
+    rc, stats = eik.status()
+    return u.cpu().numpy(), rc, stats
+
+
+def compare(got, want, p, tol=REL_TOL):
+    assert got.shape == want.shape
+    assert np.array_equal(np.isinf(got), np.isinf(want)), "+inf masks differ"
+    assert not np.any(np.isnan(got))
+    s = p.src
+    if len(s):
+        exact = want[s[:, 2], s[:, 1], s[:, 0]]
+        assert np.array_equal(got[s[:, 2], s[:, 1], s[:, 0]], exact)
+    fin = np.isfinite(want) & (want > 0)
+    if not fin.any():
+        return 0.0
+    rel = np.abs(got[fin] - want[fin]) / want[fin]
+    worst = float(rel.max())
+    assert worst <= tol, f"max rel err {worst:.3e} at {np.argmax(rel)}"
+    return worst
+
+
+def check(orc, dev, p, **kw):
+    got, rc, stats = run_gpu(dev, p, **kw)
+    assert rc == 0, stats
+    want = orc.fmm(p.F, p.h, p.src, p.q)
+    err = compare(got, want, p)
+    print(f"{p.name} {kw}: max rel err {err:.2e}, stats {stats}", flush=True)
+    return got, stats
+
+
+@pytest.mark.parametrize("cell", [8, 4])
+def test_constant_small(orc, torch_dev, cell):
+    """Plain method, small: 65^3, F = 1, centre source, tol 1e-14."""
+    p = W.constant(65, cell=cell, tol=1e-14)
+    got, stats = check(orc, torch_dev, p)
+    c = 32
+    want_axis = np.abs(np.arange(-c, c + 1)) * p.h
+    assert np.array_equal(got[c, c, :], want_axis)
+    assert stats["visits"] >= stats["cells"] * 0.9
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("cell", [8, 4])
+def test_random_small(orc, torch_dev, seed, cell):
+    """Random speeds in [0.2, 2], several sources, odd sizes (ragged last cells)."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(9, 30))
+    nx = int(rng.integers(2, 40))
+    ny = int(rng.integers(2, 25))
+    p = W.random_small(n, seed, n_sources=int(rng.integers(1, 5)), nx=nx, ny=ny)
+    check(orc, torch_dev, p, cell=cell, tol=0.0)
+
+
+@pytest.mark.parametrize("cell", [8, 4])
+def test_oscillatory(orc, torch_dev, cell):
+    p = W.oscillatory(97, periods=4)
+    check(orc, torch_dev, p, cell=cell, tol=0.0)
+
+
+@pytest.mark.parametrize("delta", [0.0, 0.01, 0.05, 0.5])
+def test_maze_priority_bands(orc, torch_dev, delta):
+    """Barrier maze with 4 sources: every width of the priority band gives the same U."""
+    p = W.maze(97, seed=3)
+    check(orc, torch_dev, p, tol=0.0, delta=delta)
+
+
+@pytest.mark.parametrize("shuffle", [1, 2, 3])
+def test_processing_order_invariance(orc, torch_dev, shuffle):
+    """Pseudo-random pop orders (the GPU analogue of uneven processor speeds) and a single
+    worker all reach the oracle's solution."""
+    p = W.oscillatory(65, periods=4)
+    check(orc, torch_dev, p, tol=0.0, shuffle=shuffle)
+
+
+def test_single_worker(orc, torch_dev):
+    p = W.maze(49, seed=5, n_sources=2)
+    check(orc, torch_dev, p, tol=0.0, workers=1)
+
+
+def test_fp64_and_fp32_speeds(orc, torch_dev):
+    p64 = W.oscillatory(65, periods=2)
+    check(orc, torch_dev, p64, tol=0.0)
+    p32 = W.oscillatory(65, periods=2, dtype=np.float32)
+    check(orc, torch_dev, p32, tol=0.0)
+
+
+@pytest.mark.parametrize("case", ["corner", "faces", "tiny", "thin", "dupes", "plane"])
+def test_edge_cases(orc, torch_dev, case):
+    rng = np.random.default_rng(42)
+    if case == "corner":       # exits at grid corners
+        n = 33
+        src = np.array([[0, 0, 0], [n - 1, n - 1, n - 1]])
+        p = W.Problem("corner", rng.uniform(0.5, 2, (n, n, n)), 1 / (n - 1), src,
+                      np.array([0.0, 0.3]))
+    elif case == "faces":      # exits on cell faces, edges and corners (r = 8 boundaries)
+        n = 41
+        src = np.array([[8, 20, 20], [15, 16, 3], [16, 16, 16], [7, 8, 31], [39, 23, 24]])
+        p = W.Problem("faces", rng.uniform(0.5, 2, (n, n, n)), 1 / (n - 1), src,
+                      rng.uniform(0, 0.05, 5))
+    elif case == "tiny":       # smallest grid: 2 x 2 x 2
+        p = W.Problem("tiny", np.ones((2, 2, 2)), 0.5, np.array([[0, 0, 0]]), np.array([0.0]))
+    elif case == "thin":       # one-cell-thin slab, ragged in every axis
+        p = W.Problem("thin", rng.uniform(0.2, 2, (3, 70, 2)), 1 / 69, np.array([[1, 0, 2]]),
+                      np.array([0.0]))
+    elif case == "dupes":      # the same exit node listed twice keeps the smaller value
+        n = 20
+        p = W.Problem("dupes", np.ones((n, n, n)), 1 / 19, np.array([[5, 5, 5], [5, 5, 5]]),
+                      np.array([0.2, 0.1]))
+    else:                      # a whole plane of exits (1D reduction)
+        n = 24
+        src = np.array([[0, j, k] for k in range(n) for j in range(n)])
+        fx = 2.0 ** rng.integers(-2, 3, size=n)
+        F = np.broadcast_to(fx[None, None, :], (n, n, n)).copy()
+        p = W.Problem("plane", F, 1 / 32, src, np.zeros(len(src)))
+    for cell in (8, 4):
+        got, _ = check(orc, torch_dev, p, cell=cell, tol=0.0)
+    if case == "dupes":
+        assert got[5, 5, 5] == 0.1
+    if case == "plane":
+        want = np.concatenate([[0.0], np.cumsum(p.h / fx[1:])])
+        assert np.array_equal(got[3, 7, :], want)
+
+
+def test_no_sources_all_unreachable(torch_dev):
+    p = W.Problem("empty", np.ones((17, 17, 17)), 1 / 16, np.zeros((0, 3), np.int64), np.zeros(0))
+    got, rc, stats = run_gpu(torch_dev, p, cell=8, tol=0.0)
+    assert rc == 0 and np.all(np.isinf(got)) and stats["visits"] == 0
+
+
+def test_invalid_speed_reported_on_device(torch_dev):
+    from paper_1306_4743_amd import eik
+    p = W.constant(17)
+    p.F[3, 4, 5] = 0.0
+    _, rc, _ = run_gpu(torch_dev, p)
+    assert rc == eik.EIK_EINVAL
+    p.F[3, 4, 5] = np.nan
+    _, rc, _ = run_gpu(torch_dev, p)
+    assert rc == eik.EIK_EINVAL
+
+
+def test_round_cap_gives_upper_bound(orc, torch_dev):
+    """A cap on rounds ends the solve with EIK_ENOCONV; values only ever decrease from +inf,
+    so the partial result is an upper bound of the solution (Section 5.1 monotonicity)."""
+    from paper_1306_4743_amd import eik
+    p = W.oscillatory(49, periods=2)
+    got, rc, stats = run_gpu(torch_dev, p, tol=0.0, max_rounds=3)
+    assert rc == eik.EIK_ENOCONV and stats["rounds"] == 3
+    want = orc.fmm(p.F, p.h, p.src, p.q)
+    assert np.all(got >= want * (1 - 1e-12))
+    assert np.isinf(got).sum() > 0
+    # the same stream is reusable after a capped solve
+    got2, rc2, _ = run_gpu(torch_dev, p, tol=0.0)
+    assert rc2 == 0
+    compare(got2, want, p)
+
+
+def test_sweep_cap_requeues(orc, torch_dev):
+    """A cap of one sweep per visit forces every productive visit to re-queue its cell; the
+    answer is unchanged."""
+    p = W.oscillatory(49, periods=3)
+    _, stats = check(orc, torch_dev, p, tol=0.0, max_sweeps=1)
+    assert stats["requeued"] > 0
+
+
+def test_device_sources(orc, torch_dev):
+    import torch
+    from paper_1306_4743_amd import eik
+    p = W.maze(41, seed=9, n_sources=3)
+    F = torch.from_numpy(p.F).to(torch_dev)
+    u = eik.solve(F, p.h, torch.from_numpy(p.src).to(torch_dev),
+                  torch.from_numpy(p.q).to(torch_dev), cell=8)
+    rc, _ = eik.status()
+    assert rc == 0
+    compare(u.cpu().numpy(), orc.fmm(p.F, p.h, p.src, p.q), p)
+
+
+def test_concurrent_streams_match_alone(orc, torch_dev):
+    """Two solves on two streams at once give the same values as alone."""
+    import torch
+    from paper_1306_4743_amd import eik
+    pa, pb = W.oscillatory(57, periods=3), W.maze(65, seed=11)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    Fa = torch.from_numpy(pa.F).to(torch_dev)
+    Fb = torch.from_numpy(pb.F).to(torch_dev)
+    torch.cuda.synchronize()
+    ua = eik.solve(Fa, pa.h, pa.src, pa.q, cell=8, stream=sa)
+    ub = eik.solve(Fb, pb.h, pb.src, pb.q, cell=4, stream=sb)
+    assert eik.status(sa)[0] == 0 and eik.status(sb)[0] == 0
+    compare(ua.cpu().numpy(), orc.fmm(pa.F, pa.h, pa.src, pa.q), pa)
+    compare(ub.cpu().numpy(), orc.fmm(pb.F, pb.h, pb.src, pb.q), pb)
+
+
+def test_oscillatory_257_full(orc, torch_dev):
+    """Plain method, oscillatory speed at its full size (257^3, 4 periods), cells 4 and 8."""
+    p = W.oscillatory(257, periods=4)
+    want = orc.fmm(p.F, p.h, p.src, p.q)
+    for cell in (8, 4):
+        got, rc, stats = run_gpu(torch_dev, p, cell=cell, tol=0.0)
+        assert rc == 0
+        err = compare(got, want, p)
+        print(f"257^3 cell {cell}: max rel err {err:.2e} {stats}", flush=True)
+
+
+def test_maze_513_full_properties(orc, torch_dev):
+    """Barrier maze at its full size (513^3, 4 sources, r = 8) in the benchmark's launch
+    configuration: eq. (2) holds at every node to rounding (rho <= 1e-13), exits are exact,
+    every node is reached.  The discrete solution is unique, so a vanishing residual everywhere
+    pins the result."""
+    p = W.maze(513, seed=3)
+    got, rc, stats = run_gpu(torch_dev, p, cell=8, tol=0.0)
+    assert rc == 0
+    assert np.all(np.isfinite(got))
+    s = p.src
+    assert np.array_equal(got[s[:, 2], s[:, 1], s[:, 0]], p.q)
+    rho, nbad = orc.residual(p.F, p.h, p.src, p.q, got, 1e-13)
+    print(f"513^3 maze: residual {rho:.2e}, bad {nbad}, stats {stats}", flush=True)
+    assert nbad == 0 and rho <= 1e-13
