@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark: solved nodes/s of the cell-scheduled Eikonal solver on one MI355X.
+
+One step = one complete solve through the C ABI (stage the speeds into the cell-blocked layout,
+seed the exit nodes, run the persistent cell-sweep kernel until the worklist is empty, write the
+row-major result), with the speed field already resident in HBM.  The default workload is the
+513^3 barrier maze (4 exit nodes, cell side 8, FP64 arithmetic, tol 0).
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel (the persistent
+solve kernel, timed with HIP events on the stream it runs on) and the serial oracle timed on the
+host on a bounded sample of the same workload recipe.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-node updates/s and solved nodes/s at 1e-10 rel err; serving p50/p99"
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+FP64_VECTOR_PEAK_TF = 78.6   # MI355X FP64 vector, published
+
+
+def bytes_per_visit(cell: int, s_u: int = 8, s_f: int = 4) -> int:
+    """Algorithmic HBM bytes of one cell visit: read the cell and its one-node halo, read the
+    speeds, write the cell back: s_u (2 r^3 + 6 r^2) + s_F r^3."""
+    r3, r2 = cell ** 3, cell ** 2
+    return s_u * (2 * r3 + 6 * r2) + s_f * r3
+
+
+def measured_traffic(workload_name: str, cell: int):
+    """HBM bytes per launch of the solve kernel from the committed FETCH_SIZE / WRITE_SIZE
+    summary, scaled by the plain-copy calibration; None unless the summary was taken on the
+    kernel source as it is now (sha256 prefix match) and on this workload."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1306_4743_amd", "csrc", "eik_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", f"k_solve_{workload_name}_pmc*.md")):
+        for line in open(path):
+            if not line.startswith("machine-readable:"):
+                continue
+            kv = dict(item.split("=", 1) for item in line.split(":", 1)[1].split())
+            if kv.get("sha") != sha or cell != 8:
+                continue
+            return (float(kv["fetch_kib"]) * float(kv["fetch_scale"])
+                    + float(kv["write_kib"]) * float(kv["write_scale"])) * 1024.0
+    return None
+
+
+def workload(name: str):
+    from paper_1306_4743_amd import workloads as W
+    if name == "maze513":
+        return W.maze(513, seed=3)
+    if name == "osc257":
+        return W.oscillatory(257, periods=4)
+    if name == "const65":
+        return W.constant(65)
+    if name == "maze257":
+        return W.maze(257, seed=3)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(args, gpu_solve):
+    """The serial oracle (FMM) on a bounded sample: the same maze recipe at 257^3 (seed 3),
+    one full solve on one host core; the GPU solves the same sample for a parity spot check."""
+    import numpy as np
+    import oracle
+    from paper_1306_4743_amd import workloads as W
+    oracle.build(force=False)
+    p = W.maze(257, seed=3)
+    t0 = time.perf_counter()
+    want = oracle.fmm(p.F, p.h, p.src, p.q)
+    dt = time.perf_counter() - t0
+    got = gpu_solve(p)
+    fin = np.isfinite(want) & (want > 0)
+    rel = float(np.max(np.abs(got[fin] - want[fin]) / want[fin]))
+    same_inf = bool(np.array_equal(np.isinf(got), np.isinf(want)))
+    return {"value": p.nodes / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"serial FP64 FMM, one full solve of the barrier maze recipe at 257^3 "
+                      f"({p.nodes} nodes, seed 3, 4 sources), {dt:.2f} s on one host core "
+                      f"(FMM is serial)",
+            "seconds": dt, "gpu_max_rel_err_on_sample": rel, "inf_masks_equal": same_inf}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="maze513")
+    ap.add_argument("--cell", type=int, default=8)
+    ap.add_argument("--delta", type=float, default=0.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-reference-mib", type=int, default=0,
+                    help="only run plain device-to-device copies of this many MiB (calibrates "
+                         "the HBM byte counters of a profiler against a known size)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent solves shard across GPUs with no exchange; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1306_4743_amd import eik
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_reference_mib:
+        n = args.copy_reference_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(max(args.steps, 1)):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes_read": n * 8, "copy_reference_bytes_written": n * 8,
+                          "copies": max(args.steps, 1)}), flush=True)
+        return
+    eik.load()
+    p = workload(args.workload)
+    F = torch.from_numpy(p.F).to(dev)
+    u = torch.empty(F.shape, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def solve(timing=False):
+        eik.solve(F, p.h, p.src, p.q, cell=args.cell, tol=p.tol, u_out=u, delta=args.delta,
+                  timing=timing)
+
+    for _ in range(args.warmup):
+        solve()
+    rc, st = eik.status()
+    if rc != 0:
+        raise SystemExit(f"warmup solve failed: {eik.strerror(rc)}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solve(timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rc, st = eik.status()
+    if rc != 0:
+        raise SystemExit(f"timed solve failed: {eik.strerror(rc)}")
+    solve_ms, total_ms = eik.kernel_times(args.steps)
+
+    ms_per_step = 1000.0 * wall / args.steps
+    value = p.nodes * args.steps / wall
+    upd_per_s = st["updates"] / (ms_per_step / 1000.0)
+    kern_ms = float(np.mean(solve_ms))
+    s_f = 4 if p.F.dtype == np.float32 else 8
+    bpv = bytes_per_visit(args.cell, 8, s_f)
+    visits = st["visits"]
+    achieved = visits * bpv / (kern_ms / 1000.0) / 1e9
+    floor_bytes = st["cells"] * bpv
+    traffic = measured_traffic(args.workload, args.cell)
+    tot_cyc = sum(st[k] for k in ("cycles_pop", "cycles_stage", "cycles_sweep", "cycles_write",
+                                  "cycles_wait"))
+    phases = {k[7:]: round(st[k] / max(tot_cyc, 1), 4) for k in
+              ("cycles_pop", "cycles_stage", "cycles_sweep", "cycles_write", "cycles_wait")}
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solved nodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": p.meta["workload"], "grid": list(p.dims), "h": p.h,
+                   "cell": args.cell, "tol": p.tol, "sources": int(len(p.src)),
+                   "f_dtype": str(p.F.dtype), "delta": args.delta or "inf"},
+        "grid_node_updates_per_s": upd_per_s,
+        "visits_per_cell": visits / st["cells"],
+        "sweeps_per_visit": st["sweeps"] / max(visits, 1),
+        "updates_per_node": st["updates"] / p.nodes,
+        "rounds": st["rounds"],
+        "solve_kernel_ms": kern_ms,
+        "whole_call_ms": float(np.mean(total_ms)),
+        "worker_phase_fractions": phases,
+        "roofline": {"bound": "hbm", "kernel": "k_solve", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_visit": bpv, "visits_per_launch": visits,
+                     "frac_at_one_visit_per_cell": floor_bytes / (kern_ms / 1000.0) / 1e9
+                     / HBM_PEAK_GBS},
+    }
+    if not args.no_cpu_baseline:
+        def gpu_solve(q):
+            Fq = torch.from_numpy(q.F).to(dev)
+            uq = eik.solve(Fq, q.h, q.src, q.q, cell=args.cell, tol=0.0)
+            rcq, _ = eik.status()
+            if rcq != 0:
+                raise SystemExit(f"sample solve failed: {eik.strerror(rcq)}")
+            return uq.cpu().numpy()
+        line["cpu_baseline"] = cpu_baseline(args, gpu_solve)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -76,6 +76,8 @@ typedef struct eik_options {
     int workers;          /* persistent workgroups; 0 = as many as fit on the device         */
     uint64_t shuffle;     /* 0 = natural order; otherwise seed of a pseudo-random permutation
                              of the order in which queued cells are taken (order tests)     */
+    int timing;           /* 1: record HIP events around the solve kernel and the whole solve
+                             of every call on the stream (read with eik_kernel_times)       */
 } eik_options;
 
 /* Per-solve counters, filled by eik_stream_status(). */
@@ -88,6 +90,12 @@ typedef struct eik_stats {
     int64_t requeued;     /* visits that hit max_sweeps and re-queued their cell             */
     int64_t cells;        /* cells in the decomposition                                      */
     int64_t status;       /* same as the return value of eik_stream_status()                 */
+    int64_t workers;      /* persistent workers (wave64) that ran                            */
+    int64_t cycles_pop;   /* shader-clock cycles summed over workers: taking cells off the list */
+    int64_t cycles_stage; /*   loading cells, halos and speeds into LDS                       */
+    int64_t cycles_sweep; /*   in-cell sweeps                                                 */
+    int64_t cycles_write; /*   write-back and tagging of neighbour cells                      */
+    int64_t cycles_wait;  /*   publishing the next list and waiting at the round barrier      */
 } eik_stats;
 
 /*
@@ -126,6 +134,13 @@ int eik_query_workspace(const int64_t dims[3], int cell, int f_dtype, int mode, 
  * enqueued on it (EIK_OK, EIK_EINVAL, EIK_ENOCONV, EIK_ECANCELLED) and, if stats != NULL,
  * its counters.  Returns EIK_EINVAL if no solve was ever enqueued on the stream. */
 int eik_stream_status(hipStream_t stream, eik_stats* stats);
+
+/* Durations of the last n timed solves on `stream` (those enqueued with options.timing = 1),
+ * oldest first: solve_ms[i] = the persistent solve kernel alone, total_ms[i] = the whole call
+ * (staging, seeding, solve, output).  Either array may be NULL.  Waits for the stream.  At most
+ * the last 256 solves are kept.  Returns the number of entries written (0 if none), or a
+ * negative code. */
+int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_ms);
 
 /* Human-readable name of a status code (static storage). */
 const char* eik_strerror(int code);

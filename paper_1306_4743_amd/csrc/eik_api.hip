@@ -42,7 +42,7 @@ bool make_layout(const int64_t dims[3], int cell, int f_dtype, Layout* L) {
     const size_t r3 = (size_t)(r * r * r), r2 = (size_t)(r * r);
     const size_t fsz = f_dtype == EIK_F32 ? 4 : 8;
     size_t o = 0;
-    L->off_small = o; o = align_up(o + 4096);
+    L->off_small = o; o = align_up(o + eik::kSmallBytes);
     L->off_u = o; o = align_up(o + n * r3 * 8);
     L->off_f = o; o = align_up(o + n * r3 * fsz);
     L->off_faces = o; o = align_up(o + n * 6 * r2 * 8);
@@ -53,11 +53,10 @@ bool make_layout(const int64_t dims[3], int cell, int f_dtype, Layout* L) {
     return true;
 }
 
-// Offsets inside the small control area.
-constexpr size_t kSmallCtl = 0;       // 4 x RoundCtl (64 B)
-constexpr size_t kSmallBar = 256;     // 2 x uint32
-constexpr size_t kSmallStatus = 512;  // int
-constexpr size_t kSmallStats = 768;   // ST_COUNT x uint64
+using eik::kSmallBar;
+using eik::kSmallCtl;
+using eik::kSmallStats;
+using eik::kSmallStatus;
 
 struct Workspace {
     int device = -1;
@@ -71,6 +70,10 @@ struct Workspace {
     bool used = false;
     int64_t cells = 0;
     std::mutex mu;  // serialises enqueues that share this workspace
+    // ring of event quadruples for timed solves
+    static constexpr int kRing = 256;
+    std::vector<eik::LaunchEvents> ring;
+    int64_t timed = 0;  // timed solves enqueued so far
 };
 
 std::mutex g_mu;
@@ -258,8 +261,21 @@ int eik_solve_ex(const int64_t dims[3], double h, const void* F, int f_dtype,
     P.stats = (unsigned long long*)(base + L.off_small + kSmallStats);
 
     int used = 0;
-    hipError_t e = eik::launch_solve(P, cell, f_dtype, F, nsrc, idx_dev, q_dev, u_out, stream, opt.workers,
-                          &used);
+    const eik::LaunchEvents* evp = nullptr;
+    if (opt.timing) {
+        if (w->ring.empty()) {
+            w->ring.resize(Workspace::kRing);
+            for (auto& q4 : w->ring)
+                for (auto& ev : q4.ev) {
+                    hipError_t ee = hipEventCreate(&ev);
+                    if (ee != hipSuccess) return hip_fail(ee);
+                }
+        }
+        evp = &w->ring[w->timed % Workspace::kRing];
+        w->timed++;
+    }
+    hipError_t e = eik::launch_solve(P, cell, f_dtype, F, nsrc, idx_dev, q_dev, u_out, stream,
+                                     opt.workers, &used, evp);
     if (e != hipSuccess) return hip_fail(e);
     w->used = true;
     w->cells = L.ncell;
@@ -300,8 +316,44 @@ int eik_stream_status(hipStream_t stream, eik_stats* stats) {
         stats->requeued = (int64_t)st[eik::ST_REQUEUED];
         stats->cells = w->cells;
         stats->status = status;
+        stats->workers = (int64_t)st[eik::ST_WORKERS];
+        stats->cycles_pop = (int64_t)st[eik::ST_CYC_POP];
+        stats->cycles_stage = (int64_t)st[eik::ST_CYC_STAGE];
+        stats->cycles_sweep = (int64_t)st[eik::ST_CYC_SWEEP];
+        stats->cycles_write = (int64_t)st[eik::ST_CYC_WRITE];
+        stats->cycles_wait = (int64_t)st[eik::ST_CYC_WAIT];
     }
     return status;
+}
+
+int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_ms) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return EIK_EHIP;
+    if (n < 0) return EIK_EINVAL;
+    Workspace* w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_ws.find(std::make_pair(dev, stream));
+        if (it != g_ws.end()) w = it->second;
+    }
+    if (!w || w->timed == 0) return 0;
+    std::lock_guard<std::mutex> lk(w->mu);
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e);
+    int64_t have = std::min<int64_t>(w->timed, Workspace::kRing);
+    if (n > have) n = (int)have;
+    for (int i = 0; i < n; ++i) {
+        const int64_t k = w->timed - n + i;
+        const eik::LaunchEvents& q4 = w->ring[k % Workspace::kRing];
+        float a = 0.f, b = 0.f;
+        e = hipEventElapsedTime(&a, q4.ev[1], q4.ev[2]);
+        if (e != hipSuccess) return hip_fail(e);
+        e = hipEventElapsedTime(&b, q4.ev[0], q4.ev[3]);
+        if (e != hipSuccess) return hip_fail(e);
+        if (solve_ms) solve_ms[i] = a;
+        if (total_ms) total_ms[i] = b;
+    }
+    return n;
 }
 
 void eik_release(void) {
@@ -316,6 +368,9 @@ void eik_release(void) {
         if (w->base) (void)hipFree(w->base);
         if (w->src_dev) (void)hipFree(w->src_dev);
         if (w->src_host) (void)hipHostFree(w->src_host);
+        for (auto& q4 : w->ring)
+            for (auto& ev : q4.ev)
+                if (ev) (void)hipEventDestroy(ev);
         (void)hipSetDevice(cur);
         delete w;
     }

@@ -23,14 +23,32 @@ constexpr int EIK_ECANCELLED_DEV = EIK_ECANCELLED;
 constexpr int kWavesPerGroup = 4;
 
 // Counter slots.
-enum { ST_ROUNDS = 0, ST_VISITS, ST_SWEEPS, ST_UPDATES, ST_DEFERRED, ST_REQUEUED, ST_COUNT = 8 };
-
-// Per-round control block: list length, pop cursor, smallest cell value in the list.
-struct RoundCtl {
-    uint32_t count;
-    uint32_t cursor;
-    uint64_t minkey;
+enum {
+    ST_ROUNDS = 0, ST_VISITS, ST_SWEEPS, ST_UPDATES, ST_DEFERRED, ST_REQUEUED,
+    // shader-clock cycles summed over workers, by phase
+    ST_CYC_POP, ST_CYC_STAGE, ST_CYC_SWEEP, ST_CYC_WRITE, ST_CYC_WAIT, ST_WORKERS,
+    ST_COUNT = 16
 };
+
+// Per-round control block: pop cursor, list length and smallest cell value in the list, each
+// on its own cache line so that pops, appends and minimum updates do not contend.
+struct RoundCtl {
+    uint32_t cursor;
+    uint32_t pad0[31];
+    uint32_t count;
+    uint32_t pad1[15];
+    uint64_t minkey;
+    uint64_t pad2[7];
+};
+static_assert(sizeof(RoundCtl) == 256, "RoundCtl is 256 bytes");
+
+// Small control area of the workspace (byte offsets).
+constexpr size_t kSmallCtl = 0;        // 4 x RoundCtl
+constexpr size_t kSmallBar = 1024;     // barrier: arrivals at [0], generation at [64] (uint32)
+constexpr size_t kSmallStatus = 2048;  // int
+constexpr size_t kSmallStats = 2304;   // ST_COUNT x uint64
+constexpr size_t kSmallBytes = 4096;
+constexpr int kBarGen = 64;            // index of the generation word in the barrier array
 
 struct SolveParams {
     int nx, ny, nz;        // grid nodes per axis
@@ -49,13 +67,19 @@ struct SolveParams {
     uint32_t* flags[2];
     int32_t* list[2];
     RoundCtl* ctl;         // [4] control blocks, slot = round & 3
-    uint32_t* bar;         // [2] grid barrier: arrivals, generation
+    uint32_t* bar;         // grid barrier: bar[0] arrivals, bar[kBarGen] generation
     int* status;           // device status word
     unsigned long long* stats;  // [ST_COUNT]
 };
 
+// Optional events recorded around the solve kernel (ev[1], ev[2]) and the whole call
+// (ev[0], ev[3]); null entries are skipped.
+struct LaunchEvents {
+    hipEvent_t ev[4];
+};
+
 hipError_t launch_solve(const SolveParams& P, int cell, int f_dtype, const void* F, int64_t nsrc,
                         const int64_t* idx3, const double* q, double* u_out, hipStream_t s,
-                        int workers, int* used);
+                        int workers, int* used, const LaunchEvents* events);
 
 }  // namespace eik

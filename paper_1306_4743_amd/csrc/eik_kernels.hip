@@ -188,16 +188,17 @@ __device__ __forceinline__ void face_node(int f, int a, int b, int& x, int& y, i
 }
 
 // ------------------------------------------------------------------------------------------
-// Per-wave LDS of one cell visit.
+// Per-wave LDS of one cell visit.  The active flag of an interior node (Algorithm 3) is the
+// sign bit of its stored value: values are >= +0, so -|U| marks "active" without extra storage
+// and is read together with the value.  Every read of a value goes through fabs().
 
 template <int R>
 struct WaveLds {
     static constexpr int B = R + 2;
     static constexpr int BOX = B * B * B;
-    double U[BOX];             // cell values with a one-node halo (edges/corners unused)
-    double S[R * R * R];       // s = h/F; -1 marks an exit node, 0 a padding node
-    uint8_t act[(BOX + 7) & ~7];  // active flags (halo slots are write-only scratch)
-    uint8_t chg[R * R * R];    // decreased during this visit
+    double U[BOX];        // cell values with a one-node halo (edges/corners unused)
+    double S[R * R * R];  // s = h/F; -1 marks an exit node, 0 a padding node
+    int32_t q[64];        // cells newly queued for the next round, not yet published
 };
 
 template <int R>
@@ -206,11 +207,39 @@ __device__ __forceinline__ int box_index(int x, int y, int z) {
     return (x + 1) + B * ((y + 1) + B * (z + 1));
 }
 
+// Per-lane node coordinates of every diagonal plane, packed two planes per register, plus a
+// bit mask of the planes in which the lane has a node.  Loaded once per kernel.
+template <int R>
+struct PlaneRegs {
+    static constexpr int NP = 3 * R - 2;
+    uint32_t pk[(NP + 1) / 2];
+    uint32_t valid;
+};
+
+template <int R>
+__device__ __forceinline__ void load_plane_regs(PlaneRegs<R>& pr, int lane) {
+    static_assert(PlaneTable<R>::PASSES == 1, "one 64-lane pass per plane");
+    const uint16_t* slots = plane_slots<R>();
+    pr.valid = 0;
+#pragma unroll
+    for (int p = 0; p < PlaneRegs<R>::NP; ++p) {
+        const uint32_t raw = slots[p * 64 + lane];
+        const bool ok = raw != 0xFFFFu;
+        if (ok) pr.valid |= 1u << p;
+        const uint32_t e = ok ? raw : 0u;
+        if (p & 1) pr.pk[p >> 1] |= e << 16;
+        else pr.pk[p >> 1] = e;
+    }
+}
+
+__device__ __forceinline__ bool is_active(double v) { return __double_as_longlong(v) < 0; }
+
 // ------------------------------------------------------------------------------------------
 // Tagging a neighbour cell for the next round (Algorithm 2 "for each c_k in DN", with Set Cell
 // Value = atomic min of the cell value and Add Cell = append to the next round's list unless
 // already queued).
 
+// Single-thread form, used while seeding.
 __device__ __forceinline__ void tag_cell(const SolveParams& P, RoundCtl* ctl_next, int nxt,
                                          int nb, uint32_t bits, double value) {
     const uint64_t kb = dbits(value);
@@ -223,72 +252,143 @@ __device__ __forceinline__ void tag_cell(const SolveParams& P, RoundCtl* ctl_nex
     atomicMin((unsigned long long*)&ctl_next->minkey, (unsigned long long)kb);
 }
 
+// Wave-level publishing of newly queued cells: they collect in the wave's LDS buffer and are
+// appended to the next round's list with one atomic per flush.
+struct WaveQueue {
+    int n;          // entries in the LDS buffer (wave-uniform)
+    double minkey;  // per-lane smallest value tagged this round (used with a priority band)
+};
+
+template <int R>
+__device__ __forceinline__ void queue_flush(const SolveParams& P, int nxt, RoundCtl* ctl_next,
+                                            WaveLds<R>& L, int lane, WaveQueue& wq) {
+    if (wq.n == 0) return;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&ctl_next->count, (uint32_t)wq.n);
+    base = __shfl(base, 0, 64);
+    if (lane < wq.n) P.list[nxt][base + lane] = L.q[lane];
+    wq.n = 0;
+    wave_sync();
+}
+
+// Every lane with do_tag set tags one cell (any lanes, in parallel): cell value <- min(value),
+// flags |= bits | QUEUED, and the cell joins the next round's list unless already queued.
+template <int R>
+__device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCtl* ctl_next,
+                                          WaveLds<R>& L, int lane, WaveQueue& wq, bool do_tag,
+                                          int target, uint32_t bits, double value) {
+    bool newq = false;
+    if (do_tag) {
+        atomicMin((unsigned long long*)&P.key[nxt][target], (unsigned long long)dbits(value));
+        const uint32_t old = atomicOr(&P.flags[nxt][target], bits | FL_QUEUED);
+        newq = !(old & FL_QUEUED);
+        wq.minkey = fmin(wq.minkey, value);
+    }
+    const uint64_t mask = __ballot(newq);
+    const int k = __popcll(mask);
+    if (k == 0) return;
+    if (wq.n + k > 64) queue_flush<R>(P, nxt, ctl_next, L, lane, wq);
+    if (newq) {
+        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+        L.q[wq.n + rank] = target;
+    }
+    wq.n += k;
+    wave_sync();
+}
+
 // ------------------------------------------------------------------------------------------
 // One visit of cell c by one wave: stage in, locking sweeps until no change, write back,
-// tag currently-downwind neighbours.  Returns counters through *cnt.
+// tag currently-downwind neighbours.
 
 struct VisitCounters {
     unsigned long long sweeps, updates, requeued;
+    unsigned long long cyc_stage, cyc_sweep, cyc_write;
 };
 
+__device__ __forceinline__ unsigned long long cycles() { return __builtin_readcyclecounter(); }
+
+// Box offset of the halo node across face f from the border node.
+template <int R>
+__device__ __forceinline__ int face_step(int f) {
+    constexpr int B = R + 2;
+    const int axis = f >> 1, dir = (f & 1) ? 1 : -1;
+    return dir * (axis == 0 ? 1 : (axis == 1 ? B : B * B));
+}
+
 template <int R, typename FT>
-__device__ void visit_cell(const SolveParams& P, int c, uint32_t fl, double popped_key,
-                           WaveLds<R>& L, int lane, RoundCtl* ctl_next, int nxt,
-                           VisitCounters& cnt) {
+__device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t fl,
+                                           double popped_key, WaveLds<R>& L,
+                                           const PlaneRegs<R>& pr, int lane,
+                                           RoundCtl* ctl_next, int nxt, VisitCounters& cnt,
+                                           WaveQueue& wq) {
     constexpr int R2 = R * R, R3 = R * R * R, B = R + 2, NP = 3 * R - 2;
-    constexpr int PASSES = PlaneTable<R>::PASSES;
+    constexpr int BOFF = 1 + B + B * B;
     const double INF = __builtin_inf();
+    const unsigned long long t0 = cycles();
     const CellXYZ cc = cell_coords(P, c);
     const double* __restrict__ ug = P.u + (size_t)c * R3;
     const FT* __restrict__ fg = reinterpret_cast<const FT*>(P.f) + (size_t)c * R3;
 
-    // Stage in: cell values, s = h/F, cleared flags.
+    // Stage in: cell values and s = h/F.
     for (int l = lane; l < R3; l += 64) {
         const int x = l % R, y = (l / R) % R, z = l / R2;
         L.U[box_index<R>(x, y, z)] = ug[l];
         const FT fv = fg[l];
         L.S[l] = fv > FT(0) ? P.h / (double)fv : (fv < FT(0) ? -1.0 : 0.0);
-        L.chg[l] = 0;
     }
-    for (int b = lane; b < WaveLds<R>::BOX; b += 64) L.act[b] = 0;
     // Halo: the neighbour's opposite face copy, +inf beyond the grid.
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int nb = cell_neighbour(P, c, cc, f);
-        const double* src = nb >= 0 ? P.faces + ((size_t)nb * 6 + (f ^ 1)) * R2 : nullptr;
-        for (int e = lane; e < R2; e += 64) {
-            const int a = e % R, bb = e / R;
+        if (lane < R2) {
             int x, y, z;
-            face_node<R>(f, a, bb, x, y, z);
-            const int axis = f >> 1, dir = (f & 1) ? 1 : -1;
-            if (axis == 0) x += dir; else if (axis == 1) y += dir; else z += dir;
-            L.U[box_index<R>(x, y, z)] = src ? src[e] : INF;
+            face_node<R>(f, lane % R, lane / R, x, y, z);
+            const double v = nb >= 0 ? P.faces[((size_t)nb * 6 + (f ^ 1)) * R2 + lane] : INF;
+            L.U[box_index<R>(x, y, z) + face_step<R>(f)] = v;
         }
     }
     wave_sync();
-    // Initial active set: all nodes on a first (seeded / re-queued) visit, otherwise the layer
-    // next to each face that received new inflow.
+    // Border values before the visit (to detect which border nodes decrease), then the initial
+    // active set: every node on a first / re-queued visit, otherwise the layer next to each face
+    // that received new inflow.
+    double before[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        before[f] = INF;
+        if (lane < R2) {
+            int x, y, z;
+            face_node<R>(f, lane % R, lane / R, x, y, z);
+            before[f] = L.U[box_index<R>(x, y, z)];
+        }
+    }
+    wave_sync();
     if (fl & FL_ALL) {
         for (int l = lane; l < R3; l += 64) {
             const int x = l % R, y = (l / R) % R, z = l / R2;
-            L.act[box_index<R>(x, y, z)] = 1;
+            if (L.S[l] > 0.0) {
+                const int b = box_index<R>(x, y, z);
+                L.U[b] = -L.U[b];
+            }
         }
     } else {
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            if (!(fl & (1u << f))) continue;
-            for (int e = lane; e < R2; e += 64) {
+            if ((fl & (1u << f)) && lane < R2) {
                 int x, y, z;
-                face_node<R>(f, e % R, e / R, x, y, z);
-                L.act[box_index<R>(x, y, z)] = 1;
+                face_node<R>(f, lane % R, lane / R, x, y, z);
+                if (L.S[x + R * (y + R * z)] > 0.0) {
+                    const int b = box_index<R>(x, y, z);
+                    L.U[b] = -fabs(L.U[b]);
+                }
             }
         }
     }
     wave_sync();
 
-    // Sweeps: preferred directions first (Gray order), then the default Gray cycle.
+    const unsigned long long t1 = cycles();
+    // Sweeps: preferred directions first (Gray order), then the default Gray cycle.  A sweep in
+    // direction d visits the planes of the reflected coordinates x ^ mx etc. in increasing order.
     const uint32_t pref = (fl >> FL_DIR_SHIFT) & 0xFFu;
-    const uint16_t* slots = plane_slots<R>();
     int pi = 0, ci = 0;
     bool visit_changed = false, requeue = false;
     unsigned long long upd = 0;
@@ -300,49 +400,51 @@ __device__ void visit_cell(const SolveParams& P, int c, uint32_t fl, double popp
             if (pref & (1u << cand)) { d = cand; break; }
         }
         if (d < 0) d = kGray[(ci++) & 7];
+        const int mx = (d & 1) ? R - 1 : 0, my = (d & 2) ? R - 1 : 0, mz = (d & 4) ? R - 1 : 0;
         bool changed = false;
         double maxdec = 0.0;
-        for (int p = 0; p < NP; ++p) {
 #pragma unroll
-            for (int pass = 0; pass < PASSES; ++pass) {
-                const uint16_t raw = slots[(p * PASSES + pass) * 64 + lane];
-                const bool valid = raw != 0xFFFF;
-                const int e = valid ? raw : 0;  // unused slots decode to node (0,0,0), inactive
-                int x = e & 31, y = (e >> 5) & 31, z = (e >> 10) & 31;
-                if (d & 1) x = R - 1 - x;
-                if (d & 2) y = R - 1 - y;
-                if (d & 4) z = R - 1 - z;
-                const int b = box_index<R>(x, y, z);
-                const bool go = valid && L.act[b] != 0;
-                if (__any(go)) {
-                    if (go) {
-                        L.act[b] = 0;
-                        const int l = x + R * (y + R * z);
-                        const double s = L.S[l];
-                        if (s > 0.0) {
-                            const double xm = L.U[b - 1], xp = L.U[b + 1];
-                            const double ym = L.U[b - B], yp = L.U[b + B];
-                            const double zm = L.U[b - B * B], zp = L.U[b + B * B];
-                            const double old = L.U[b];
-                            const double g = local_solve(fmin(xm, xp), fmin(ym, yp), fmin(zm, zp), s);
-                            ++upd;
-                            if (g < old) {
-                                L.U[b] = g;
-                                L.chg[l] = 1;
-                                changed = true;
-                                maxdec = fmax(maxdec, old - g);
-                                if (xm > g) L.act[b - 1] = 1;
-                                if (xp > g) L.act[b + 1] = 1;
-                                if (ym > g) L.act[b - B] = 1;
-                                if (yp > g) L.act[b + B] = 1;
-                                if (zm > g) L.act[b - B * B] = 1;
-                                if (zp > g) L.act[b + B * B] = 1;
-                            }
-                        }
+        for (int p = 0; p < NP; ++p) {
+            uint32_t e = (pr.pk[p >> 1] >> ((p & 1) * 16)) & 0xFFFFu;
+            // Keep the decode inside the sweep loop: hoisting the 3 x NP decoded coordinates
+            // out of it costs more registers than the few ALU operations it saves.
+            asm volatile("" : "+v"(e));
+            const int x = (int)(e & 31u) ^ mx, y = (int)((e >> 5) & 31u) ^ my,
+                      z = (int)((e >> 10) & 31u) ^ mz;
+            const int b = x + B * (y + B * z) + BOFF;
+            const int l = x + R * (y + R * z);
+            double raw = L.U[b];
+            double s = L.S[l];
+            double xm = L.U[b - 1], xp = L.U[b + 1];
+            double ym = L.U[b - B], yp = L.U[b + B];
+            double zm = L.U[b - B * B], zp = L.U[b + B * B];
+            // Issue every LDS read of the step before the activity test: one LDS round trip.
+            asm volatile("" : "+v"(raw), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
+                         "+v"(zm), "+v"(zp));
+            const bool act = ((pr.valid >> p) & 1u) && is_active(raw);
+            if (__any(act)) {
+                if (act) {
+                    const double old = -raw;  // |raw|; writing it back clears the active flag
+                    xm = fabs(xm); xp = fabs(xp); ym = fabs(ym);
+                    yp = fabs(yp); zm = fabs(zm); zp = fabs(zp);
+                    const double g = local_solve(fmin(xm, xp), fmin(ym, yp), fmin(zm, zp), s);
+                    // exit nodes (s < 0) keep their value; padding nodes are never active
+                    const bool dec = s > 0.0 && g < old;
+                    upd += s > 0.0;
+                    L.U[b] = dec ? g : old;
+                    if (dec) {
+                        maxdec = fmax(maxdec, old - g);
+                        changed = true;
+                        if (xm > g) L.U[b - 1] = -xm;
+                        if (xp > g) L.U[b + 1] = -xp;
+                        if (ym > g) L.U[b - B] = -ym;
+                        if (yp > g) L.U[b + B] = -yp;
+                        if (zm > g) L.U[b - B * B] = -zm;
+                        if (zp > g) L.U[b + B * B] = -zp;
                     }
                 }
-                wave_sync();
             }
+            wave_sync();
         }
         ++nsweeps;
         const bool any_changed = __any(changed);
@@ -352,54 +454,63 @@ __device__ void visit_cell(const SolveParams& P, int c, uint32_t fl, double popp
         if (nsweeps >= P.max_sweeps) { requeue = true; break; }
     }
     cnt.sweeps += (unsigned long long)nsweeps;
-    cnt.updates += wave_sum(upd);
+    cnt.updates += upd;
+    const unsigned long long t2 = cycles();
 
     // Write back the cell and the faces that changed; tag downwind neighbours (eq. (5) value:
     // the smallest newly decreased border value below the neighbour's value across the face).
+    // Lane f (f < 6) tags the neighbour across face f; lane 6 re-queues the cell itself.
+    bool my_tag = false;
+    int my_target = 0;
+    uint32_t my_bits = 0;
+    double my_value = INF;
     if (visit_changed) {
         double* __restrict__ uw = P.u + (size_t)c * R3;
         for (int l = lane; l < R3; l += 64) {
             const int x = l % R, y = (l / R) % R, z = l / R2;
-            uw[l] = L.U[box_index<R>(x, y, z)];
+            uw[l] = fabs(L.U[box_index<R>(x, y, z)]);
         }
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
             const int nb = cell_neighbour(P, c, cc, f);
-            bool face_changed = false, inflow = false;
-            double cand = INF;
-            for (int e = lane; e < R2; e += 64) {
+            bool ch = false, inflow = false;
+            double v = INF;
+            if (lane < R2) {
                 int x, y, z;
-                face_node<R>(f, e % R, e / R, x, y, z);
-                const int l = x + R * (y + R * z);
+                face_node<R>(f, lane % R, lane / R, x, y, z);
                 const int b = box_index<R>(x, y, z);
-                const double v = L.U[b];
-                const int axis = f >> 1, dir = (f & 1) ? 1 : -1;
-                const int hb = b + dir * (axis == 0 ? 1 : (axis == 1 ? B : B * B));
-                const bool ch = L.chg[l] != 0;
-                face_changed |= ch;
-                if (ch && v < L.U[hb]) { inflow = true; cand = fmin(cand, v); }
+                v = fabs(L.U[b]);
+                ch = v < before[f];
+                inflow = ch && v < fabs(L.U[b + face_step<R>(f)]);
             }
-            if (__any(face_changed)) {
-                double* fw = P.faces + ((size_t)c * 6 + f) * R2;
-                for (int e = lane; e < R2; e += 64) {
-                    int x, y, z;
-                    face_node<R>(f, e % R, e / R, x, y, z);
-                    fw[e] = L.U[box_index<R>(x, y, z)];
-                }
-            }
+            if (__any(ch) && lane < R2)
+                P.faces[((size_t)c * 6 + f) * R2 + lane] = v;
             if (nb >= 0 && __any(inflow)) {
-                const double kv = wave_min(cand);
-                if (lane == 0) {
+                const double kv = wave_min(inflow ? v : INF);
+                if (lane == f) {
                     const int g = f ^ 1;
-                    tag_cell(P, ctl_next, nxt, nb, (1u << g) | (pref_mask_for_face(g) << FL_DIR_SHIFT), kv);
+                    my_tag = true;
+                    my_target = nb;
+                    my_bits = (1u << g) | (pref_mask_for_face(g) << FL_DIR_SHIFT);
+                    my_value = kv;
                 }
             }
         }
     }
     if (requeue) {
-        if (lane == 0) tag_cell(P, ctl_next, nxt, c, FL_ALL, popped_key);
+        if (lane == 6) {
+            my_tag = true;
+            my_target = c;
+            my_bits = FL_ALL;
+            my_value = popped_key;
+        }
         cnt.requeued += 1;
     }
+    tag_lanes<R>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits, my_value);
+    const unsigned long long t3 = cycles();
+    cnt.cyc_stage += t1 - t0;
+    cnt.cyc_sweep += t2 - t1;
+    cnt.cyc_write += t3 - t2;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -414,7 +525,7 @@ __device__ bool grid_barrier(const SolveParams& P) {
     if (threadIdx.x == 0) {
         s_abort = 0;
         uint32_t* count = &P.bar[0];
-        uint32_t* gen = &P.bar[1];
+        uint32_t* gen = &P.bar[kBarGen];
         const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         const uint32_t arrived = atomicAdd(count, 1u);
@@ -425,7 +536,7 @@ __device__ bool grid_barrier(const SolveParams& P) {
         } else {
             uint64_t polls = 0;
             while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(8);
                 if (++polls > P.watchdog_polls) {
                     atomicCAS(P.status, 0, EIK_ECANCELLED_DEV);
                     s_abort = 1;
@@ -444,18 +555,23 @@ __device__ bool grid_barrier(const SolveParams& P) {
 // launch runs every round (persistent, grid barrier between rounds).
 
 template <int R, typename FT, int W>
-__global__ void __launch_bounds__(64 * W)
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3)))
 k_solve(SolveParams P) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     WaveLds<R>& L = reinterpret_cast<WaveLds<R>*>(lds_raw)[wave];
-    VisitCounters cnt{0, 0, 0};
+    VisitCounters cnt{0, 0, 0, 0, 0, 0};
+    unsigned long long cyc_pop = 0, cyc_wait = 0;
+    PlaneRegs<R> pr;
+    load_plane_regs<R>(pr, lane);
     unsigned long long visits = 0, deferred = 0;
     int rounds_done = 0;
 
+    const int nwaves_total = (int)gridDim.x * W;
     for (int t = 0;; ++t) {
         const int cur = t & 1, nxt = cur ^ 1;
         RoundCtl* ctl_cur = &P.ctl[t & 3];
+        RoundCtl* ctl_next = &P.ctl[(t + 1) & 3];
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             RoundCtl* r2 = &P.ctl[(t + 2) & 3];
             r2->count = 0;
@@ -463,41 +579,64 @@ k_solve(SolveParams P) {
             r2->minkey = dbits(__builtin_inf());
         }
         const uint32_t n = __hip_atomic_load(&ctl_cur->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double minkey = bitsd(ld_relaxed_u64(&ctl_cur->minkey));
-        const double thr = P.delta > 0.0 ? minkey + P.delta : __builtin_inf();
-        RoundCtl* ctl_next = &P.ctl[(t + 1) & 3];
+        const double thr = P.delta > 0.0 ? bitsd(ld_relaxed_u64(&ctl_cur->minkey)) + P.delta
+                                         : __builtin_inf();
+        // Cells per pop: one when the list is short (balance), more when it is long (fewer
+        // atomics on the shared cursor).
+        const uint32_t chunk = n >= (uint32_t)nwaves_total * 32u ? 8u
+                             : (n >= (uint32_t)nwaves_total * 8u ? 4u
+                             : (n >= (uint32_t)nwaves_total * 2u ? 2u : 1u));
+        WaveQueue wq{0, __builtin_inf()};
         for (;;) {
-            uint32_t i = 0;
-            if (lane == 0) i = atomicAdd(&ctl_cur->cursor, 1u);
-            i = __shfl(i, 0, 64);
-            if (i >= n) break;
-            uint32_t idx = i;
-            if (P.shuffle) {
-                const uint64_t mix = P.shuffle * 0x9E3779B97F4A7C15ull + (uint64_t)t * 0xBF58476D1CE4E5B9ull;
-                idx = (uint32_t)(((uint64_t)i * 2654435761ull + (mix >> 17)) % n);
+            const unsigned long long tp0 = cycles();
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&ctl_cur->cursor, chunk);
+            base = __shfl(base, 0, 64);
+            if (base >= n) { cyc_pop += cycles() - tp0; break; }
+            const uint32_t cnt_here = n - base < chunk ? n - base : chunk;
+            // Lanes j < cnt_here take cell j of the chunk: its flags and value are exchanged
+            // for empty ones (the removal of Algorithm 2 with V^c <- +inf).
+            int my_c = 0;
+            uint32_t my_fl = 0;
+            unsigned long long my_kb = 0;
+            if ((uint32_t)lane < cnt_here) {
+                uint32_t idx = base + lane;
+                if (P.shuffle) {
+                    const uint64_t mix = P.shuffle * 0x9E3779B97F4A7C15ull + (uint64_t)t * 0xBF58476D1CE4E5B9ull;
+                    idx = (uint32_t)(((uint64_t)idx * 2654435761ull + (mix >> 17)) % n);
+                }
+                my_c = P.list[cur][idx];
+                my_fl = atomicExch(&P.flags[cur][my_c], 0u);
+                my_kb = atomicExch((unsigned long long*)&P.key[cur][my_c],
+                                   (unsigned long long)dbits(__builtin_inf()));
             }
-            const int c = P.list[cur][idx];
-            uint32_t fl = 0;
-            unsigned long long kb = 0;
-            if (lane == 0) {
-                fl = atomicExch(&P.flags[cur][c], 0u);
-                kb = atomicExch((unsigned long long*)&P.key[cur][c], (unsigned long long)dbits(__builtin_inf()));
+            // Cells outside the lowest band go straight back to the next round's list.
+            const bool defer = (uint32_t)lane < cnt_here && !(bitsd(my_kb) < thr);
+            deferred += __popcll(__ballot(defer));
+            tag_lanes<R>(P, nxt, ctl_next, L, lane, wq, defer, my_c, my_fl & ~FL_QUEUED,
+                         bitsd(my_kb));
+            cyc_pop += cycles() - tp0;
+            for (uint32_t j = 0; j < cnt_here; ++j) {
+                const int c = __shfl(my_c, (int)j, 64);
+                const uint32_t fl = __shfl(my_fl, (int)j, 64);
+                const double key = bitsd(__shfl(my_kb, (int)j, 64));
+                if (!(key < thr)) continue;
+                ++visits;
+                visit_cell<R, FT>(P, c, fl, key, L, pr, lane, ctl_next, nxt, cnt, wq);
             }
-            fl = __shfl(fl, 0, 64);
-            kb = __shfl(kb, 0, 64);
-            const double key = bitsd(kb);
-            if (!(key < thr)) {
-                // Not in the lowest band: carry the cell, its flags and value to the next round.
-                if (lane == 0) tag_cell(P, ctl_next, nxt, c, fl & ~FL_QUEUED, key);
-                ++deferred;
-                continue;
-            }
-            ++visits;
-            visit_cell<R, FT>(P, c, fl, key, L, lane, ctl_next, nxt, cnt);
+        }
+        const unsigned long long tw0 = cycles();
+        queue_flush<R>(P, nxt, ctl_next, L, lane, wq);
+        if (P.delta > 0.0) {
+            const double mk = wave_min(wq.minkey);
+            if (lane == 0 && mk < __builtin_inf())
+                atomicMin((unsigned long long*)&ctl_next->minkey, (unsigned long long)dbits(mk));
         }
         ++rounds_done;
-        if (!grid_barrier(P)) break;
-        const uint32_t nnext = __hip_atomic_load(&P.ctl[(t + 1) & 3].count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool ok = grid_barrier(P);
+        cyc_wait += cycles() - tw0;
+        if (!ok) break;
+        const uint32_t nnext = __hip_atomic_load(&ctl_next->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int st = __hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (nnext == 0 || st != 0) break;
         if (t + 1 >= P.max_rounds) {
@@ -506,12 +645,19 @@ k_solve(SolveParams P) {
         }
     }
     // Counters.
+    cnt.updates = wave_sum(cnt.updates);
     if (lane == 0) {
         atomicAdd(&P.stats[ST_VISITS], visits);
         atomicAdd(&P.stats[ST_SWEEPS], cnt.sweeps);
         atomicAdd(&P.stats[ST_UPDATES], cnt.updates);
         atomicAdd(&P.stats[ST_DEFERRED], deferred);
         atomicAdd(&P.stats[ST_REQUEUED], cnt.requeued);
+        atomicAdd(&P.stats[ST_CYC_POP], cyc_pop);
+        atomicAdd(&P.stats[ST_CYC_STAGE], cnt.cyc_stage);
+        atomicAdd(&P.stats[ST_CYC_SWEEP], cnt.cyc_sweep);
+        atomicAdd(&P.stats[ST_CYC_WRITE], cnt.cyc_write);
+        atomicAdd(&P.stats[ST_CYC_WAIT], cyc_wait);
+        atomicAdd(&P.stats[ST_WORKERS], 1ull);
         if (blockIdx.x == 0 && wave == 0) atomicAdd(&P.stats[ST_ROUNDS], (unsigned long long)rounds_done);
     }
 }
@@ -542,7 +688,9 @@ __global__ void k_init_nodes(SolveParams P, const FT* __restrict__ F) {
             }
         }
         fb[g] = fv;
-        P.u[g] = INF;
+        // Padding nodes hold NaN: fmin() ignores them (like +inf beyond the grid) and every
+        // comparison with them is false, so they are never activated or used as inflow.
+        P.u[g] = fv == FT(0) ? __builtin_nan("") : INF;
     }
 }
 
@@ -565,7 +713,7 @@ __global__ void k_init_cells(SolveParams P) {
         P.ctl[g0].cursor = 0;
         P.ctl[g0].minkey = dbits(INF);
     }
-    if (g0 < 2) P.bar[g0] = 0;
+    if (g0 < 2) P.bar[g0 * kBarGen] = 0;
     if (g0 == 0) *P.status = 0;  // first kernel of the solve; later kernels may set it
     if (g0 < ST_COUNT) P.stats[g0] = 0;
 }
@@ -680,11 +828,13 @@ static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int worker
 template <int R, typename FT>
 static hipError_t launch_all_t(const SolveParams& P, const void* F, int64_t nsrc,
                                const int64_t* idx3, const double* q, double* u_out,
-                               hipStream_t s, int workers, int* used) {
+                               hipStream_t s, int workers, int* used, const LaunchEvents* ev) {
     const int threads = 256;
     const size_t nodes = (size_t)P.ncell * R * R * R;
     int blocks = (int)((nodes + threads - 1) / threads);
     if (blocks > 65536) blocks = 65536;
+    hipError_t e;
+    if (ev && ev->ev[0] && (e = hipEventRecord(ev->ev[0], s)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_init_cells<R>), dim3(blocks), dim3(threads), 0, s, P);
     hipLaunchKernelGGL((k_init_nodes<R, FT>), dim3(blocks), dim3(threads), 0, s, P,
                        reinterpret_cast<const FT*>(F));
@@ -692,29 +842,34 @@ static hipError_t launch_all_t(const SolveParams& P, const void* F, int64_t nsrc
         const int sb = (int)((nsrc + 63) / 64);
         hipLaunchKernelGGL((k_seed<R, FT>), dim3(sb), dim3(64), 0, s, P, nsrc, idx3, q);
     }
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (ev && ev->ev[1] && (e = hipEventRecord(ev->ev[1], s)) != hipSuccess) return e;
     if (nsrc > 0) {
         e = launch_solve_t<R, FT, kWavesPerGroup>(P, s, workers, used);
         if (e != hipSuccess) return e;
     }
+    if (ev && ev->ev[2] && (e = hipEventRecord(ev->ev[2], s)) != hipSuccess) return e;
     const size_t out_nodes = (size_t)P.nx * P.ny * P.nz;
     int ob = (int)((out_nodes + threads - 1) / threads);
     if (ob > 65536) ob = 65536;
     hipLaunchKernelGGL((k_output<R>), dim3(ob), dim3(threads), 0, s, P, u_out);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev && ev->ev[3] && (e = hipEventRecord(ev->ev[3], s)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 hipError_t launch_solve(const SolveParams& P, int cell, int f_dtype, const void* F,
                         int64_t nsrc, const int64_t* idx3, const double* q, double* u_out,
-                        hipStream_t s, int workers, int* used) {
+                        hipStream_t s, int workers, int* used, const LaunchEvents* ev) {
     if (cell == 8) {
-        return f_dtype == 1 ? launch_all_t<8, float>(P, F, nsrc, idx3, q, u_out, s, workers, used)
-                            : launch_all_t<8, double>(P, F, nsrc, idx3, q, u_out, s, workers, used);
+        return f_dtype == 1 ? launch_all_t<8, float>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev)
+                            : launch_all_t<8, double>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev);
     }
     if (cell == 4) {
-        return f_dtype == 1 ? launch_all_t<4, float>(P, F, nsrc, idx3, q, u_out, s, workers, used)
-                            : launch_all_t<4, double>(P, F, nsrc, idx3, q, u_out, s, workers, used);
+        return f_dtype == 1 ? launch_all_t<4, float>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev)
+                            : launch_all_t<4, double>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev);
     }
     return hipErrorInvalidValue;
 }

@@ -33,13 +33,14 @@ class Sources(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("delta", ctypes.c_double),
                 ("max_rounds", ctypes.c_int64), ("max_sweeps", ctypes.c_int),
-                ("workers", ctypes.c_int), ("shuffle", ctypes.c_uint64)]
+                ("workers", ctypes.c_int), ("shuffle", ctypes.c_uint64), ("timing", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("rounds", "visits", "sweeps", "updates", "deferred", "requeued", "cells",
-                 "status")]
+                 "status", "workers", "cycles_pop", "cycles_stage", "cycles_sweep",
+                 "cycles_write", "cycles_wait")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -49,7 +50,7 @@ _lib = None
 
 # Every symbol declared in include/eik.h.
 EXPORTS = ("eik_solve", "eik_solve_ex", "eik_query_workspace", "eik_stream_status",
-           "eik_strerror", "eik_release", "eik_version")
+           "eik_kernel_times", "eik_strerror", "eik_release", "eik_version")
 
 
 def load():
@@ -71,6 +72,8 @@ def load():
     lib.eik_query_workspace.restype = i32
     lib.eik_stream_status.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.eik_stream_status.restype = i32
+    lib.eik_kernel_times.argtypes = [vp, i32, vp, vp]
+    lib.eik_kernel_times.restype = i32
     lib.eik_strerror.argtypes = [i32]
     lib.eik_strerror.restype = ctypes.c_char_p
     lib.eik_release.argtypes = []
@@ -127,7 +130,7 @@ class _HostSources:
 
 def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, stream=None,
           delta: float = 0.0, max_rounds: int = 0, max_sweeps: int = 0, workers: int = 0,
-          shuffle: int = 0, check: bool = True):
+          shuffle: int = 0, timing: bool = False, check: bool = True):
     """Enqueue one solve of eq. (2) on ``stream`` (torch stream; default: current stream).
 
     F: torch CUDA tensor [nz, ny, nx] of float32 or float64 speeds (contiguous).
@@ -165,7 +168,7 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
         keep = _HostSources(idx3, q)
         src = keep.struct
     opts = Options(EIK_MODE_FP64, float(delta), int(max_rounds), int(max_sweeps), int(workers),
-                   int(shuffle))
+                   int(shuffle), int(bool(timing)))
     dims = _dims_array((nx, ny, nz))
     rc = lib.eik_solve_ex(ctypes.cast(dims, ctypes.c_void_p), float(h),
                           ctypes.c_void_p(F.data_ptr()), f_dtype, ctypes.byref(src),
@@ -182,6 +185,16 @@ def status(stream=None):
     st = Stats()
     rc = load().eik_stream_status(_stream_handle(stream), ctypes.byref(st))
     return rc, st.as_dict()
+
+
+def kernel_times(n: int, stream=None):
+    """(solve_kernel_ms, whole_call_ms) arrays of the last n solves enqueued with timing=True."""
+    a = np.zeros(max(n, 0), dtype=np.float64)
+    b = np.zeros(max(n, 0), dtype=np.float64)
+    got = load().eik_kernel_times(_stream_handle(stream), int(n), a.ctypes.data, b.ctypes.data)
+    if got < 0:
+        raise EikError(got, "eik_kernel_times: ")
+    return a[:got], b[:got]
 
 
 def release():
