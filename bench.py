@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--workload", default="maze513")
     ap.add_argument("--cell", type=int, default=8)
     ap.add_argument("--delta", type=float, default=0.0)
+    ap.add_argument("--inner", type=int, default=0,
+                    help="in-cell solver: 0 default, 1 sweeps, 2 active-list, 3 dual sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-reference-mib", type=int, default=0,
                     help="only run plain device-to-device copies of this many MiB (calibrates "
@@ -132,7 +134,7 @@ def main():
 
     def solve(timing=False):
         eik.solve(F, p.h, p.src, p.q, cell=args.cell, tol=p.tol, u_out=u, delta=args.delta,
-                  timing=timing)
+                  timing=timing, inner=args.inner)
 
     for _ in range(args.warmup):
         solve()
@@ -180,7 +182,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": p.meta["workload"], "grid": list(p.dims), "h": p.h,
                    "cell": args.cell, "tol": p.tol, "sources": int(len(p.src)),
-                   "f_dtype": str(p.F.dtype), "delta": args.delta or "inf"},
+                   "f_dtype": str(p.F.dtype), "delta": args.delta or "inf",
+                   "inner": args.inner or "default"},
         "grid_node_updates_per_s": upd_per_s,
         "visits_per_cell": visits / st["cells"],
         "sweeps_per_visit": st["sweeps"] / max(visits, 1),

@@ -55,6 +55,18 @@ extern "C" {
 /* Arithmetic modes (eik_options.mode). */
 #define EIK_MODE_FP64 0  /* all storage and arithmetic in FP64                            */
 
+/* In-cell solvers (eik_options.inner).  All solve the cell sub-problem of Section 4 exactly:
+ *   EIK_INNER_SWEEP  locking sweeps (Algorithm 3) in the 8 directions, each sweep visiting the
+ *                    diagonal planes x'+y'+z' = p of the cell in order (one plane per wave step);
+ *   EIK_INNER_LIST   relaxation over a compacted list of active nodes: every pass evaluates the
+ *                    listed nodes in dense 64-lane chunks and a node that decreases lists its
+ *                    larger neighbours (Algorithm 3 activation without an ordering of nodes);
+ *   EIK_INNER_DUAL   the locking sweeps run as two streams on the cell at once, half a sweep
+ *                    apart, with directions that never put one node in both streams' planes. */
+#define EIK_INNER_SWEEP 1
+#define EIK_INNER_LIST 2
+#define EIK_INNER_DUAL 3
+
 /* Exit set Q' and its values q (Section 4 notation: Q' = X intersect Q, values prescribed). */
 typedef struct eik_sources {
     int64_t n;            /* number of exit nodes, >= 0 (0: every value is +inf)            */
@@ -78,6 +90,12 @@ typedef struct eik_options {
                              of the order in which queued cells are taken (order tests)     */
     int timing;           /* 1: record HIP events around the solve kernel and the whole solve
                              of every call on the stream (read with eik_kernel_times)       */
+    int64_t* round_log;   /* NULL, or a device array of 2 * round_log_len int64: for round t
+                             < round_log_len, [2t] = cells in the round's list and [2t+1] =
+                             shader-clock cycle count when the round ended (analysis)       */
+    int64_t round_log_len;
+    int inner;            /* in-cell solver: 0 = default (EIK_INNER_SWEEP at cell 8,
+                             EIK_INNER_LIST at cell 4), or one of EIK_INNER_*                */
 } eik_options;
 
 /* Per-solve counters, filled by eik_stream_status(). */

@@ -79,6 +79,26 @@ struct Workspace {
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
+// Per device: the event recorded after the most recently enqueued persistent solve kernel.
+// Each new solve kernel waits for it, so solve kernels of different streams run one at a time
+// (each needs the whole device resident for its grid barrier); the other kernels still overlap.
+struct DeviceOrder {
+    std::mutex mu;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int next = 0;
+    bool any = false;
+};
+std::map<int, DeviceOrder*> g_order;
+
+DeviceOrder* device_order(int dev) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_order.find(dev);
+    if (it != g_order.end()) return it->second;
+    DeviceOrder* d = new DeviceOrder();
+    g_order[dev] = d;
+    return d;
+}
+
 int hip_fail(hipError_t e) {
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return EIK_ENOMEM;
     return EIK_EHIP;
@@ -178,6 +198,8 @@ int eik_solve_ex(const int64_t dims[3], double h, const void* F, int f_dtype,
     if (opt.mode != EIK_MODE_FP64) return EIK_EINVAL;
     if (std::isnan(opt.delta) || opt.max_rounds < 0 || opt.max_sweeps < 0 || opt.workers < 0)
         return EIK_EINVAL;
+    if (opt.round_log_len < 0 || (opt.round_log_len > 0 && !opt.round_log)) return EIK_EINVAL;
+    if (opt.inner < 0 || opt.inner > EIK_INNER_DUAL) return EIK_EINVAL;
     const int64_t nsrc = sources->n;
     if (nsrc < 0 || (nsrc > 0 && (!sources->idx3 || !sources->q))) return EIK_EINVAL;
     if (nsrc > (int64_t(1) << 24)) return EIK_EINVAL;
@@ -240,6 +262,9 @@ int eik_solve_ex(const int64_t dims[3], double h, const void* F, int f_dtype,
     P.ncell = (int)L.ncell;
     P.max_rounds = opt.max_rounds > 0 ? (int)std::min<int64_t>(opt.max_rounds, 1 << 30) : (1 << 20);
     P.max_sweeps = opt.max_sweeps > 0 ? opt.max_sweeps : 512;
+    // default in-cell solver: sweeps at r = 8, the list relaxation at r = 4 (measured fastest)
+    const int inner = opt.inner ? opt.inner : (cell == 8 ? EIK_INNER_SWEEP : EIK_INNER_LIST);
+    P.inner = inner == EIK_INNER_SWEEP ? 0 : (inner == EIK_INNER_LIST ? 1 : 2);
     P.h = h;
     P.tol = tol;
     P.delta = opt.delta > 0.0 ? opt.delta : 0.0;
@@ -259,6 +284,8 @@ int eik_solve_ex(const int64_t dims[3], double h, const void* F, int f_dtype,
     P.bar = (uint32_t*)(base + L.off_small + kSmallBar);
     P.status = (int*)(base + L.off_small + kSmallStatus);
     P.stats = (unsigned long long*)(base + L.off_small + kSmallStats);
+    P.round_log = opt.round_log;
+    P.round_log_len = opt.round_log ? opt.round_log_len : 0;
 
     int used = 0;
     const eik::LaunchEvents* evp = nullptr;
@@ -274,8 +301,24 @@ int eik_solve_ex(const int64_t dims[3], double h, const void* F, int f_dtype,
         evp = &w->ring[w->timed % Workspace::kRing];
         w->timed++;
     }
+    DeviceOrder* dord = device_order(w->device);
+    std::lock_guard<std::mutex> olk(dord->mu);
+    for (auto& ev : dord->ev) {
+        if (!ev) {
+            hipError_t ee = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (ee != hipSuccess) return hip_fail(ee);
+        }
+    }
+    // Alternate two events: the new launch waits on the previous one and records the other.
+    eik::SolveOrder order;
+    order.after = dord->any ? dord->ev[dord->next ^ 1] : nullptr;
+    order.done = dord->ev[dord->next];
     hipError_t e = eik::launch_solve(P, cell, f_dtype, F, nsrc, idx_dev, q_dev, u_out, stream,
-                                     opt.workers, &used, evp);
+                                     opt.workers, &used, evp, &order);
+    if (e == hipSuccess && nsrc > 0) {
+        dord->any = true;
+        dord->next ^= 1;
+    }
     if (e != hipSuccess) return hip_fail(e);
     w->used = true;
     w->cells = L.ncell;

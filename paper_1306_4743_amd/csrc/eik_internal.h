@@ -19,8 +19,10 @@ constexpr int EIK_EINVAL_DEV = EIK_EINVAL;
 constexpr int EIK_ENOCONV_DEV = EIK_ENOCONV;
 constexpr int EIK_ECANCELLED_DEV = EIK_ECANCELLED;
 
-// Persistent workers per workgroup (each wave64 is one worker).
+// Persistent workers per workgroup (each wave64 is one worker); the dual sweep keeps one more
+// byte array per worker in LDS, so three workers per group keep twelve workers per CU.
 constexpr int kWavesPerGroup = 4;
+constexpr int kWavesPerGroupDual = 3;
 
 // Counter slots.
 enum {
@@ -56,6 +58,7 @@ struct SolveParams {
     int ncell;             // ncx * ncy * ncz
     int max_rounds;
     int max_sweeps;
+    int inner;             // in-cell solver: 0 sweeps, 1 active-list relaxation, 2 dual sweeps
     double h, tol, delta;
     uint64_t shuffle;
     uint64_t watchdog_polls;  // polls of the barrier word before a wait is abandoned
@@ -70,6 +73,8 @@ struct SolveParams {
     uint32_t* bar;         // grid barrier: bar[0] arrivals, bar[kBarGen] generation
     int* status;           // device status word
     unsigned long long* stats;  // [ST_COUNT]
+    int64_t* round_log;    // optional [2 * round_log_len]
+    int64_t round_log_len;
 };
 
 // Optional events recorded around the solve kernel (ev[1], ev[2]) and the whole call
@@ -78,8 +83,17 @@ struct LaunchEvents {
     hipEvent_t ev[4];
 };
 
+// Ordering of persistent solve kernels on one device: the launch waits for `after` (the end of
+// the previous solve kernel, any stream) and records `done` right after itself.  A grid
+// barrier needs every workgroup of its launch resident, which two such launches cannot share.
+struct SolveOrder {
+    hipEvent_t after;  // may be null
+    hipEvent_t done;
+};
+
 hipError_t launch_solve(const SolveParams& P, int cell, int f_dtype, const void* F, int64_t nsrc,
                         const int64_t* idx3, const double* q, double* u_out, hipStream_t s,
-                        int workers, int* used, const LaunchEvents* events);
+                        int workers, int* used, const LaunchEvents* events,
+                        const SolveOrder* order);
 
 }  // namespace eik

@@ -70,6 +70,42 @@ struct PlaneTable {
 __constant__ PlaneTable<4> kPlanes4 = PlaneTable<4>();
 __constant__ PlaneTable<8> kPlanes8 = PlaneTable<8>();
 
+// Two sweep streams on one cell, offset by half a sweep: at step t, lanes [0, n_t) take the
+// nodes of plane t of stream 0 and the next lanes take plane (t + H) mod NP of stream 1
+// (bit 15 set), H = NP / 2.  The two planes hold at most 49 nodes at r = 8 (13 at r = 4).
+template <int R>
+struct DualTable {
+    static constexpr int NP = 3 * R - 2;
+    static constexpr int H = NP / 2;
+    uint16_t slot[NP * 64];
+    constexpr DualTable() : slot() {
+        for (int i = 0; i < NP * 64; ++i) slot[i] = 0xFFFF;
+        for (int t = 0; t < NP; ++t) {
+            int n = 0;
+            for (int stream = 0; stream < 2; ++stream) {
+                const int p = stream ? (t + H) % NP : t;
+                for (int z = 0; z < R; ++z)
+                    for (int y = 0; y < R; ++y) {
+                        int x = p - y - z;
+                        if (x < 0 || x >= R) continue;
+                        slot[t * 64 + n] = (uint16_t)(x | (y << 5) | (z << 10) | (stream << 15));
+                        ++n;
+                    }
+            }
+        }
+    }
+};
+
+__constant__ DualTable<4> kDual4 = DualTable<4>();
+__constant__ DualTable<8> kDual8 = DualTable<8>();
+
+template <int R>
+__device__ __forceinline__ const uint16_t* dual_slots();
+template <>
+__device__ __forceinline__ const uint16_t* dual_slots<4>() { return kDual4.slot; }
+template <>
+__device__ __forceinline__ const uint16_t* dual_slots<8>() { return kDual8.slot; }
+
 template <int R>
 __device__ __forceinline__ const uint16_t* plane_slots();
 template <>
@@ -125,27 +161,61 @@ __device__ __forceinline__ uint64_t ld_relaxed_u64(const uint64_t* p) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Local solve of eq. (2): the smallest U with sum_k max(U - m_k, 0)^2 = s^2 given the upwind
-// axis values m_k (+inf when absent).  Sorted a <= b <= c, one, two or three terms are tried;
-// the discriminants are in difference form (no cancellation of O(U^2) quantities).  Each
-// branch is taken only when its guard holds, so +inf never meets +inf in a subtraction.
+// Square root of d >= 0 for the local solve: hardware reciprocal square root refined by one
+// Goldschmidt step and two Newton corrections (the standard refinement, without the rescaling
+// for subnormal or huge arguments that the discriminants here never need).  Within one ulp.
+__device__ __forceinline__ double disc_sqrt(double d) {
+    const double r = __builtin_amdgcn_rsq(d);
+    double g = d * r, hh = 0.5 * r;
+    const double e = fma(-hh, g, 0.5);
+    g = fma(g, e, g);
+    hh = fma(hh, e, hh);
+    double res = fma(-g, g, d);
+    g = fma(res, hh, g);
+    res = fma(-g, g, d);
+    g = fma(res, hh, g);
+    return d > 0.0 ? g : 0.0;
+}
 
+// IEEE minimum / maximum of two doubles as single instructions.  (The library fmin/fmax first
+// quiet signalling NaNs with an extra instruction per operand; these values never hold one.)
+__device__ __forceinline__ double vmin(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double vmax(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+// min(|a|, |b|): the smaller of two neighbour values whose sign bit may carry an active flag.
+__device__ __forceinline__ double vmin_abs(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Local solve of eq. (2): the smallest U with sum_k max(U - m_k, 0)^2 = s^2 given the upwind
+// axis values m_k (+inf when absent).  Sorted a <= b <= c: the one-term root a + s holds if it
+// does not exceed b, else the two-term root if it does not exceed c, else the three-term root.
+// The discriminants are in difference form (no cancellation of O(U^2) quantities); the
+// three-term one is symmetric in the m_k, so it is formed from the unsorted values in parallel
+// with the sort.  All three candidates are computed and the valid one selected; a candidate
+// whose guard fails may be NaN (when b or c is +inf) and is never selected.
 __device__ __forceinline__ double local_solve(double m0, double m1, double m2, double s) {
-    const double t1 = fmin(m0, m1), t2 = fmax(m0, m1);
-    const double t3 = fmin(t2, m2), c = fmax(t2, m2);
-    const double a = fmin(t1, t3), b = fmax(t1, t3);
-    double u = a + s;
-    if (u > b) {
-        const double dab = a - b;
-        u = 0.5 * (a + b + sqrt(fma(2.0 * s, s, -dab * dab)));
-        if (u > c) {
-            const double dac = a - c, dbc = b - c;
-            double d3 = 3.0 * s * s - dab * dab - dac * dac - dbc * dbc;
-            d3 = fmax(d3, 0.0);
-            u = (a + b + c + sqrt(d3)) * (1.0 / 3.0);
-        }
-    }
-    return u;
+    const double t1 = vmin(m0, m1), t2 = vmax(m0, m1);
+    const double t3 = vmin(t2, m2), c = vmax(t2, m2);
+    const double a = vmin(t1, t3), b = vmax(t1, t3);
+    const double ss = s * s;
+    const double d01 = m0 - m1, d02 = m0 - m2, d12 = m1 - m2;
+    const double d3 = vmax(fma(3.0, ss, -fma(d01, d01, fma(d02, d02, d12 * d12))), 0.0);
+    const double u3 = (m0 + m1 + m2 + disc_sqrt(d3)) * (1.0 / 3.0);
+    const double dab = a - b;
+    const double d2 = fma(2.0, ss, -dab * dab);
+    const double u2 = 0.5 * (a + b + disc_sqrt(d2));
+    const double u1 = a + s;
+    return u1 <= b ? u1 : (u2 <= c ? u2 : u3);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -192,13 +262,20 @@ __device__ __forceinline__ void face_node(int f, int a, int b, int& x, int& y, i
 // sign bit of its stored value: values are >= +0, so -|U| marks "active" without extra storage
 // and is read together with the value.  Every read of a value goes through fabs().
 
-template <int R>
+// In-cell solvers.
+constexpr int INNER_SWEEP = 0;  // locking sweeps in diagonal-plane order (Algorithm 3)
+constexpr int INNER_LIST = 1;   // relaxation over a compacted list of active nodes
+constexpr int INNER_DUAL = 2;   // two sweep streams on one cell, half a sweep apart
+
+template <int R, int INNER>
 struct WaveLds {
     static constexpr int B = R + 2;
     static constexpr int BOX = B * B * B;
     double U[BOX];        // cell values with a one-node halo (edges/corners unused)
     double S[R * R * R];  // s = h/F; -1 marks an exit node, 0 a padding node
     int32_t q[64];        // cells newly queued for the next round, not yet published
+    uint16_t lst[INNER == INNER_LIST ? 2 : 0][R * R * R];  // lists of the list relaxation
+    uint8_t A[INNER == INNER_DUAL ? ((BOX + 7) & ~7) : 0];  // active flags of the dual sweep
 };
 
 template <int R>
@@ -214,12 +291,23 @@ struct PlaneRegs {
     static constexpr int NP = 3 * R - 2;
     uint32_t pk[(NP + 1) / 2];
     uint32_t valid;
+    int dummy;  // this lane's scratch slot: a box node on a halo edge, never read
 };
 
-template <int R>
+template <int R, int INNER>
 __device__ __forceinline__ void load_plane_regs(PlaneRegs<R>& pr, int lane) {
     static_assert(PlaneTable<R>::PASSES == 1, "one 64-lane pass per plane");
-    const uint16_t* slots = plane_slots<R>();
+    const uint16_t* slots = INNER == INNER_DUAL ? dual_slots<R>() : plane_slots<R>();
+    // Halo edges: lines where two coordinates are -1 or R (12 R nodes); lane -> one of them.
+    {
+        const int e = lane % (12 * R), edge = e / R, t = e % R;
+        const int u = (edge & 1) ? R : -1, v = (edge & 2) ? R : -1;
+        const int kind = edge >> 2;
+        const int x = kind == 0 ? u : (kind == 1 ? u : t);
+        const int y = kind == 0 ? v : (kind == 1 ? t : u);
+        const int z = kind == 0 ? t : v;
+        pr.dummy = box_index<R>(x, y, z);
+    }
     pr.valid = 0;
 #pragma unroll
     for (int p = 0; p < PlaneRegs<R>::NP; ++p) {
@@ -259,9 +347,9 @@ struct WaveQueue {
     double minkey;  // per-lane smallest value tagged this round (used with a priority band)
 };
 
-template <int R>
+template <int R, int INNER>
 __device__ __forceinline__ void queue_flush(const SolveParams& P, int nxt, RoundCtl* ctl_next,
-                                            WaveLds<R>& L, int lane, WaveQueue& wq) {
+                                            WaveLds<R, INNER>& L, int lane, WaveQueue& wq) {
     if (wq.n == 0) return;
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&ctl_next->count, (uint32_t)wq.n);
@@ -273,9 +361,9 @@ __device__ __forceinline__ void queue_flush(const SolveParams& P, int nxt, Round
 
 // Every lane with do_tag set tags one cell (any lanes, in parallel): cell value <- min(value),
 // flags |= bits | QUEUED, and the cell joins the next round's list unless already queued.
-template <int R>
+template <int R, int INNER>
 __device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCtl* ctl_next,
-                                          WaveLds<R>& L, int lane, WaveQueue& wq, bool do_tag,
+                                          WaveLds<R, INNER>& L, int lane, WaveQueue& wq, bool do_tag,
                                           int target, uint32_t bits, double value) {
     bool newq = false;
     if (do_tag) {
@@ -287,7 +375,7 @@ __device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCt
     const uint64_t mask = __ballot(newq);
     const int k = __popcll(mask);
     if (k == 0) return;
-    if (wq.n + k > 64) queue_flush<R>(P, nxt, ctl_next, L, lane, wq);
+    if (wq.n + k > 64) queue_flush<R, INNER>(P, nxt, ctl_next, L, lane, wq);
     if (newq) {
         const int rank = __popcll(mask & ((1ull << lane) - 1ull));
         L.q[wq.n + rank] = target;
@@ -315,9 +403,9 @@ __device__ __forceinline__ int face_step(int f) {
     return dir * (axis == 0 ? 1 : (axis == 1 ? B : B * B));
 }
 
-template <int R, typename FT>
+template <int R, typename FT, int INNER>
 __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t fl,
-                                           double popped_key, WaveLds<R>& L,
+                                           double popped_key, WaveLds<R, INNER>& L,
                                            const PlaneRegs<R>& pr, int lane,
                                            RoundCtl* ctl_next, int nxt, VisitCounters& cnt,
                                            WaveQueue& wq) {
@@ -362,13 +450,19 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         }
     }
     wave_sync();
+    // Marks node b active: the sign bit of its value, or its flag byte for the dual sweep.
+    auto activate = [&](int b) {
+        if constexpr (INNER == INNER_DUAL) L.A[b] = 1;
+        else L.U[b] = -fabs(L.U[b]);
+    };
+    if constexpr (INNER == INNER_DUAL) {
+        for (int b = lane; b < WaveLds<R, INNER>::BOX; b += 64) L.A[b] = 0;
+        wave_sync();
+    }
     if (fl & FL_ALL) {
         for (int l = lane; l < R3; l += 64) {
             const int x = l % R, y = (l / R) % R, z = l / R2;
-            if (L.S[l] > 0.0) {
-                const int b = box_index<R>(x, y, z);
-                L.U[b] = -L.U[b];
-            }
+            if (L.S[l] > 0.0) activate(box_index<R>(x, y, z));
         }
     } else {
 #pragma unroll
@@ -376,82 +470,274 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
             if ((fl & (1u << f)) && lane < R2) {
                 int x, y, z;
                 face_node<R>(f, lane % R, lane / R, x, y, z);
-                if (L.S[x + R * (y + R * z)] > 0.0) {
-                    const int b = box_index<R>(x, y, z);
-                    L.U[b] = -fabs(L.U[b]);
-                }
+                if (L.S[x + R * (y + R * z)] > 0.0) activate(box_index<R>(x, y, z));
             }
         }
     }
     wave_sync();
 
     const unsigned long long t1 = cycles();
-    // Sweeps: preferred directions first (Gray order), then the default Gray cycle.  A sweep in
-    // direction d visits the planes of the reflected coordinates x ^ mx etc. in increasing order.
-    const uint32_t pref = (fl >> FL_DIR_SHIFT) & 0xFFu;
-    int pi = 0, ci = 0;
     bool visit_changed = false, requeue = false;
-    unsigned long long upd = 0;
+    unsigned int upd = 0;
     int nsweeps = 0;
-    for (;;) {
-        int d = -1;
-        while (pi < 8) {
-            const int cand = kGray[pi++];
-            if (pref & (1u << cand)) { d = cand; break; }
-        }
-        if (d < 0) d = kGray[(ci++) & 7];
-        const int mx = (d & 1) ? R - 1 : 0, my = (d & 2) ? R - 1 : 0, mz = (d & 4) ? R - 1 : 0;
-        bool changed = false;
-        double maxdec = 0.0;
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            uint32_t e = (pr.pk[p >> 1] >> ((p & 1) * 16)) & 0xFFFFu;
-            // Keep the decode inside the sweep loop: hoisting the 3 x NP decoded coordinates
-            // out of it costs more registers than the few ALU operations it saves.
-            asm volatile("" : "+v"(e));
-            const int x = (int)(e & 31u) ^ mx, y = (int)((e >> 5) & 31u) ^ my,
-                      z = (int)((e >> 10) & 31u) ^ mz;
-            const int b = x + B * (y + B * z) + BOFF;
-            const int l = x + R * (y + R * z);
-            double raw = L.U[b];
-            double s = L.S[l];
-            double xm = L.U[b - 1], xp = L.U[b + 1];
-            double ym = L.U[b - B], yp = L.U[b + B];
-            double zm = L.U[b - B * B], zp = L.U[b + B * B];
-            // Issue every LDS read of the step before the activity test: one LDS round trip.
-            asm volatile("" : "+v"(raw), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
-                         "+v"(zm), "+v"(zp));
-            const bool act = ((pr.valid >> p) & 1u) && is_active(raw);
-            if (__any(act)) {
-                if (act) {
-                    const double old = -raw;  // |raw|; writing it back clears the active flag
+    const bool track_dec = P.tol > 0.0;
+    if constexpr (INNER == INNER_SWEEP) {
+        // Sweeps: preferred directions first (Gray order), then the default Gray cycle.  A sweep in
+        // direction d visits the planes of the reflected coordinates x ^ mx etc. in increasing order.
+        const uint32_t pref = (fl >> FL_DIR_SHIFT) & 0xFFu;
+        int pi = 0, ci = 0;
+        for (;;) {
+            int d = -1;
+            while (pi < 8) {
+                const int cand = kGray[pi++];
+                if (pref & (1u << cand)) { d = cand; break; }
+            }
+            if (d < 0) d = kGray[(ci++) & 7];
+            const int mx = (d & 1) ? R - 1 : 0, my = (d & 2) ? R - 1 : 0, mz = (d & 4) ? R - 1 : 0;
+            bool changed = false;
+            double maxdec = 0.0;
+    #pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                uint32_t e = (pr.pk[p >> 1] >> ((p & 1) * 16)) & 0xFFFFu;
+                // Keep the decode inside the sweep loop: hoisting the 3 x NP decoded coordinates
+                // out of it costs more registers than the few ALU operations it saves.
+                asm volatile("" : "+v"(e));
+                const int x = (int)(e & 31u) ^ mx, y = (int)((e >> 5) & 31u) ^ my,
+                          z = (int)((e >> 10) & 31u) ^ mz;
+                const int b = x + B * (y + B * z) + BOFF;
+                const int l = x + R * (y + R * z);
+                double raw = L.U[b];
+                double s = L.S[l];
+                double xm = L.U[b - 1], xp = L.U[b + 1];
+                double ym = L.U[b - B], yp = L.U[b + B];
+                double zm = L.U[b - B * B], zp = L.U[b + B * B];
+                // Issue every LDS read of the step before the activity test: one LDS round trip.
+                asm volatile("" : "+v"(raw), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
+                             "+v"(zm), "+v"(zp));
+                const bool act = ((pr.valid >> p) & 1u) && is_active(raw);
+                if (__any(act)) {
+                    // Every lane runs the same instructions: an active lane stores its value
+                    // back (|raw| clears the flag) and an activation stores -|v| into the
+                    // neighbour; stores with nothing to do go to the lane's own scratch slot on
+                    // a halo edge, which no node reads.  Two lanes never store different values
+                    // to one node in one step (a plane's nodes are not neighbours of each other;
+                    // activations of a shared neighbour agree).
+                    const double old = fabs(raw);
                     xm = fabs(xm); xp = fabs(xp); ym = fabs(ym);
                     yp = fabs(yp); zm = fabs(zm); zp = fabs(zp);
-                    const double g = local_solve(fmin(xm, xp), fmin(ym, yp), fmin(zm, zp), s);
-                    // exit nodes (s < 0) keep their value; padding nodes are never active
-                    const bool dec = s > 0.0 && g < old;
-                    upd += s > 0.0;
-                    L.U[b] = dec ? g : old;
-                    if (dec) {
-                        maxdec = fmax(maxdec, old - g);
-                        changed = true;
-                        if (xm > g) L.U[b - 1] = -xm;
-                        if (xp > g) L.U[b + 1] = -xp;
-                        if (ym > g) L.U[b - B] = -ym;
-                        if (yp > g) L.U[b + B] = -yp;
-                        if (zm > g) L.U[b - B * B] = -zm;
-                        if (zp > g) L.U[b + B * B] = -zp;
+                    const double g = local_solve(vmin(xm, xp), vmin(ym, yp), vmin(zm, zp), s);
+                    const bool live = act && s > 0.0;
+                    const bool dec = live && g < old;
+                    upd += live ? 1u : 0u;
+                    const int dm = pr.dummy;
+                    L.U[act ? b : dm] = dec ? g : old;
+                    changed |= dec;
+                    if (track_dec && dec) maxdec = fmax(maxdec, old - g);
+                    L.U[(dec && xm > g) ? b - 1 : dm] = -xm;
+                    L.U[(dec && xp > g) ? b + 1 : dm] = -xp;
+                    L.U[(dec && ym > g) ? b - B : dm] = -ym;
+                    L.U[(dec && yp > g) ? b + B : dm] = -yp;
+                    L.U[(dec && zm > g) ? b - B * B : dm] = -zm;
+                    L.U[(dec && zp > g) ? b + B * B : dm] = -zp;
+                }
+                wave_sync();
+            }
+            ++nsweeps;
+            const bool any_changed = __any(changed);
+            visit_changed |= any_changed;
+            if (!any_changed) break;
+            // Done when no node is left active (all were evaluated in this sweep except those
+            // activated in planes it had already passed): saves the confirming sweep.
+            bool left = false;
+            for (int l = lane; l < R3; l += 64) {
+                const int x = l % R, y = (l / R) % R, z = l / R2;
+                left |= is_active(L.U[box_index<R>(x, y, z)]);
+            }
+            if (!__any(left)) break;
+            if (P.tol > 0.0 && wave_max(maxdec) <= P.tol) break;
+            if (nsweeps >= P.max_sweeps) { requeue = true; break; }
+        }
+    } else if constexpr (INNER == INNER_DUAL) {
+        // Two sweep streams on the cell at once, half a sweep apart: at step t stream 0
+        // updates plane t of its direction and stream 1 plane t + H of its own.  For two
+        // directions that differ in one or two axes the two planes never share a node (their
+        // plane indices differ by an odd number below H, or by an even number, never by H),
+        // so each node has one writer per step; reads of nodes the other stream writes in the
+        // same step see the older value (an upper bound), which the activation flags repair.
+        // Per step: values first, then the own flags cleared, then neighbour flags set, so an
+        // activation is never lost.  Directions come from the same sequence as the sweeps
+        // (preferred ones first, then the Gray cycle); a stream never takes the direction
+        // opposite to the other stream's (the one pair whose planes can meet).
+        constexpr int H = NP / 2;
+        const uint32_t pref = (fl >> FL_DIR_SHIFT) & 0xFFu;
+        int pi = 0, ci = 0;
+        auto next_dir = [&]() {
+            while (pi < 8) {
+                const int cand = kGray[pi++];
+                if (pref & (1u << cand)) return cand;
+            }
+            return kGray[(ci++) & 7];
+        };
+        int d0 = next_dir();
+        int d1 = next_dir();
+        if (__popc((uint32_t)(d0 ^ d1)) == 3) d1 = d0;
+        bool done = false;
+        double maxdec = 0.0, dec_prev = 0.0;
+        bool changed = false;
+        const int dm = pr.dummy;
+        while (!done) {
+#pragma unroll
+            for (int t = 0; t < NP; ++t) {
+                if (t == 0 && nsweeps > 0) {
+                    d0 = next_dir();
+                    if (__popc((uint32_t)(d0 ^ d1)) == 3) d0 = d1;
+                }
+                if (t == H && nsweeps > 1) {
+                    d1 = next_dir();
+                    if (__popc((uint32_t)(d0 ^ d1)) == 3) d1 = d0;
+                }
+                uint32_t e = (pr.pk[t >> 1] >> ((t & 1) * 16)) & 0xFFFFu;
+                asm volatile("" : "+v"(e));
+                const int dd = (e & 0x8000u) ? d1 : d0;
+                const int x = (int)(e & 31u) ^ ((dd & 1) ? R - 1 : 0);
+                const int y = (int)((e >> 5) & 31u) ^ ((dd & 2) ? R - 1 : 0);
+                const int z = (int)((e >> 10) & 31u) ^ ((dd & 4) ? R - 1 : 0);
+                const int b = x + B * (y + B * z) + BOFF;
+                const int l = x + R * (y + R * z);
+                double old = L.U[b];
+                double s = L.S[l];
+                double xm = L.U[b - 1], xp = L.U[b + 1];
+                double ym = L.U[b - B], yp = L.U[b + B];
+                double zm = L.U[b - B * B], zp = L.U[b + B * B];
+                uint32_t af = L.A[b];
+                asm volatile("" : "+v"(old), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
+                             "+v"(zm), "+v"(zp), "+v"(af));
+                const bool act = ((pr.valid >> t) & 1u) && af != 0u;
+                if (__any(act)) {
+                    const double g = local_solve(vmin(xm, xp), vmin(ym, yp), vmin(zm, zp), s);
+                    const bool live = act && s > 0.0;
+                    const bool dec = live && g < old;
+                    upd += live ? 1u : 0u;
+                    changed |= dec;
+                    if (track_dec && dec) maxdec = fmax(maxdec, old - g);
+                    L.U[dec ? b : dm] = g;
+                    L.A[act ? b : dm] = 0;
+                    L.A[(dec && xm > g) ? b - 1 : dm] = 1;
+                    L.A[(dec && xp > g) ? b + 1 : dm] = 1;
+                    L.A[(dec && ym > g) ? b - B : dm] = 1;
+                    L.A[(dec && yp > g) ? b + B : dm] = 1;
+                    L.A[(dec && zm > g) ? b - B * B : dm] = 1;
+                    L.A[(dec && zp > g) ? b + B * B : dm] = 1;
+                }
+                wave_sync();
+                if (t == H - 1 || t == NP - 1) {
+                    // One sweep's worth of steps (H steps of two streams) has passed.
+                    ++nsweeps;
+                    const bool any_changed = __any(changed);
+                    visit_changed |= any_changed;
+                    bool left = false;
+                    for (int q = lane; q < R3; q += 64) {
+                        const int qx = q % R, qy = (q / R) % R, qz = q / R2;
+                        left |= L.A[box_index<R>(qx, qy, qz)] != 0;
                     }
+                    // The tol test needs a complete sweep: the last NP steps hold one for the
+                    // stream whose sweep began NP steps ago.
+                    const double dec_half = track_dec ? wave_max(maxdec) : 0.0;
+                    const bool small = track_dec && nsweeps >= 2 && fmax(dec_half, dec_prev) <= P.tol;
+                    dec_prev = dec_half;
+                    if (!__any(left) || small) {
+                        done = true;
+                        break;
+                    }
+                    // The cap applies at the end of a cycle, after which stream 0 has swept
+                    // every node once: a capped visit still evaluates every active node.
+                    if (t == NP - 1 && nsweeps >= P.max_sweeps) {
+                        requeue = true;
+                        done = true;
+                        break;
+                    }
+                    changed = false;
+                    maxdec = 0.0;
                 }
             }
-            wave_sync();
         }
-        ++nsweeps;
-        const bool any_changed = __any(changed);
-        visit_changed |= any_changed;
-        if (!any_changed) break;
-        if (P.tol > 0.0 && wave_max(maxdec) <= P.tol) break;
-        if (nsweeps >= P.max_sweeps) { requeue = true; break; }
+    } else {
+        // Relaxation over a list of active nodes (the cell sub-problem of Section 4 solved by a
+        // label-correcting iteration instead of sweeps, which Section 5 allows): every pass
+        // evaluates the listed nodes in dense 64-lane chunks, and a node that decreases queues
+        // its larger in-cell neighbours for the next pass (Algorithm 3 activation).  The sign bit
+        // of a value means "listed and not yet evaluated"; setting it with an LDS atomic
+        // dedupes the lists.  Chunks see earlier chunks' results (values only decrease), so the
+        // iteration reaches the same fixed point as the sweeps.
+        int n_cur = 0, cur = 0;
+        for (int base = 0; base < R3; base += 64) {
+            const int l = base + lane;
+            bool on = false;
+            if (l < R3) {
+                const int x = l % R, y = (l / R) % R, z = l / R2;
+                on = is_active(L.U[box_index<R>(x, y, z)]);
+            }
+            const uint64_t m = __ballot(on);
+            if (on) L.lst[0][n_cur + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)l;
+            n_cur += __popcll(m);
+        }
+        wave_sync();
+        const uint64_t below = (1ull << lane) - 1ull;
+        while (n_cur > 0) {
+            int n_next = 0;
+            bool changed = false;
+            double maxdec = 0.0;
+            for (int base = 0; base < n_cur; base += 64) {
+                const bool valid = base + lane < n_cur;
+                const int l = valid ? (int)L.lst[cur][base + lane] : 0;
+                const int x = l % R, y = (l / R) % R, z = l / R2;
+                const int b = x + B * (y + B * z) + BOFF;
+                double raw = L.U[b];
+                double s = L.S[l];
+                double xm = L.U[b - 1], xp = L.U[b + 1];
+                double ym = L.U[b - B], yp = L.U[b + B];
+                double zm = L.U[b - B * B], zp = L.U[b + B * B];
+                asm volatile("" : "+v"(raw), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
+                             "+v"(zm), "+v"(zp));
+                const double old = fabs(raw);
+                xm = fabs(xm); xp = fabs(xp); ym = fabs(ym);
+                yp = fabs(yp); zm = fabs(zm); zp = fabs(zp);
+                const double g = local_solve(fmin(xm, xp), fmin(ym, yp), fmin(zm, zp), s);
+                const bool live = valid && s > 0.0;
+                const bool dec = live && g < old;
+                upd += live ? 1u : 0u;
+                L.U[valid ? b : 0] = dec ? g : old;  // positive: no longer listed
+                if (dec) {
+                    maxdec = fmax(maxdec, old - g);
+                    changed = true;
+                }
+                // Queue the larger in-cell neighbours (halo nodes belong to other cells).
+                const bool want[6] = {dec && x > 0 && xm > g, dec && x < R - 1 && xp > g,
+                                      dec && y > 0 && ym > g, dec && y < R - 1 && yp > g,
+                                      dec && z > 0 && zm > g, dec && z < R - 1 && zp > g};
+                const int off[6] = {-1, 1, -B, B, -B * B, B * B};
+                const int loff[6] = {-1, 1, -R, R, -R2, R2};
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    bool app = false;
+                    if (want[k]) {
+                        unsigned int* hi = reinterpret_cast<unsigned int*>(&L.U[b + off[k]]) + 1;
+                        app = !(atomicOr(hi, 0x80000000u) & 0x80000000u);
+                    }
+                    const uint64_t m = __ballot(app);
+                    if (app) L.lst[cur ^ 1][n_next + __popcll(m & below)] = (uint16_t)(l + loff[k]);
+                    n_next += __popcll(m);
+                }
+                wave_sync();
+            }
+            ++nsweeps;
+            const bool any_changed = __any(changed);
+            visit_changed |= any_changed;
+            cur ^= 1;
+            n_cur = n_next;
+            if (P.tol > 0.0 && wave_max(maxdec) <= P.tol) break;
+            if (n_cur > 0 && nsweeps >= P.max_sweeps) { requeue = true; break; }
+        }
     }
     cnt.sweeps += (unsigned long long)nsweeps;
     cnt.updates += upd;
@@ -506,7 +792,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         }
         cnt.requeued += 1;
     }
-    tag_lanes<R>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits, my_value);
+    tag_lanes<R, INNER>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits, my_value);
     const unsigned long long t3 = cycles();
     cnt.cyc_stage += t1 - t0;
     cnt.cyc_sweep += t2 - t1;
@@ -554,16 +840,16 @@ __device__ bool grid_barrier(const SolveParams& P) {
 // The solver.  Each wave is an independent worker; each workgroup holds `W` workers.  One
 // launch runs every round (persistent, grid barrier between rounds).
 
-template <int R, typename FT, int W>
+template <int R, typename FT, int W, int INNER>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3)))
 k_solve(SolveParams P) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    WaveLds<R>& L = reinterpret_cast<WaveLds<R>*>(lds_raw)[wave];
+    WaveLds<R, INNER>& L = reinterpret_cast<WaveLds<R, INNER>*>(lds_raw)[wave];
     VisitCounters cnt{0, 0, 0, 0, 0, 0};
     unsigned long long cyc_pop = 0, cyc_wait = 0;
     PlaneRegs<R> pr;
-    load_plane_regs<R>(pr, lane);
+    load_plane_regs<R, INNER>(pr, lane);
     unsigned long long visits = 0, deferred = 0;
     int rounds_done = 0;
 
@@ -613,7 +899,7 @@ k_solve(SolveParams P) {
             // Cells outside the lowest band go straight back to the next round's list.
             const bool defer = (uint32_t)lane < cnt_here && !(bitsd(my_kb) < thr);
             deferred += __popcll(__ballot(defer));
-            tag_lanes<R>(P, nxt, ctl_next, L, lane, wq, defer, my_c, my_fl & ~FL_QUEUED,
+            tag_lanes<R, INNER>(P, nxt, ctl_next, L, lane, wq, defer, my_c, my_fl & ~FL_QUEUED,
                          bitsd(my_kb));
             cyc_pop += cycles() - tp0;
             for (uint32_t j = 0; j < cnt_here; ++j) {
@@ -622,11 +908,11 @@ k_solve(SolveParams P) {
                 const double key = bitsd(__shfl(my_kb, (int)j, 64));
                 if (!(key < thr)) continue;
                 ++visits;
-                visit_cell<R, FT>(P, c, fl, key, L, pr, lane, ctl_next, nxt, cnt, wq);
+                visit_cell<R, FT, INNER>(P, c, fl, key, L, pr, lane, ctl_next, nxt, cnt, wq);
             }
         }
         const unsigned long long tw0 = cycles();
-        queue_flush<R>(P, nxt, ctl_next, L, lane, wq);
+        queue_flush<R, INNER>(P, nxt, ctl_next, L, lane, wq);
         if (P.delta > 0.0) {
             const double mk = wave_min(wq.minkey);
             if (lane == 0 && mk < __builtin_inf())
@@ -635,6 +921,10 @@ k_solve(SolveParams P) {
         ++rounds_done;
         const bool ok = grid_barrier(P);
         cyc_wait += cycles() - tw0;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && t < P.round_log_len) {
+            P.round_log[2 * t] = (int64_t)n;
+            P.round_log[2 * t + 1] = (int64_t)cycles();
+        }
         if (!ok) break;
         const uint32_t nnext = __hip_atomic_load(&ctl_next->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int st = __hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -781,13 +1071,13 @@ __global__ void k_output(SolveParams P, double* __restrict__ out) {
 // ------------------------------------------------------------------------------------------
 // Host-side launchers.
 
-template <int R, int W>
-constexpr size_t solve_lds_bytes() { return sizeof(WaveLds<R>) * W; }
+template <int R, int W, int INNER>
+constexpr size_t solve_lds_bytes() { return sizeof(WaveLds<R, INNER>) * W; }
 
-template <int R, typename FT, int W>
+template <int R, typename FT, int W, int INNER>
 static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int workers, int* used) {
-    const size_t lds = solve_lds_bytes<R, W>();
-    auto kern = k_solve<R, FT, W>;
+    const size_t lds = solve_lds_bytes<R, W, INNER>();
+    auto kern = k_solve<R, FT, W, INNER>;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -828,7 +1118,8 @@ static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int worker
 template <int R, typename FT>
 static hipError_t launch_all_t(const SolveParams& P, const void* F, int64_t nsrc,
                                const int64_t* idx3, const double* q, double* u_out,
-                               hipStream_t s, int workers, int* used, const LaunchEvents* ev) {
+                               hipStream_t s, int workers, int* used, const LaunchEvents* ev,
+                               const SolveOrder* order) {
     const int threads = 256;
     const size_t nodes = (size_t)P.ncell * R * R * R;
     int blocks = (int)((nodes + threads - 1) / threads);
@@ -846,8 +1137,16 @@ static hipError_t launch_all_t(const SolveParams& P, const void* F, int64_t nsrc
     if (e != hipSuccess) return e;
     if (ev && ev->ev[1] && (e = hipEventRecord(ev->ev[1], s)) != hipSuccess) return e;
     if (nsrc > 0) {
-        e = launch_solve_t<R, FT, kWavesPerGroup>(P, s, workers, used);
+        if (order && order->after && (e = hipStreamWaitEvent(s, order->after, 0)) != hipSuccess)
+            return e;
+        if (P.inner == INNER_SWEEP)
+            e = launch_solve_t<R, FT, kWavesPerGroup, INNER_SWEEP>(P, s, workers, used);
+        else if (P.inner == INNER_LIST)
+            e = launch_solve_t<R, FT, kWavesPerGroup, INNER_LIST>(P, s, workers, used);
+        else
+            e = launch_solve_t<R, FT, kWavesPerGroupDual, INNER_DUAL>(P, s, workers, used);
         if (e != hipSuccess) return e;
+        if (order && (e = hipEventRecord(order->done, s)) != hipSuccess) return e;
     }
     if (ev && ev->ev[2] && (e = hipEventRecord(ev->ev[2], s)) != hipSuccess) return e;
     const size_t out_nodes = (size_t)P.nx * P.ny * P.nz;
@@ -862,14 +1161,15 @@ static hipError_t launch_all_t(const SolveParams& P, const void* F, int64_t nsrc
 
 hipError_t launch_solve(const SolveParams& P, int cell, int f_dtype, const void* F,
                         int64_t nsrc, const int64_t* idx3, const double* q, double* u_out,
-                        hipStream_t s, int workers, int* used, const LaunchEvents* ev) {
+                        hipStream_t s, int workers, int* used, const LaunchEvents* ev,
+                        const SolveOrder* order) {
     if (cell == 8) {
-        return f_dtype == 1 ? launch_all_t<8, float>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev)
-                            : launch_all_t<8, double>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev);
+        return f_dtype == 1 ? launch_all_t<8, float>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev, order)
+                            : launch_all_t<8, double>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev, order);
     }
     if (cell == 4) {
-        return f_dtype == 1 ? launch_all_t<4, float>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev)
-                            : launch_all_t<4, double>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev);
+        return f_dtype == 1 ? launch_all_t<4, float>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev, order)
+                            : launch_all_t<4, double>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev, order);
     }
     return hipErrorInvalidValue;
 }

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libeik.so")
 EIK_OK, EIK_EINVAL, EIK_ENOMEM, EIK_EHIP, EIK_ENOCONV, EIK_ECANCELLED = 0, -1, -2, -3, -4, -5
 EIK_F64, EIK_F32 = 0, 1
 EIK_MODE_FP64 = 0
+EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL = 1, 2, 3
 
 
 class EikError(RuntimeError):
@@ -33,7 +34,9 @@ class Sources(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("delta", ctypes.c_double),
                 ("max_rounds", ctypes.c_int64), ("max_sweeps", ctypes.c_int),
-                ("workers", ctypes.c_int), ("shuffle", ctypes.c_uint64), ("timing", ctypes.c_int)]
+                ("workers", ctypes.c_int), ("shuffle", ctypes.c_uint64), ("timing", ctypes.c_int),
+                ("round_log", ctypes.c_void_p), ("round_log_len", ctypes.c_int64),
+                ("inner", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -130,7 +133,8 @@ class _HostSources:
 
 def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, stream=None,
           delta: float = 0.0, max_rounds: int = 0, max_sweeps: int = 0, workers: int = 0,
-          shuffle: int = 0, timing: bool = False, check: bool = True):
+          shuffle: int = 0, timing: bool = False, round_log=None, inner: int = 0,
+          check: bool = True):
     """Enqueue one solve of eq. (2) on ``stream`` (torch stream; default: current stream).
 
     F: torch CUDA tensor [nz, ny, nx] of float32 or float64 speeds (contiguous).
@@ -167,8 +171,13 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
     else:
         keep = _HostSources(idx3, q)
         src = keep.struct
+    rl_ptr, rl_len = None, 0
+    if round_log is not None:
+        if not (round_log.is_cuda and round_log.dtype == torch.int64 and round_log.is_contiguous()):
+            raise ValueError("round_log must be a contiguous int64 CUDA tensor")
+        rl_ptr, rl_len = round_log.data_ptr(), round_log.numel() // 2
     opts = Options(EIK_MODE_FP64, float(delta), int(max_rounds), int(max_sweeps), int(workers),
-                   int(shuffle), int(bool(timing)))
+                   int(shuffle), int(bool(timing)), rl_ptr, rl_len, int(inner))
     dims = _dims_array((nx, ny, nz))
     rc = lib.eik_solve_ex(ctypes.cast(dims, ctypes.c_void_p), float(h),
                           ctypes.c_void_p(F.data_ptr()), f_dtype, ctypes.byref(src),
