@@ -47,6 +47,7 @@ extern "C" {
 #define EIK_EHIP (-3)       /* a HIP runtime call failed                                     */
 #define EIK_ENOCONV (-4)    /* the round cap was reached before the worklist emptied         */
 #define EIK_ECANCELLED (-5) /* the solve was stopped by the device watchdog                  */
+#define EIK_EBUSY (-6)      /* a server has no room for the problem now (retry after a step)  */
 
 /* Element types of F. */
 #define EIK_F64 0
@@ -148,6 +149,9 @@ int eik_solve_ex(const int64_t dims[3], double h, const void* F, int f_dtype,
  * f_dtype as in eik_solve.  Returns EIK_OK or EIK_EINVAL. */
 int eik_query_workspace(const int64_t dims[3], int cell, int f_dtype, int mode, size_t* bytes);
 
+/* Device bytes of one grid's arrays inside a server pool (values, speeds, face copies). */
+int eik_problem_bytes(const int64_t dims[3], int cell, int f_dtype, size_t* bytes);
+
 /* Waits for all work on `stream`, then returns the device-side status of the last solve
  * enqueued on it (EIK_OK, EIK_EINVAL, EIK_ENOCONV, EIK_ECANCELLED) and, if stats != NULL,
  * its counters.  Returns EIK_EINVAL if no solve was ever enqueued on the stream. */
@@ -159,6 +163,72 @@ int eik_stream_status(hipStream_t stream, eik_stats* stats);
  * the last 256 solves are kept.  Returns the number of entries written (0 if none), or a
  * negative code. */
 int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_ms);
+
+/* One problem of a batch or of a server: the arguments of eik_solve for one grid. */
+typedef struct eik_problem {
+    int64_t dims[3];      /* as in eik_solve                                                  */
+    double h;
+    const void* F;        /* device speeds of the batch's / server's f_dtype                   */
+    eik_sources sources;
+    double* u_out;        /* device, nx*ny*nz doubles                                          */
+    double tol;
+} eik_problem;
+
+/*
+ * eik_solve_batch -- solve n independent problems in one persistent launch.  Every problem is
+ * validated as in eik_solve (any invalid one: EIK_EINVAL, nothing enqueued); all share f_dtype,
+ * cell and options.  The grids' cells are swept together round by round, so many small grids
+ * fill the device.  Each result equals the result of solving the problem alone (up to rounding
+ * order).  eik_batch_status() returns the per-problem device status after the stream finishes.
+ */
+int eik_solve_batch(int n, const eik_problem* problems, int f_dtype, int cell, hipStream_t stream,
+                    const eik_options* options);
+
+/* Waits for `stream` and writes the device status of each problem of the last batch (or of
+ * the single problem of the last eik_solve) into status[0 .. n-1].  Returns the number written
+ * or a negative code. */
+int eik_batch_status(hipStream_t stream, int n, int* status);
+
+/*
+ * Continuous-batching server.  A server owns a device pool (grids' arrays) and a cell-id
+ * space; problems are admitted while they fit, swept together with the problems already on
+ * the device, and retired (their u_out written) as soon as their own cells leave the worklist,
+ * independently of the others.  Work happens in steps: a step starts the problems admitted
+ * since the last step (staging, seeding into the next round's worklist), runs up to `rounds`
+ * worklist rounds of every problem on the device in one persistent launch, then retires the
+ * problems none of whose cells is queued.  A problem's result equals the result of solving it
+ * alone (up to rounding order).  All calls of one server must come from one thread; its stream
+ * must not be used for anything else while the server exists.
+ *   eik_server_create   pool_bytes of device memory for grid arrays, at most max_cells cells
+ *                       and max_problems problems on the device at once; cell, f_dtype and
+ *                       options (delta, max_sweeps, workers, inner) fixed for its lifetime.
+ *                       Returns EIK_EINVAL, EIK_ENOMEM or EIK_EHIP on failure (*out untouched).
+ *   eik_server_submit   admits one problem if it fits now (pool space eik_problem_bytes(),
+ *                       ncell cells, a free problem slot), else returns EIK_EBUSY (retry after
+ *                       a step retired something); EIK_EINVAL if it is invalid or could never
+ *                       fit.  On success *ticket (0, 1, 2, ... per server) identifies it.  F,
+ *                       host-side sources and u_out must stay valid until the next
+ *                       eik_server_step returned (F and the sources are read by it); u_out
+ *                       until the problem is reported finished.
+ *   eik_server_step     one step, blocking until it ran; *finished (may be NULL) receives the
+ *                       number of problems retired in it.  Returns EIK_OK, EIK_EINVAL
+ *                       (rounds < 1), a host error, or EIK_ECANCELLED if the device watchdog
+ *                       stopped the launch: then every problem on the device is retired with
+ *                       that status and the server starts again empty.
+ *   eik_server_poll     up to max retired problems not yet polled, oldest first: tickets and
+ *                       statuses (EIK_OK, EIK_EINVAL for an invalid speed, EIK_ECANCELLED).
+ *   eik_server_load     problems on the device (admitted, not retired), cells and pool bytes
+ *                       they occupy; any pointer may be NULL.
+ *   eik_server_destroy  waits for the stream and frees everything.
+ */
+typedef struct eik_server eik_server;
+int eik_server_create(eik_server** out, size_t pool_bytes, int64_t max_cells, int max_problems,
+                      int cell, int f_dtype, hipStream_t stream, const eik_options* options);
+int eik_server_submit(eik_server* srv, const eik_problem* problem, int64_t* ticket);
+int eik_server_step(eik_server* srv, int64_t rounds, int* finished);
+int eik_server_poll(eik_server* srv, int max, int64_t* tickets, int* status, int* n_out);
+int eik_server_load(eik_server* srv, int* problems, int64_t* cells, size_t* pool_used);
+int eik_server_destroy(eik_server* srv);
 
 /* Human-readable name of a status code (static storage). */
 const char* eik_strerror(int code);

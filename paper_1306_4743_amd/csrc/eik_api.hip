@@ -1,9 +1,10 @@
-// eik_api.hip -- the C ABI of libeik: argument validation, per-stream workspaces, launches.
+// eik_api.hip -- the C ABI of libeik: argument validation, workspaces, launches, the server.
 //
 // Every entry point is declared, with its contract, in include/eik.h.
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -15,135 +16,21 @@
 
 namespace {
 
+using eik::kSmallBar;
+using eik::kSmallCtl;
+using eik::kSmallNextRound;
+using eik::kSmallStats;
+using eik::kSmallStatus;
+using eik::Slot;
 using eik::SolveParams;
 
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
-struct Layout {
-    int ncx = 0, ncy = 0, ncz = 0;
-    int64_t ncell = 0;
-    size_t off_u = 0, off_f = 0, off_faces = 0, off_key = 0, off_flags = 0, off_list = 0,
-           off_small = 0, total = 0;
-};
-
-// Device workspace of one solve: cell-blocked values, speeds, face copies, the double-buffered
-// cell state, the lists and a small control area (round control blocks, barrier, status,
-// counters).
-bool make_layout(const int64_t dims[3], int cell, int f_dtype, Layout* L) {
-    const int64_t r = cell;
-    L->ncx = (int)((dims[0] + r - 1) / r);
-    L->ncy = (int)((dims[1] + r - 1) / r);
-    L->ncz = (int)((dims[2] + r - 1) / r);
-    L->ncell = (int64_t)L->ncx * L->ncy * L->ncz;
-    if (L->ncell * r * r * r >= (int64_t(1) << 31)) return false;
-    const size_t n = (size_t)L->ncell;
-    const size_t r3 = (size_t)(r * r * r), r2 = (size_t)(r * r);
-    const size_t fsz = f_dtype == EIK_F32 ? 4 : 8;
-    size_t o = 0;
-    L->off_small = o; o = align_up(o + eik::kSmallBytes);
-    L->off_u = o; o = align_up(o + n * r3 * 8);
-    L->off_f = o; o = align_up(o + n * r3 * fsz);
-    L->off_faces = o; o = align_up(o + n * 6 * r2 * 8);
-    L->off_key = o; o = align_up(o + 2 * n * 8);
-    L->off_flags = o; o = align_up(o + 2 * n * 4);
-    L->off_list = o; o = align_up(o + 2 * n * 4);
-    L->total = o;
-    return true;
-}
-
-using eik::kSmallBar;
-using eik::kSmallCtl;
-using eik::kSmallStats;
-using eik::kSmallStatus;
-
-struct Workspace {
-    int device = -1;
-    void* base = nullptr;
-    size_t bytes = 0;
-    void* src_dev = nullptr;  // device copy of host-provided sources
-    size_t src_bytes = 0;
-    void* src_host = nullptr;  // pinned staging buffer
-    size_t src_host_bytes = 0;
-    hipEvent_t staged = nullptr;  // last copy out of src_host finished
-    bool used = false;
-    int64_t cells = 0;
-    std::mutex mu;  // serialises enqueues that share this workspace
-    // ring of event quadruples for timed solves
-    static constexpr int kRing = 256;
-    std::vector<eik::LaunchEvents> ring;
-    int64_t timed = 0;  // timed solves enqueued so far
-};
-
-std::mutex g_mu;
-std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
-
-// Per device: the event recorded after the most recently enqueued persistent solve kernel.
-// Each new solve kernel waits for it, so solve kernels of different streams run one at a time
-// (each needs the whole device resident for its grid barrier); the other kernels still overlap.
-struct DeviceOrder {
-    std::mutex mu;
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    int next = 0;
-    bool any = false;
-};
-std::map<int, DeviceOrder*> g_order;
-
-DeviceOrder* device_order(int dev) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_order.find(dev);
-    if (it != g_order.end()) return it->second;
-    DeviceOrder* d = new DeviceOrder();
-    g_order[dev] = d;
-    return d;
-}
-
 int hip_fail(hipError_t e) {
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return EIK_ENOMEM;
     return EIK_EHIP;
-}
-
-Workspace* get_workspace(hipStream_t stream, int* rc) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) { *rc = hip_fail(e); return nullptr; }
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto key = std::make_pair(dev, stream);
-    auto it = g_ws.find(key);
-    if (it != g_ws.end()) return it->second;
-    Workspace* w = new Workspace();
-    w->device = dev;
-    e = hipEventCreateWithFlags(&w->staged, hipEventDisableTiming);
-    if (e != hipSuccess) { delete w; *rc = hip_fail(e); return nullptr; }
-    g_ws[key] = w;
-    return w;
-}
-
-// Grows a device buffer; waits for the stream first because the old buffer may be in use.
-int ensure_device(void** p, size_t* have, size_t need, hipStream_t stream) {
-    if (*have >= need && *p) return EIK_OK;
-    hipError_t e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e);
-    if (*p) { (void)hipFree(*p); *p = nullptr; *have = 0; }
-    e = hipMalloc(p, need);
-    if (e != hipSuccess) { *p = nullptr; return hip_fail(e); }
-    *have = need;
-    return EIK_OK;
-}
-
-int ensure_host(Workspace* w, size_t need) {
-    if (w->src_host_bytes >= need && w->src_host) return EIK_OK;
-    if (w->src_host) {
-        (void)hipEventSynchronize(w->staged);
-        (void)hipHostFree(w->src_host);
-        w->src_host = nullptr;
-        w->src_host_bytes = 0;
-    }
-    hipError_t e = hipHostMalloc(&w->src_host, need, hipHostMallocDefault);
-    if (e != hipSuccess) { w->src_host = nullptr; return hip_fail(e); }
-    w->src_host_bytes = need;
-    return EIK_OK;
 }
 
 bool valid_dims(const int64_t* dims) {
@@ -155,7 +42,476 @@ bool valid_dims(const int64_t* dims) {
     return m * dims[2] < (int64_t(1) << 31);
 }
 
+// Cells and array sizes of one grid.
+struct GridSize {
+    int ncx = 0, ncy = 0, ncz = 0;
+    int64_t ncell = 0;
+    size_t u_bytes = 0, f_bytes = 0, faces_bytes = 0;
+    size_t bytes() const { return align_up(u_bytes) + align_up(f_bytes) + align_up(faces_bytes); }
+};
+
+bool grid_size(const int64_t dims[3], int cell, int f_dtype, GridSize* g) {
+    const int64_t r = cell;
+    g->ncx = (int)((dims[0] + r - 1) / r);
+    g->ncy = (int)((dims[1] + r - 1) / r);
+    g->ncz = (int)((dims[2] + r - 1) / r);
+    g->ncell = (int64_t)g->ncx * g->ncy * g->ncz;
+    if (g->ncell * r * r * r >= (int64_t(1) << 31)) return false;
+    const size_t n = (size_t)g->ncell, r3 = (size_t)(r * r * r), r2 = (size_t)(r * r);
+    g->u_bytes = n * r3 * 8;
+    g->f_bytes = n * r3 * (f_dtype == EIK_F32 ? 4 : 8);
+    g->faces_bytes = n * 6 * r2 * 8;
+    return true;
+}
+
+// Shared part of a workspace: control area, slot table, per-slot status and counts, and the
+// global per-cell arrays for `cells` cells.
+struct CommonLayout {
+    size_t off_small = 0, off_slots = 0, off_slot_status = 0, off_counts = 0, off_key = 0,
+           off_flags = 0, off_list = 0, off_cell_slot = 0, total = 0;
+};
+
+CommonLayout common_layout(int64_t cells, int slots) {
+    CommonLayout L;
+    size_t o = 0;
+    const size_t n = (size_t)std::max<int64_t>(cells, 1), ns = (size_t)std::max(slots, 1);
+    L.off_small = o; o = align_up(o + eik::kSmallBytes);
+    L.off_slots = o; o = align_up(o + ns * sizeof(Slot));
+    L.off_slot_status = o; o = align_up(o + ns * sizeof(int));
+    L.off_counts = o; o = align_up(o + ns * sizeof(int));
+    L.off_key = o; o = align_up(o + 2 * n * 8);
+    L.off_flags = o; o = align_up(o + 2 * n * 4);
+    L.off_list = o; o = align_up(o + 2 * n * 4);
+    L.off_cell_slot = o; o = align_up(o + n * 4);
+    L.total = o;
+    return L;
+}
+
+// Fills the launch parameters that point into a workspace.
+void bind_common(SolveParams* P, unsigned char* base, const CommonLayout& L, int64_t cells) {
+    P->slots = (const Slot*)(base + L.off_slots);
+    P->cell_slot = (const int*)(base + L.off_cell_slot);
+    P->key[0] = (uint64_t*)(base + L.off_key);
+    P->key[1] = P->key[0] + cells;
+    P->flags[0] = (uint32_t*)(base + L.off_flags);
+    P->flags[1] = P->flags[0] + cells;
+    P->list[0] = (int32_t*)(base + L.off_list);
+    P->list[1] = P->list[0] + cells;
+    P->ctl = (eik::RoundCtl*)(base + L.off_small + kSmallCtl);
+    P->bar = (uint32_t*)(base + L.off_small + kSmallBar);
+    P->status = (int*)(base + L.off_small + kSmallStatus);
+    P->stats = (unsigned long long*)(base + L.off_small + kSmallStats);
+    P->next_round = (int64_t*)(base + L.off_small + kSmallNextRound);
+}
+
+// Options common to single solves, batches and servers.
+int parse_options(const eik_options* options, int cell, eik_options* opt, SolveParams* P) {
+    std::memset(opt, 0, sizeof(*opt));
+    if (options) *opt = *options;
+    if (opt->mode != EIK_MODE_FP64) return EIK_EINVAL;
+    if (std::isnan(opt->delta) || opt->max_rounds < 0 || opt->max_sweeps < 0 || opt->workers < 0)
+        return EIK_EINVAL;
+    if (opt->round_log_len < 0 || (opt->round_log_len > 0 && !opt->round_log)) return EIK_EINVAL;
+    if (opt->inner < 0 || opt->inner > EIK_INNER_DUAL) return EIK_EINVAL;
+    std::memset(P, 0, sizeof(*P));
+    P->max_rounds = opt->max_rounds > 0 ? opt->max_rounds : (int64_t(1) << 20);
+    P->max_sweeps = opt->max_sweeps > 0 ? opt->max_sweeps : 512;
+    // default in-cell solver: sweeps at r = 8, the list relaxation at r = 4 (measured fastest)
+    const int inner = opt->inner ? opt->inner : (cell == 8 ? EIK_INNER_SWEEP : EIK_INNER_LIST);
+    P->inner = inner == EIK_INNER_SWEEP ? 0 : (inner == EIK_INNER_LIST ? 1 : 2);
+    P->delta = opt->delta > 0.0 ? opt->delta : 0.0;
+    P->shuffle = opt->shuffle;
+    P->watchdog_polls = 1ull << 23;  // several seconds of polling
+    P->round_log = opt->round_log;
+    P->round_log_len = opt->round_log ? opt->round_log_len : 0;
+    return EIK_OK;
+}
+
+// Synchronous validation of one problem (host-side sources are checked here).
+int validate_problem(const eik_problem& pb, int f_dtype) {
+    if (!valid_dims(pb.dims) || !pb.F || !pb.u_out) return EIK_EINVAL;
+    if (!(pb.h > 0.0) || !std::isfinite(pb.h)) return EIK_EINVAL;
+    if (!(pb.tol >= 0.0) || !std::isfinite(pb.tol)) return EIK_EINVAL;
+    if (f_dtype != EIK_F32 && f_dtype != EIK_F64) return EIK_EINVAL;
+    const eik_sources& src = pb.sources;
+    if (src.n < 0 || (src.n > 0 && (!src.idx3 || !src.q))) return EIK_EINVAL;
+    if (src.n > (int64_t(1) << 24)) return EIK_EINVAL;
+    if (!src.on_device) {
+        for (int64_t n = 0; n < src.n; ++n) {
+            const int64_t* p = src.idx3 + 3 * n;
+            for (int a = 0; a < 3; ++a)
+                if (p[a] < 0 || p[a] >= pb.dims[a]) return EIK_EINVAL;
+            const double qv = src.q[n];
+            if (!(qv >= 0.0) || !std::isfinite(qv)) return EIK_EINVAL;
+        }
+    }
+    return EIK_OK;
+}
+
+Slot make_slot(const eik_problem& pb, const GridSize& g, int cell_base, unsigned char* mem,
+               int* status_dev) {
+    Slot S;
+    std::memset(&S, 0, sizeof(S));
+    S.nx = (int)pb.dims[0];
+    S.ny = (int)pb.dims[1];
+    S.nz = (int)pb.dims[2];
+    S.ncx = g.ncx;
+    S.ncy = g.ncy;
+    S.ncz = g.ncz;
+    S.cell_base = cell_base;
+    S.ncell = (int)g.ncell;
+    S.h = pb.h;
+    S.tol = pb.tol;
+    S.u = (double*)mem;
+    S.f = mem + align_up(g.u_bytes);
+    S.faces = (double*)(mem + align_up(g.u_bytes) + align_up(g.f_bytes));
+    S.status = status_dev;
+    return S;
+}
+
+// Pinned staging of host-side data (sources, slot tables); one buffer, reused after its last
+// copy finished.
+struct Staging {
+    void* host = nullptr;
+    size_t host_bytes = 0;
+    void* dev = nullptr;
+    size_t dev_bytes = 0;
+    hipEvent_t done = nullptr;
+    bool recorded = false;
+
+    int reserve(size_t bytes, hipStream_t stream) {
+        hipError_t e;
+        if (!done && (e = hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e);
+        if (recorded && (e = hipEventSynchronize(done)) != hipSuccess) return hip_fail(e);
+        if (host_bytes < bytes) {
+            if (host) (void)hipHostFree(host);
+            host = nullptr;
+            host_bytes = 0;
+            if ((e = hipHostMalloc(&host, bytes, hipHostMallocDefault)) != hipSuccess)
+                return hip_fail(e);
+            host_bytes = bytes;
+        }
+        if (dev_bytes < bytes) {
+            if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e);
+            if (dev) (void)hipFree(dev);
+            dev = nullptr;
+            dev_bytes = 0;
+            if ((e = hipMalloc(&dev, bytes)) != hipSuccess) return hip_fail(e);
+            dev_bytes = bytes;
+        }
+        return EIK_OK;
+    }
+    void release() {
+        if (done) {
+            if (recorded) (void)hipEventSynchronize(done);
+            (void)hipEventDestroy(done);
+        }
+        if (host) (void)hipHostFree(host);
+        if (dev) (void)hipFree(dev);
+        *this = Staging();
+    }
+};
+
+struct SourceRefs {
+    const int64_t* idx3;
+    const double* q;
+};
+
+// Copies `extra` (a slot table) and the host-side sources of a set of problems to the device
+// through one pinned buffer; returns device pointers per problem and the table's offset.
+int stage_sources(Staging& st, const std::vector<const eik_problem*>& pbs,
+                  std::vector<SourceRefs>* refs, const void* extra, size_t extra_bytes,
+                  hipStream_t stream) {
+    size_t bytes = align_up(extra_bytes);
+    for (const eik_problem* pb : pbs)
+        if (!pb->sources.on_device) bytes += align_up((size_t)pb->sources.n * 32);
+    refs->assign(pbs.size(), SourceRefs{nullptr, nullptr});
+    if (bytes == 0) return EIK_OK;
+    int rc = st.reserve(bytes, stream);
+    if (rc != EIK_OK) return rc;
+    unsigned char* h = (unsigned char*)st.host;
+    unsigned char* d = (unsigned char*)st.dev;
+    size_t o = 0;
+    if (extra_bytes) {
+        std::memcpy(h, extra, extra_bytes);
+        o = align_up(extra_bytes);
+    }
+    for (size_t i = 0; i < pbs.size(); ++i) {
+        const eik_sources& s = pbs[i]->sources;
+        if (s.on_device) {
+            (*refs)[i] = SourceRefs{s.idx3, s.q};
+            continue;
+        }
+        if (s.n == 0) continue;
+        std::memcpy(h + o, s.idx3, (size_t)s.n * 24);
+        std::memcpy(h + o + (size_t)s.n * 24, s.q, (size_t)s.n * 8);
+        (*refs)[i] = SourceRefs{(const int64_t*)(d + o), (const double*)(d + o + (size_t)s.n * 24)};
+        o += align_up((size_t)s.n * 32);
+    }
+    hipError_t e = hipMemcpyAsync(d, h, o, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipEventRecord(st.done, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    st.recorded = true;
+    return EIK_OK;
+}
+
+// Per device: the event recorded after the most recently enqueued persistent solve kernel.
+// Each new solve kernel waits for it, so solve kernels of different streams run one at a time
+// (a grid barrier needs its whole launch resident); the other kernels still overlap.
+struct DeviceOrder {
+    std::mutex mu;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int next = 0;
+    bool any = false;
+};
+std::mutex g_mu;
+std::map<int, DeviceOrder*> g_order;
+
+DeviceOrder* device_order(int dev) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_order.find(dev);
+    if (it != g_order.end()) return it->second;
+    DeviceOrder* d = new DeviceOrder();
+    g_order[dev] = d;
+    return d;
+}
+
+// Launches the persistent solve kernel for rounds [P.round_begin, P.round_end), ordered after
+// every earlier solve kernel of the device.
+int ordered_solve(int dev, const SolveParams& P, int cell, int f_dtype, hipStream_t stream,
+                  int workers) {
+    DeviceOrder* dord = device_order(dev);
+    std::lock_guard<std::mutex> lk(dord->mu);
+    for (auto& ev : dord->ev) {
+        if (!ev) {
+            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+    }
+    hipError_t e;
+    if (dord->any && (e = hipStreamWaitEvent(stream, dord->ev[dord->next ^ 1], 0)) != hipSuccess)
+        return hip_fail(e);
+    int used = 0;
+    e = eik::launch_solve_rounds(P, cell, f_dtype, stream, workers, &used);
+    if (e != hipSuccess) return hip_fail(e);
+    if ((e = hipEventRecord(dord->ev[dord->next], stream)) != hipSuccess) return hip_fail(e);
+    dord->any = true;
+    dord->next ^= 1;
+    return EIK_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Per-stream workspace of eik_solve / eik_solve_batch.
+
+struct Workspace {
+    int device = -1;
+    void* base = nullptr;
+    size_t bytes = 0;
+    Staging staging;
+    bool used = false;
+    int64_t cells = 0;
+    int nslots = 0;
+    CommonLayout layout;
+    std::mutex mu;  // serialises enqueues that share this workspace
+    static constexpr int kRing = 256;
+    std::vector<hipEvent_t> ring;  // 4 events per timed solve
+    int64_t timed = 0;
+};
+
+std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+
+Workspace* get_workspace(hipStream_t stream, int* rc) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { *rc = hip_fail(e); return nullptr; }
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, stream);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) return it->second;
+    Workspace* w = new Workspace();
+    w->device = dev;
+    g_ws[key] = w;
+    return w;
+}
+
+Workspace* find_workspace(hipStream_t stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ws.find(std::make_pair(dev, stream));
+    return it == g_ws.end() ? nullptr : it->second;
+}
+
+int ensure_device(void** p, size_t* have, size_t need, hipStream_t stream) {
+    if (*have >= need && *p) return EIK_OK;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e);
+    if (*p) { (void)hipFree(*p); *p = nullptr; *have = 0; }
+    e = hipMalloc(p, need);
+    if (e != hipSuccess) { *p = nullptr; return hip_fail(e); }
+    *have = need;
+    return EIK_OK;
+}
+
+int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipStream_t stream,
+                     const eik_options* options) {
+    if (n < 1 || n > (1 << 20) || !pbs) return EIK_EINVAL;
+    if (cell != 4 && cell != 8) return EIK_EINVAL;
+    eik_options opt;
+    SolveParams P;
+    int rc = parse_options(options, cell, &opt, &P);
+    if (rc != EIK_OK) return rc;
+    std::vector<GridSize> gs((size_t)n);
+    int64_t cells = 0;
+    size_t grid_bytes = 0;
+    int64_t nsrc_total = 0;
+    for (int i = 0; i < n; ++i) {
+        if ((rc = validate_problem(pbs[i], f_dtype)) != EIK_OK) return rc;
+        if (!grid_size(pbs[i].dims, cell, f_dtype, &gs[i])) return EIK_EINVAL;
+        cells += gs[i].ncell;
+        grid_bytes += gs[i].bytes();
+        nsrc_total += pbs[i].sources.n;
+    }
+    if (cells >= (int64_t(1) << 31)) return EIK_EINVAL;
+    const CommonLayout L = common_layout(cells, n);
+
+    Workspace* w = get_workspace(stream, &rc);
+    if (!w) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    rc = ensure_device(&w->base, &w->bytes, L.total + grid_bytes, stream);
+    if (rc != EIK_OK) return rc;
+    unsigned char* base = (unsigned char*)w->base;
+    bind_common(&P, base, L, cells);
+    int* slot_status = (int*)(base + L.off_slot_status);
+
+    // Slot table, built on the host and copied with the sources through one pinned buffer.
+    std::vector<Slot> slots((size_t)n);
+    size_t off = L.total;
+    int64_t cell_base = 0;
+    for (int i = 0; i < n; ++i) {
+        slots[i] = make_slot(pbs[i], gs[i], (int)cell_base, base + off, slot_status + i);
+        off += gs[i].bytes();
+        cell_base += gs[i].ncell;
+    }
+    std::vector<const eik_problem*> ptrs((size_t)n);
+    for (int i = 0; i < n; ++i) ptrs[i] = &pbs[i];
+    std::vector<SourceRefs> refs;
+    rc = stage_sources(w->staging, ptrs, &refs, slots.data(), slots.size() * sizeof(Slot), stream);
+    if (rc != EIK_OK) return rc;
+    hipError_t e = hipMemcpyAsync(base + L.off_slots, w->staging.dev, slots.size() * sizeof(Slot),
+                                  hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e);
+
+    hipEvent_t* ev = nullptr;
+    if (opt.timing) {
+        if (w->ring.empty()) {
+            w->ring.assign(4 * Workspace::kRing, nullptr);
+            for (auto& x : w->ring)
+                if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(e);
+        }
+        ev = &w->ring[4 * (w->timed % Workspace::kRing)];
+        w->timed++;
+    }
+    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return hip_fail(e);
+    if ((e = eik::launch_init_global(P, stream)) != hipSuccess) return hip_fail(e);
+    for (int i = 0; i < n; ++i) {
+        e = eik::launch_init_slot(P, slots[i], i, cell, f_dtype, pbs[i].F, stream);
+        if (e != hipSuccess) return hip_fail(e);
+        e = eik::launch_seed(P, slots[i], cell, f_dtype, 0, pbs[i].sources.n, refs[i].idx3,
+                             refs[i].q, stream);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return hip_fail(e);
+    if (nsrc_total > 0) {
+        P.round_begin = 0;
+        P.round_end = P.max_rounds;
+        rc = ordered_solve(w->device, P, cell, f_dtype, stream, opt.workers);
+        if (rc != EIK_OK) return rc;
+    }
+    if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return hip_fail(e);
+    for (int i = 0; i < n; ++i)
+        if ((e = eik::launch_output(slots[i], cell, pbs[i].u_out, stream)) != hipSuccess)
+            return hip_fail(e);
+    if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return hip_fail(e);
+    w->used = true;
+    w->cells = cells;
+    w->nslots = n;
+    w->layout = L;
+    return EIK_OK;
+}
+
+template <typename T>
+bool range_alloc(std::vector<std::pair<T, T>>& fl, T size, T align, T* out) {
+    for (size_t i = 0; i < fl.size(); ++i) {
+        const T start = (fl[i].first + align - 1) / align * align;
+        const T end = fl[i].first + fl[i].second;
+        if (start + size <= end) {
+            const T pre = start - fl[i].first, post = end - (start + size);
+            const T f0 = fl[i].first;
+            fl.erase(fl.begin() + (long)i);
+            if (post) fl.insert(fl.begin() + (long)i, {start + size, post});
+            if (pre) fl.insert(fl.begin() + (long)i, {f0, pre});
+            *out = start;
+            return true;
+        }
+    }
+    return false;
+}
+
+template <typename T>
+void range_free(std::vector<std::pair<T, T>>& fl, T off, T size) {
+    fl.push_back({off, size});
+    std::sort(fl.begin(), fl.end());
+    std::vector<std::pair<T, T>> merged;
+    for (auto& r : fl) {
+        if (!merged.empty() && merged.back().first + merged.back().second == r.first)
+            merged.back().second += r.second;
+        else
+            merged.push_back(r);
+    }
+    fl.swap(merged);
+}
+
 }  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Server state.
+
+struct eik_server {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    int cell = 8, f_dtype = EIK_F32;
+    eik_options opt;
+    SolveParams P;
+    CommonLayout layout;
+    void* base = nullptr;  // common part
+    void* pool = nullptr;  // grids' arrays
+    size_t pool_bytes = 0;
+    int64_t max_cells = 0;
+    int max_problems = 0;
+    Staging staging;
+    struct Problem {
+        int64_t ticket = -1;
+        bool active = false;   // admitted and not yet retired
+        bool started = false;  // seeded into a round
+        eik_problem pb;
+        GridSize g;
+        Slot slot;
+        size_t pool_off = 0;
+    };
+    std::vector<Problem> problems;                       // indexed by slot
+    std::vector<std::pair<size_t, size_t>> free_pool;    // (offset, size), sorted
+    std::vector<std::pair<int64_t, int64_t>> free_cells;
+    std::vector<int> fresh;                              // slots admitted since the last step
+    std::vector<std::pair<int64_t, int>> finished;       // (ticket, status) not yet polled
+    int64_t next_ticket = 0;
+    int64_t next_round = 0;
+    int* host_words = nullptr;  // pinned: counts, statuses, next round, launch status
+    size_t pool_used = 0;
+    int64_t cells_used = 0;
+};
 
 extern "C" {
 
@@ -167,162 +523,47 @@ const char* eik_strerror(int code) {
         case EIK_EHIP: return "EIK_EHIP: HIP runtime error";
         case EIK_ENOCONV: return "EIK_ENOCONV: round cap reached before convergence";
         case EIK_ECANCELLED: return "EIK_ECANCELLED: stopped by the device watchdog";
+        case EIK_EBUSY: return "EIK_EBUSY: no room on the device now";
         default: return "EIK: unknown status";
     }
 }
 
-const char* eik_version(void) { return "eik-mi355x 0.1 (gfx950)"; }
+const char* eik_version(void) { return "eik-mi355x 0.2 (gfx950)"; }
+
+int eik_problem_bytes(const int64_t dims[3], int cell, int f_dtype, size_t* bytes) {
+    if (!bytes || !valid_dims(dims) || (cell != 4 && cell != 8) ||
+        (f_dtype != EIK_F32 && f_dtype != EIK_F64))
+        return EIK_EINVAL;
+    GridSize g;
+    if (!grid_size(dims, cell, f_dtype, &g)) return EIK_EINVAL;
+    *bytes = g.bytes();
+    return EIK_OK;
+}
 
 int eik_query_workspace(const int64_t dims[3], int cell, int f_dtype, int mode, size_t* bytes) {
-    if (!bytes || !valid_dims(dims) || (cell != 4 && cell != 8) ||
-        (f_dtype != EIK_F32 && f_dtype != EIK_F64) || mode != EIK_MODE_FP64)
-        return EIK_EINVAL;
-    Layout L;
-    if (!make_layout(dims, cell, f_dtype, &L)) return EIK_EINVAL;
-    *bytes = L.total;
+    if (mode != EIK_MODE_FP64) return EIK_EINVAL;
+    size_t grid = 0;
+    int rc = eik_problem_bytes(dims, cell, f_dtype, &grid);
+    if (rc != EIK_OK) return rc;
+    GridSize g;
+    grid_size(dims, cell, f_dtype, &g);
+    *bytes = common_layout(g.ncell, 1).total + grid;
     return EIK_OK;
 }
 
 int eik_solve_ex(const int64_t dims[3], double h, const void* F, int f_dtype,
                  const eik_sources* sources, double* u_out, int cell, double tol,
                  hipStream_t stream, const eik_options* options) {
-    eik_options opt;
-    std::memset(&opt, 0, sizeof(opt));
-    if (options) opt = *options;
-    // ---- synchronous validation: nothing is enqueued on failure
-    if (!valid_dims(dims) || !F || !u_out || !sources) return EIK_EINVAL;
-    if (!(h > 0.0) || !std::isfinite(h)) return EIK_EINVAL;
-    if (f_dtype != EIK_F32 && f_dtype != EIK_F64) return EIK_EINVAL;
-    if (cell != 4 && cell != 8) return EIK_EINVAL;
-    if (!(tol >= 0.0) || !std::isfinite(tol)) return EIK_EINVAL;
-    if (opt.mode != EIK_MODE_FP64) return EIK_EINVAL;
-    if (std::isnan(opt.delta) || opt.max_rounds < 0 || opt.max_sweeps < 0 || opt.workers < 0)
-        return EIK_EINVAL;
-    if (opt.round_log_len < 0 || (opt.round_log_len > 0 && !opt.round_log)) return EIK_EINVAL;
-    if (opt.inner < 0 || opt.inner > EIK_INNER_DUAL) return EIK_EINVAL;
-    const int64_t nsrc = sources->n;
-    if (nsrc < 0 || (nsrc > 0 && (!sources->idx3 || !sources->q))) return EIK_EINVAL;
-    if (nsrc > (int64_t(1) << 24)) return EIK_EINVAL;
-    if (!sources->on_device) {
-        for (int64_t n = 0; n < nsrc; ++n) {
-            const int64_t* p = sources->idx3 + 3 * n;
-            for (int a = 0; a < 3; ++a)
-                if (p[a] < 0 || p[a] >= dims[a]) return EIK_EINVAL;
-            const double qv = sources->q[n];
-            if (!(qv >= 0.0) || !std::isfinite(qv)) return EIK_EINVAL;
-        }
-    }
-    Layout L;
-    if (!make_layout(dims, cell, f_dtype, &L)) return EIK_EINVAL;
-
-    int rc = EIK_OK;
-    Workspace* w = get_workspace(stream, &rc);
-    if (!w) return rc;
-    std::lock_guard<std::mutex> lk(w->mu);
-    rc = ensure_device(&w->base, &w->bytes, L.total, stream);
-    if (rc != EIK_OK) return rc;
-
-    // ---- sources: host lists are staged through pinned memory into the workspace
-    const int64_t* idx_dev = nullptr;
-    const double* q_dev = nullptr;
-    if (nsrc > 0) {
-        if (sources->on_device) {
-            idx_dev = sources->idx3;
-            q_dev = sources->q;
-        } else {
-            const size_t sb = (size_t)nsrc * 32;
-            rc = ensure_device(&w->src_dev, &w->src_bytes, sb, stream);
-            if (rc != EIK_OK) return rc;
-            rc = ensure_host(w, sb);
-            if (rc != EIK_OK) return rc;
-            hipError_t e = hipEventSynchronize(w->staged);
-            if (e != hipSuccess) return hip_fail(e);
-            unsigned char* hb = (unsigned char*)w->src_host;
-            std::memcpy(hb, sources->idx3, (size_t)nsrc * 24);
-            std::memcpy(hb + (size_t)nsrc * 24, sources->q, (size_t)nsrc * 8);
-            e = hipMemcpyAsync(w->src_dev, hb, sb, hipMemcpyHostToDevice, stream);
-            if (e != hipSuccess) return hip_fail(e);
-            e = hipEventRecord(w->staged, stream);
-            if (e != hipSuccess) return hip_fail(e);
-            idx_dev = (const int64_t*)w->src_dev;
-            q_dev = (const double*)((unsigned char*)w->src_dev + (size_t)nsrc * 24);
-        }
-    }
-
-    // ---- parameters
-    unsigned char* base = (unsigned char*)w->base;
-    SolveParams P;
-    std::memset(&P, 0, sizeof(P));
-    P.nx = (int)dims[0];
-    P.ny = (int)dims[1];
-    P.nz = (int)dims[2];
-    P.ncx = L.ncx;
-    P.ncy = L.ncy;
-    P.ncz = L.ncz;
-    P.ncell = (int)L.ncell;
-    P.max_rounds = opt.max_rounds > 0 ? (int)std::min<int64_t>(opt.max_rounds, 1 << 30) : (1 << 20);
-    P.max_sweeps = opt.max_sweeps > 0 ? opt.max_sweeps : 512;
-    // default in-cell solver: sweeps at r = 8, the list relaxation at r = 4 (measured fastest)
-    const int inner = opt.inner ? opt.inner : (cell == 8 ? EIK_INNER_SWEEP : EIK_INNER_LIST);
-    P.inner = inner == EIK_INNER_SWEEP ? 0 : (inner == EIK_INNER_LIST ? 1 : 2);
-    P.h = h;
-    P.tol = tol;
-    P.delta = opt.delta > 0.0 ? opt.delta : 0.0;
-    P.shuffle = opt.shuffle;
-    P.watchdog_polls = 1ull << 23;  // several seconds of polling
-    P.u = (double*)(base + L.off_u);
-    P.fw = base + L.off_f;
-    P.f = P.fw;
-    P.faces = (double*)(base + L.off_faces);
-    P.key[0] = (uint64_t*)(base + L.off_key);
-    P.key[1] = P.key[0] + L.ncell;
-    P.flags[0] = (uint32_t*)(base + L.off_flags);
-    P.flags[1] = P.flags[0] + L.ncell;
-    P.list[0] = (int32_t*)(base + L.off_list);
-    P.list[1] = P.list[0] + L.ncell;
-    P.ctl = (eik::RoundCtl*)(base + L.off_small + kSmallCtl);
-    P.bar = (uint32_t*)(base + L.off_small + kSmallBar);
-    P.status = (int*)(base + L.off_small + kSmallStatus);
-    P.stats = (unsigned long long*)(base + L.off_small + kSmallStats);
-    P.round_log = opt.round_log;
-    P.round_log_len = opt.round_log ? opt.round_log_len : 0;
-
-    int used = 0;
-    const eik::LaunchEvents* evp = nullptr;
-    if (opt.timing) {
-        if (w->ring.empty()) {
-            w->ring.resize(Workspace::kRing);
-            for (auto& q4 : w->ring)
-                for (auto& ev : q4.ev) {
-                    hipError_t ee = hipEventCreate(&ev);
-                    if (ee != hipSuccess) return hip_fail(ee);
-                }
-        }
-        evp = &w->ring[w->timed % Workspace::kRing];
-        w->timed++;
-    }
-    DeviceOrder* dord = device_order(w->device);
-    std::lock_guard<std::mutex> olk(dord->mu);
-    for (auto& ev : dord->ev) {
-        if (!ev) {
-            hipError_t ee = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-            if (ee != hipSuccess) return hip_fail(ee);
-        }
-    }
-    // Alternate two events: the new launch waits on the previous one and records the other.
-    eik::SolveOrder order;
-    order.after = dord->any ? dord->ev[dord->next ^ 1] : nullptr;
-    order.done = dord->ev[dord->next];
-    hipError_t e = eik::launch_solve(P, cell, f_dtype, F, nsrc, idx_dev, q_dev, u_out, stream,
-                                     opt.workers, &used, evp, &order);
-    if (e == hipSuccess && nsrc > 0) {
-        dord->any = true;
-        dord->next ^= 1;
-    }
-    if (e != hipSuccess) return hip_fail(e);
-    w->used = true;
-    w->cells = L.ncell;
-    return EIK_OK;
+    if (!dims || !sources) return EIK_EINVAL;
+    eik_problem pb;
+    std::memset(&pb, 0, sizeof(pb));
+    for (int a = 0; a < 3; ++a) pb.dims[a] = dims[a];
+    pb.h = h;
+    pb.F = F;
+    pb.sources = *sources;
+    pb.u_out = u_out;
+    pb.tol = tol;
+    return solve_batch_impl(1, &pb, f_dtype, cell, stream, options);
 }
 
 int eik_solve(const int64_t dims[3], double h, const void* F, int f_dtype,
@@ -331,25 +572,33 @@ int eik_solve(const int64_t dims[3], double h, const void* F, int f_dtype,
     return eik_solve_ex(dims, h, F, f_dtype, sources, u_out, cell, tol, stream, nullptr);
 }
 
+int eik_solve_batch(int n, const eik_problem* problems, int f_dtype, int cell, hipStream_t stream,
+                    const eik_options* options) {
+    return solve_batch_impl(n, problems, f_dtype, cell, stream, options);
+}
+
 int eik_stream_status(hipStream_t stream, eik_stats* stats) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return EIK_EHIP;
-    Workspace* w = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_ws.find(std::make_pair(dev, stream));
-        if (it != g_ws.end()) w = it->second;
-    }
+    Workspace* w = find_workspace(stream);
     if (!w || !w->used) return EIK_EINVAL;
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e);
     unsigned char* base = (unsigned char*)w->base;
     int status = 0;
     unsigned long long st[eik::ST_COUNT];
-    e = hipMemcpy(&status, base + kSmallStatus, sizeof(int), hipMemcpyDeviceToHost);
+    e = hipMemcpy(&status, base + w->layout.off_small + kSmallStatus, sizeof(int),
+                  hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e);
-    e = hipMemcpy(st, base + kSmallStats, sizeof(st), hipMemcpyDeviceToHost);
+    e = hipMemcpy(st, base + w->layout.off_small + kSmallStats, sizeof(st), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e);
+    if (status == 0) {
+        // otherwise the first failing grid's status
+        std::vector<int> ss((size_t)w->nslots);
+        e = hipMemcpy(ss.data(), base + w->layout.off_slot_status, ss.size() * sizeof(int),
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e);
+        for (int v : ss)
+            if (v != 0) { status = v; break; }
+    }
     if (stats) {
         stats->rounds = (int64_t)st[eik::ST_ROUNDS];
         stats->visits = (int64_t)st[eik::ST_VISITS];
@@ -369,30 +618,40 @@ int eik_stream_status(hipStream_t stream, eik_stats* stats) {
     return status;
 }
 
+int eik_batch_status(hipStream_t stream, int n, int* status) {
+    Workspace* w = find_workspace(stream);
+    if (!w || !w->used || n < 0 || (n > 0 && !status)) return EIK_EINVAL;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e);
+    int launch = 0;
+    unsigned char* base = (unsigned char*)w->base;
+    e = hipMemcpy(&launch, base + w->layout.off_small + kSmallStatus, sizeof(int),
+                  hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    n = std::min(n, w->nslots);
+    e = hipMemcpy(status, base + w->layout.off_slot_status, (size_t)n * sizeof(int),
+                  hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    for (int i = 0; i < n; ++i)
+        if (status[i] == 0) status[i] = launch;
+    return n;
+}
+
 int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_ms) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return EIK_EHIP;
     if (n < 0) return EIK_EINVAL;
-    Workspace* w = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_ws.find(std::make_pair(dev, stream));
-        if (it != g_ws.end()) w = it->second;
-    }
+    Workspace* w = find_workspace(stream);
     if (!w || w->timed == 0) return 0;
     std::lock_guard<std::mutex> lk(w->mu);
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e);
-    int64_t have = std::min<int64_t>(w->timed, Workspace::kRing);
+    const int64_t have = std::min<int64_t>(w->timed, Workspace::kRing);
     if (n > have) n = (int)have;
     for (int i = 0; i < n; ++i) {
         const int64_t k = w->timed - n + i;
-        const eik::LaunchEvents& q4 = w->ring[k % Workspace::kRing];
+        hipEvent_t* q4 = &w->ring[4 * (k % Workspace::kRing)];
         float a = 0.f, b = 0.f;
-        e = hipEventElapsedTime(&a, q4.ev[1], q4.ev[2]);
-        if (e != hipSuccess) return hip_fail(e);
-        e = hipEventElapsedTime(&b, q4.ev[0], q4.ev[3]);
-        if (e != hipSuccess) return hip_fail(e);
+        if ((e = hipEventElapsedTime(&a, q4[1], q4[2])) != hipSuccess) return hip_fail(e);
+        if ((e = hipEventElapsedTime(&b, q4[0], q4[3])) != hipSuccess) return hip_fail(e);
         if (solve_ms) solve_ms[i] = a;
         if (total_ms) total_ms[i] = b;
     }
@@ -401,23 +660,218 @@ int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_
 
 void eik_release(void) {
     std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
     for (auto& kv : g_ws) {
         Workspace* w = kv.second;
-        int cur = 0;
-        (void)hipGetDevice(&cur);
         (void)hipSetDevice(w->device);
         (void)hipStreamSynchronize(kv.first.second);
-        if (w->staged) { (void)hipEventSynchronize(w->staged); (void)hipEventDestroy(w->staged); }
+        w->staging.release();
         if (w->base) (void)hipFree(w->base);
-        if (w->src_dev) (void)hipFree(w->src_dev);
-        if (w->src_host) (void)hipHostFree(w->src_host);
-        for (auto& q4 : w->ring)
-            for (auto& ev : q4.ev)
-                if (ev) (void)hipEventDestroy(ev);
-        (void)hipSetDevice(cur);
+        for (auto& x : w->ring)
+            if (x) (void)hipEventDestroy(x);
         delete w;
     }
     g_ws.clear();
+    (void)hipSetDevice(cur);
+}
+
+// ---------------------------------- server ------------------------------------------------
+
+int eik_server_create(eik_server** out, size_t pool_bytes, int64_t max_cells, int max_problems,
+                      int cell, int f_dtype, hipStream_t stream, const eik_options* options) {
+    if (!out || pool_bytes == 0 || max_cells < 1 || max_cells >= (int64_t(1) << 31) ||
+        max_problems < 1 || max_problems > (1 << 16) || (cell != 4 && cell != 8) ||
+        (f_dtype != EIK_F32 && f_dtype != EIK_F64))
+        return EIK_EINVAL;
+    eik_server* s = new eik_server();
+    int rc = parse_options(options, cell, &s->opt, &s->P);
+    if (rc != EIK_OK) { delete s; return rc; }
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) { delete s; return hip_fail(e); }
+    s->stream = stream;
+    s->cell = cell;
+    s->f_dtype = f_dtype;
+    s->max_cells = max_cells;
+    s->max_problems = max_problems;
+    s->pool_bytes = pool_bytes;
+    s->layout = common_layout(max_cells, max_problems);
+    const size_t hb = ((size_t)max_problems * 2 + 8) * sizeof(int) + 64;
+    if ((e = hipMalloc(&s->base, s->layout.total)) != hipSuccess ||
+        (e = hipMalloc(&s->pool, pool_bytes)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&s->host_words, hb, hipHostMallocDefault)) != hipSuccess) {
+        eik_server_destroy(s);
+        return hip_fail(e);
+    }
+    bind_common(&s->P, (unsigned char*)s->base, s->layout, max_cells);
+    s->problems.resize((size_t)max_problems);
+    s->free_pool.push_back({0, pool_bytes});
+    s->free_cells.push_back({0, max_cells});
+    if ((e = eik::launch_init_global(s->P, stream)) != hipSuccess) {
+        eik_server_destroy(s);
+        return hip_fail(e);
+    }
+    *out = s;
+    return EIK_OK;
+}
+
+int eik_server_submit(eik_server* s, const eik_problem* pb, int64_t* ticket) {
+    if (!s || !pb || !ticket) return EIK_EINVAL;
+    int rc = validate_problem(*pb, s->f_dtype);
+    if (rc != EIK_OK) return rc;
+    GridSize g;
+    if (!grid_size(pb->dims, s->cell, s->f_dtype, &g)) return EIK_EINVAL;
+    if (g.ncell > s->max_cells || g.bytes() > s->pool_bytes) return EIK_EINVAL;  // never fits
+    int slot = -1;
+    for (int i = 0; i < s->max_problems; ++i)
+        if (!s->problems[i].active) { slot = i; break; }
+    if (slot < 0) return EIK_EBUSY;
+    size_t poff = 0;
+    int64_t cbase = 0;
+    if (!range_alloc<size_t>(s->free_pool, g.bytes(), kAlign, &poff)) return EIK_EBUSY;
+    if (!range_alloc<int64_t>(s->free_cells, g.ncell, 1, &cbase)) {
+        range_free<size_t>(s->free_pool, poff, g.bytes());
+        return EIK_EBUSY;
+    }
+    eik_server::Problem& p = s->problems[slot];
+    p.ticket = s->next_ticket++;
+    p.active = true;
+    p.started = false;
+    p.pb = *pb;
+    p.g = g;
+    p.pool_off = poff;
+    int* slot_status = (int*)((unsigned char*)s->base + s->layout.off_slot_status) + slot;
+    p.slot = make_slot(*pb, g, (int)cbase, (unsigned char*)s->pool + poff, slot_status);
+    s->fresh.push_back(slot);
+    s->pool_used += g.bytes();
+    s->cells_used += g.ncell;
+    *ticket = p.ticket;
+    return EIK_OK;
+}
+
+int eik_server_step(eik_server* s, int64_t rounds, int* finished) {
+    if (!s || rounds < 1) return EIK_EINVAL;
+    hipStream_t st = s->stream;
+    unsigned char* base = (unsigned char*)s->base;
+    const int ns = s->max_problems;
+    hipError_t e;
+    int rc;
+    // 1. Admit: slot table, sources, init and seeding into the list of the next round.
+    if (!s->fresh.empty()) {
+        std::vector<const eik_problem*> ptrs;
+        for (int slot : s->fresh) ptrs.push_back(&s->problems[slot].pb);
+        std::vector<Slot> table((size_t)ns);
+        for (int i = 0; i < ns; ++i) table[i] = s->problems[i].slot;
+        std::vector<SourceRefs> refs;
+        rc = stage_sources(s->staging, ptrs, &refs, table.data(), table.size() * sizeof(Slot), st);
+        if (rc != EIK_OK) return rc;
+        e = hipMemcpyAsync(base + s->layout.off_slots, s->staging.dev, table.size() * sizeof(Slot),
+                           hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e);
+        for (size_t k = 0; k < s->fresh.size(); ++k) {
+            eik_server::Problem& p = s->problems[s->fresh[k]];
+            e = eik::launch_init_slot(s->P, p.slot, s->fresh[k], s->cell, s->f_dtype, p.pb.F, st);
+            if (e != hipSuccess) return hip_fail(e);
+            e = eik::launch_seed(s->P, p.slot, s->cell, s->f_dtype, s->next_round,
+                                 p.pb.sources.n, refs[k].idx3, refs[k].q, st);
+            if (e != hipSuccess) return hip_fail(e);
+            p.started = true;
+        }
+        s->fresh.clear();
+    }
+    // 2. Up to `rounds` rounds of every problem on the device, in one persistent launch.
+    SolveParams P = s->P;
+    P.round_begin = s->next_round;
+    P.round_end = s->next_round + rounds;
+    P.max_rounds = int64_t(1) << 62;
+    P.round_log_len = 0;
+    rc = ordered_solve(s->device, P, s->cell, s->f_dtype, st, s->opt.workers);
+    if (rc != EIK_OK) return rc;
+    // 3. Per problem: cells still queued, status; the round where the launch stopped.
+    int* counts_dev = (int*)(base + s->layout.off_counts);
+    e = eik::launch_slot_counts(P, counts_dev, ns, st);
+    if (e != hipSuccess) return hip_fail(e);
+    int* hw = s->host_words;
+    if ((e = hipMemcpyAsync(hw, counts_dev, (size_t)ns * sizeof(int), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(hw + ns, base + s->layout.off_slot_status, (size_t)ns * sizeof(int),
+                            hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(hw + 2 * ns, base + s->layout.off_small + kSmallNextRound,
+                            sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(hw + 2 * ns + 2, base + s->layout.off_small + kSmallStatus,
+                            sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hip_fail(e);
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e);
+    int64_t nr;
+    std::memcpy(&nr, hw + 2 * ns, sizeof(nr));
+    s->next_round = nr;
+    const int launch_status = hw[2 * ns + 2];
+    // 4. Retire converged problems: write their results, free their space.
+    int nfin = 0;
+    std::vector<int> done;
+    for (int i = 0; i < ns; ++i) {
+        eik_server::Problem& p = s->problems[i];
+        if (!p.active || !p.started) continue;
+        if (hw[i] != 0 && launch_status == 0) continue;
+        if ((e = eik::launch_output(p.slot, s->cell, p.pb.u_out, st)) != hipSuccess)
+            return hip_fail(e);
+        const int status = hw[ns + i] != 0 ? hw[ns + i] : launch_status;
+        s->finished.push_back({p.ticket, status});
+        done.push_back(i);
+        ++nfin;
+    }
+    if (!done.empty()) {
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e);
+        for (int i : done) {
+            eik_server::Problem& p = s->problems[i];
+            range_free<size_t>(s->free_pool, p.pool_off, p.g.bytes());
+            range_free<int64_t>(s->free_cells, p.slot.cell_base, p.g.ncell);
+            s->pool_used -= p.g.bytes();
+            s->cells_used -= p.g.ncell;
+            p = eik_server::Problem();
+        }
+    }
+    if (launch_status != 0) {
+        // The launch was stopped (watchdog): every problem on the device was retired above with
+        // that status; the next step starts from a clean control state.
+        if ((e = eik::launch_init_global(s->P, st)) != hipSuccess) return hip_fail(e);
+        s->next_round = 0;
+    }
+    if (finished) *finished = nfin;
+    return launch_status;
+}
+
+int eik_server_poll(eik_server* s, int max, int64_t* tickets, int* status, int* n_out) {
+    if (!s || max < 0 || !n_out || (max > 0 && (!tickets || !status))) return EIK_EINVAL;
+    const int n = std::min<int>(max, (int)s->finished.size());
+    for (int i = 0; i < n; ++i) {
+        tickets[i] = s->finished[i].first;
+        status[i] = s->finished[i].second;
+    }
+    s->finished.erase(s->finished.begin(), s->finished.begin() + n);
+    *n_out = n;
+    return EIK_OK;
+}
+
+int eik_server_load(eik_server* s, int* problems, int64_t* cells, size_t* pool_used) {
+    if (!s) return EIK_EINVAL;
+    int np = 0;
+    for (auto& p : s->problems) np += p.active ? 1 : 0;
+    if (problems) *problems = np;
+    if (cells) *cells = s->cells_used;
+    if (pool_used) *pool_used = s->pool_used;
+    return EIK_OK;
+}
+
+int eik_server_destroy(eik_server* s) {
+    if (!s) return EIK_EINVAL;
+    if (s->stream || s->base) (void)hipStreamSynchronize(s->stream);
+    s->staging.release();
+    if (s->host_words) (void)hipHostFree(s->host_words);
+    if (s->base) (void)hipFree(s->base);
+    if (s->pool) (void)hipFree(s->pool);
+    delete s;
+    return EIK_OK;
 }
 
 }  // extern "C"

@@ -48,52 +48,59 @@ static_assert(sizeof(RoundCtl) == 256, "RoundCtl is 256 bytes");
 constexpr size_t kSmallCtl = 0;        // 4 x RoundCtl
 constexpr size_t kSmallBar = 1024;     // barrier: arrivals at [0], generation at [64] (uint32)
 constexpr size_t kSmallStatus = 2048;  // int
+constexpr size_t kSmallNextRound = 2112;  // int64: first round of the next launch
 constexpr size_t kSmallStats = 2304;   // ST_COUNT x uint64
 constexpr size_t kSmallBytes = 4096;
 constexpr int kBarGen = 64;            // index of the generation word in the barrier array
 
-struct SolveParams {
+// One grid of a (possibly batched) solve.  Its cells occupy the global cell ids
+// [cell_base, cell_base + ncell); its arrays are its own.
+struct Slot {
     int nx, ny, nz;        // grid nodes per axis
     int ncx, ncy, ncz;     // cells per axis
+    int cell_base;         // global id of the slot's cell 0
     int ncell;             // ncx * ncy * ncz
-    int max_rounds;
+    double h, tol;
+    double* u;             // [ncell][r^3] cell-blocked values
+    void* f;               // [ncell][r^3] cell-blocked speeds (F dtype); 0 padding, <0 exit
+    double* faces;         // [ncell][6][r^2] border layers
+    int* status;           // this grid's status word (device)
+    int pad[2];
+};
+
+struct SolveParams {
     int max_sweeps;
     int inner;             // in-cell solver: 0 sweeps, 1 active-list relaxation, 2 dual sweeps
-    double h, tol, delta;
+    int64_t round_begin;   // first round of this launch
+    int64_t round_end;     // the launch stops after round round_end - 1 (end of an epoch)
+    int64_t max_rounds;    // absolute cap on rounds -> EIK_ENOCONV
+    double delta;
     uint64_t shuffle;
     uint64_t watchdog_polls;  // polls of the barrier word before a wait is abandoned
-    double* u;             // [ncell][r^3] cell-blocked values
-    void* fw;              // [ncell][r^3] cell-blocked speeds (F dtype); 0 padding, <0 exit
-    const void* f;         // same pointer, read-only view used by the sweeps
-    double* faces;         // [ncell][6][r^2] border layers
-    uint64_t* key[2];      // cell values (FP64 bit patterns, all >= +0)
+    const Slot* slots;     // slot table (device)
+    const int* cell_slot;  // [global cells] slot of each cell
+    uint64_t* key[2];      // cell values (FP64 bit patterns, all >= +0), global cell ids
     uint32_t* flags[2];
     int32_t* list[2];
     RoundCtl* ctl;         // [4] control blocks, slot = round & 3
     uint32_t* bar;         // grid barrier: bar[0] arrivals, bar[kBarGen] generation
-    int* status;           // device status word
+    int* status;           // device status word of the launch (watchdog, round cap)
     unsigned long long* stats;  // [ST_COUNT]
+    int64_t* next_round;   // written when the launch ends: the first round of the next launch
     int64_t* round_log;    // optional [2 * round_log_len]
     int64_t round_log_len;
 };
 
-// Optional events recorded around the solve kernel (ev[1], ev[2]) and the whole call
-// (ev[0], ev[3]); null entries are skipped.
-struct LaunchEvents {
-    hipEvent_t ev[4];
-};
-
-// Ordering of persistent solve kernels on one device: the launch waits for `after` (the end of
-// the previous solve kernel, any stream) and records `done` right after itself.  A grid
-// barrier needs every workgroup of its launch resident, which two such launches cannot share.
-struct SolveOrder {
-    hipEvent_t after;  // may be null
-    hipEvent_t done;
-};
-
-hipError_t launch_solve(const SolveParams& P, int cell, int f_dtype, const void* F, int64_t nsrc,
-                        const int64_t* idx3, const double* q, double* u_out, hipStream_t s,
-                        int workers, int* used, const LaunchEvents* events,
-                        const SolveOrder* order);
+// Launchers (eik_kernels.hip).  All enqueue on `s` and return the first launch error.
+hipError_t launch_init_global(const SolveParams& P, hipStream_t s);
+hipError_t launch_init_slot(const SolveParams& P, const Slot& S, int slot, int cell, int f_dtype,
+                            const void* F, hipStream_t s);
+hipError_t launch_seed(const SolveParams& P, const Slot& S, int cell, int f_dtype, int64_t round,
+                       int64_t nsrc, const int64_t* idx3, const double* q, hipStream_t s);
+hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipStream_t s,
+                               int workers, int* used);
+hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s);
+// Cells of each slot queued for the first round of the next launch (P.next_round).
+hipError_t launch_slot_counts(const SolveParams& P, int* counts, int nslots, hipStream_t s);
 
 }  // namespace eik

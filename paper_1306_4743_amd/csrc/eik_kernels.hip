@@ -225,23 +225,24 @@ struct CellXYZ {
     int x, y, z;
 };
 
-__device__ __forceinline__ CellXYZ cell_coords(const SolveParams& P, int c) {
+// Cell coordinates of local cell lc of a slot.
+__device__ __forceinline__ CellXYZ cell_coords(const Slot& S, int lc) {
     CellXYZ r;
-    r.x = c % P.ncx;
-    r.y = (c / P.ncx) % P.ncy;
-    r.z = c / (P.ncx * P.ncy);
+    r.x = lc % S.ncx;
+    r.y = (lc / S.ncx) % S.ncy;
+    r.z = lc / (S.ncx * S.ncy);
     return r;
 }
 
-// Neighbour cell across face f (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z); -1 beyond the grid.
-__device__ __forceinline__ int cell_neighbour(const SolveParams& P, int c, CellXYZ cc, int f) {
+// Local neighbour cell across face f (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z); -1 beyond the grid.
+__device__ __forceinline__ int cell_neighbour(const Slot& S, int lc, CellXYZ cc, int f) {
     switch (f) {
-        case 0: return cc.x > 0 ? c - 1 : -1;
-        case 1: return cc.x + 1 < P.ncx ? c + 1 : -1;
-        case 2: return cc.y > 0 ? c - P.ncx : -1;
-        case 3: return cc.y + 1 < P.ncy ? c + P.ncx : -1;
-        case 4: return cc.z > 0 ? c - P.ncx * P.ncy : -1;
-        default: return cc.z + 1 < P.ncz ? c + P.ncx * P.ncy : -1;
+        case 0: return cc.x > 0 ? lc - 1 : -1;
+        case 1: return cc.x + 1 < S.ncx ? lc + 1 : -1;
+        case 2: return cc.y > 0 ? lc - S.ncx : -1;
+        case 3: return cc.y + 1 < S.ncy ? lc + S.ncx : -1;
+        case 4: return cc.z > 0 ? lc - S.ncx * S.ncy : -1;
+        default: return cc.z + 1 < S.ncz ? lc + S.ncx * S.ncy : -1;
     }
 }
 
@@ -413,25 +414,29 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     constexpr int BOFF = 1 + B + B * B;
     const double INF = __builtin_inf();
     const unsigned long long t0 = cycles();
-    const CellXYZ cc = cell_coords(P, c);
-    const double* __restrict__ ug = P.u + (size_t)c * R3;
-    const FT* __restrict__ fg = reinterpret_cast<const FT*>(P.f) + (size_t)c * R3;
+    // The cell's grid (slot) and its local index there; c itself is a global cell id.
+    c = __builtin_amdgcn_readfirstlane(c);
+    const Slot S = P.slots[P.cell_slot[c]];
+    const int lc = c - S.cell_base;
+    const CellXYZ cc = cell_coords(S, lc);
+    const double* __restrict__ ug = S.u + (size_t)lc * R3;
+    const FT* __restrict__ fg = reinterpret_cast<const FT*>(S.f) + (size_t)lc * R3;
 
     // Stage in: cell values and s = h/F.
     for (int l = lane; l < R3; l += 64) {
         const int x = l % R, y = (l / R) % R, z = l / R2;
         L.U[box_index<R>(x, y, z)] = ug[l];
         const FT fv = fg[l];
-        L.S[l] = fv > FT(0) ? P.h / (double)fv : (fv < FT(0) ? -1.0 : 0.0);
+        L.S[l] = fv > FT(0) ? S.h / (double)fv : (fv < FT(0) ? -1.0 : 0.0);
     }
     // Halo: the neighbour's opposite face copy, +inf beyond the grid.
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        const int nb = cell_neighbour(P, c, cc, f);
+        const int nb = cell_neighbour(S, lc, cc, f);
         if (lane < R2) {
             int x, y, z;
             face_node<R>(f, lane % R, lane / R, x, y, z);
-            const double v = nb >= 0 ? P.faces[((size_t)nb * 6 + (f ^ 1)) * R2 + lane] : INF;
+            const double v = nb >= 0 ? S.faces[((size_t)nb * 6 + (f ^ 1)) * R2 + lane] : INF;
             L.U[box_index<R>(x, y, z) + face_step<R>(f)] = v;
         }
     }
@@ -480,7 +485,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     bool visit_changed = false, requeue = false;
     unsigned int upd = 0;
     int nsweeps = 0;
-    const bool track_dec = P.tol > 0.0;
+    const bool track_dec = S.tol > 0.0;
     if constexpr (INNER == INNER_SWEEP) {
         // Sweeps: preferred directions first (Gray order), then the default Gray cycle.  A sweep in
         // direction d visits the planes of the reflected coordinates x ^ mx etc. in increasing order.
@@ -554,7 +559,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                 left |= is_active(L.U[box_index<R>(x, y, z)]);
             }
             if (!__any(left)) break;
-            if (P.tol > 0.0 && wave_max(maxdec) <= P.tol) break;
+            if (track_dec && wave_max(maxdec) <= S.tol) break;
             if (nsweeps >= P.max_sweeps) { requeue = true; break; }
         }
     } else if constexpr (INNER == INNER_DUAL) {
@@ -643,7 +648,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                     // The tol test needs a complete sweep: the last NP steps hold one for the
                     // stream whose sweep began NP steps ago.
                     const double dec_half = track_dec ? wave_max(maxdec) : 0.0;
-                    const bool small = track_dec && nsweeps >= 2 && fmax(dec_half, dec_prev) <= P.tol;
+                    const bool small = track_dec && nsweeps >= 2 && fmax(dec_half, dec_prev) <= S.tol;
                     dec_prev = dec_half;
                     if (!__any(left) || small) {
                         done = true;
@@ -735,7 +740,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
             visit_changed |= any_changed;
             cur ^= 1;
             n_cur = n_next;
-            if (P.tol > 0.0 && wave_max(maxdec) <= P.tol) break;
+            if (track_dec && wave_max(maxdec) <= S.tol) break;
             if (n_cur > 0 && nsweeps >= P.max_sweeps) { requeue = true; break; }
         }
     }
@@ -751,14 +756,14 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     uint32_t my_bits = 0;
     double my_value = INF;
     if (visit_changed) {
-        double* __restrict__ uw = P.u + (size_t)c * R3;
+        double* __restrict__ uw = S.u + (size_t)lc * R3;
         for (int l = lane; l < R3; l += 64) {
             const int x = l % R, y = (l / R) % R, z = l / R2;
             uw[l] = fabs(L.U[box_index<R>(x, y, z)]);
         }
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            const int nb = cell_neighbour(P, c, cc, f);
+            const int nb = cell_neighbour(S, lc, cc, f);
             bool ch = false, inflow = false;
             double v = INF;
             if (lane < R2) {
@@ -770,13 +775,13 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                 inflow = ch && v < fabs(L.U[b + face_step<R>(f)]);
             }
             if (__any(ch) && lane < R2)
-                P.faces[((size_t)c * 6 + f) * R2 + lane] = v;
+                S.faces[((size_t)lc * 6 + f) * R2 + lane] = v;
             if (nb >= 0 && __any(inflow)) {
                 const double kv = wave_min(inflow ? v : INF);
                 if (lane == f) {
                     const int g = f ^ 1;
                     my_tag = true;
-                    my_target = nb;
+                    my_target = S.cell_base + nb;
                     my_bits = (1u << g) | (pref_mask_for_face(g) << FL_DIR_SHIFT);
                     my_value = kv;
                 }
@@ -854,8 +859,8 @@ k_solve(SolveParams P) {
     int rounds_done = 0;
 
     const int nwaves_total = (int)gridDim.x * W;
-    for (int t = 0;; ++t) {
-        const int cur = t & 1, nxt = cur ^ 1;
+    for (int64_t t = P.round_begin;; ++t) {
+        const int cur = (int)(t & 1), nxt = cur ^ 1;
         RoundCtl* ctl_cur = &P.ctl[t & 3];
         RoundCtl* ctl_next = &P.ctl[(t + 1) & 3];
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -928,9 +933,13 @@ k_solve(SolveParams P) {
         if (!ok) break;
         const uint32_t nnext = __hip_atomic_load(&ctl_next->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int st = __hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (nnext == 0 || st != 0) break;
-        if (t + 1 >= P.max_rounds) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(P.status, 0, EIK_ENOCONV_DEV);
+        // Every workgroup reads the same words after the barrier, so all leave together.
+        if (nnext == 0 || st != 0 || t + 1 >= P.round_end || t + 1 >= P.max_rounds) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                *P.next_round = t + 1;
+                if (nnext != 0 && st == 0 && t + 1 >= P.max_rounds)
+                    atomicCAS(P.status, 0, EIK_ENOCONV_DEV);
+            }
             break;
         }
     }
@@ -953,119 +962,148 @@ k_solve(SolveParams P) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Stage inputs (a1): row-major F -> cell-blocked F with padding marked 0, u <- +inf, faces <- +inf.
-// Speeds that are not finite and positive set the status to EIK_EINVAL.
+// Stage inputs (a1): row-major F -> cell-blocked F of one slot with padding marked 0, u <- +inf
+// (NaN on padding).  Speeds that are not finite and positive set the slot's status to
+// EIK_EINVAL.
 
 template <int R, typename FT>
-__global__ void k_init_nodes(SolveParams P, const FT* __restrict__ F) {
+__global__ void k_init_nodes(Slot S, const FT* __restrict__ F) {
     constexpr int R3 = R * R * R;
-    const size_t total = (size_t)P.ncell * R3;
+    const size_t total = (size_t)S.ncell * R3;
     const double INF = __builtin_inf();
-    FT* fb = reinterpret_cast<FT*>(P.fw);
+    FT* fb = reinterpret_cast<FT*>(S.f);
     for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < total;
          g += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(g / R3), l = (int)(g % R3);
+        const int lc = (int)(g / R3), l = (int)(g % R3);
         const int x = l % R, y = (l / R) % R, z = l / (R * R);
-        const CellXYZ cc = cell_coords(P, c);
+        const CellXYZ cc = cell_coords(S, lc);
         const int i = cc.x * R + x, j = cc.y * R + y, k = cc.z * R + z;
         FT fv = FT(0);
-        if (i < P.nx && j < P.ny && k < P.nz) {
-            fv = F[(size_t)i + (size_t)P.nx * ((size_t)j + (size_t)P.ny * k)];
+        if (i < S.nx && j < S.ny && k < S.nz) {
+            fv = F[(size_t)i + (size_t)S.nx * ((size_t)j + (size_t)S.ny * k)];
             const double dv = (double)fv;
             if (!(dv > 0.0) || !(dv <= 1.7976931348623157e308)) {
-                atomicCAS(P.status, 0, EIK_EINVAL_DEV);
+                atomicCAS(S.status, 0, EIK_EINVAL_DEV);
                 fv = FT(1);
             }
         }
         fb[g] = fv;
-        // Padding nodes hold NaN: fmin() ignores them (like +inf beyond the grid) and every
-        // comparison with them is false, so they are never activated or used as inflow.
-        P.u[g] = fv == FT(0) ? __builtin_nan("") : INF;
+        // Padding nodes hold NaN: the minimum ignores them (like +inf beyond the grid) and
+        // every comparison with them is false, so they are never activated or used as inflow.
+        S.u[g] = fv == FT(0) ? __builtin_nan("") : INF;
     }
 }
 
+// The slot's face copies <- +inf, its cells' state cleared and mapped to the slot.
 template <int R>
-__global__ void k_init_cells(SolveParams P) {
+__global__ void k_init_cells(SolveParams P, Slot S, int slot) {
     constexpr int R2 = R * R;
-    const size_t nf = (size_t)P.ncell * 6 * R2;
+    const size_t nf = (size_t)S.ncell * 6 * R2;
     const double INF = __builtin_inf();
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t g0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    for (size_t g = g0; g < nf; g += stride) P.faces[g] = INF;
-    for (size_t g = g0; g < (size_t)P.ncell; g += stride) {
-        P.key[0][g] = dbits(INF);
-        P.key[1][g] = dbits(INF);
-        P.flags[0][g] = 0;
-        P.flags[1][g] = 0;
+    for (size_t g = g0; g < nf; g += stride) S.faces[g] = INF;
+    for (size_t g = g0; g < (size_t)S.ncell; g += stride) {
+        const size_t c = (size_t)S.cell_base + g;
+        P.key[0][c] = dbits(INF);
+        P.key[1][c] = dbits(INF);
+        P.flags[0][c] = 0;
+        P.flags[1][c] = 0;
+        const_cast<int*>(P.cell_slot)[c] = slot;
     }
+    if (g0 == 0) *S.status = 0;
+}
+
+// Round control, barrier, launch status and counters (once per solve or server).
+__global__ void k_init_global(SolveParams P) {
+    const int g0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const double INF = __builtin_inf();
     if (g0 < 4) {
         P.ctl[g0].count = 0;
         P.ctl[g0].cursor = 0;
         P.ctl[g0].minkey = dbits(INF);
     }
     if (g0 < 2) P.bar[g0 * kBarGen] = 0;
-    if (g0 == 0) *P.status = 0;  // first kernel of the solve; later kernels may set it
+    if (g0 == 0) {
+        *P.status = 0;
+        *P.next_round = 0;
+    }
     if (g0 < ST_COUNT) P.stats[g0] = 0;
 }
 
 // Seed (a2): exit nodes fixed at q (min over duplicates), marked as exits in the blocked speed
 // array, copied into their cell's face layers; their cells and the cells of their six grid
-// neighbours are queued for round 0 with every node active and cell value q (the initial cell
-// values of Section 4).
+// neighbours are queued for round `round` with every node active and cell value q (the initial
+// cell values of Section 4).
 template <int R, typename FT>
-__global__ void k_seed(SolveParams P, int64_t nsrc, const int64_t* __restrict__ idx3,
-                       const double* __restrict__ q) {
+__global__ void k_seed(SolveParams P, Slot S, int64_t round, int64_t nsrc,
+                       const int64_t* __restrict__ idx3, const double* __restrict__ q) {
     constexpr int R2 = R * R, R3 = R * R * R;
     const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (n >= nsrc) return;
     const int64_t i = idx3[3 * n], j = idx3[3 * n + 1], k = idx3[3 * n + 2];
     const double qv = q[n] + 0.0;  // -0.0 -> +0.0 so that bit order is value order
-    if (i < 0 || i >= P.nx || j < 0 || j >= P.ny || k < 0 || k >= P.nz || !(qv >= 0.0) ||
+    if (i < 0 || i >= S.nx || j < 0 || j >= S.ny || k < 0 || k >= S.nz || !(qv >= 0.0) ||
         !(qv <= 1.7976931348623157e308)) {
-        atomicCAS(P.status, 0, EIK_EINVAL_DEV);
+        atomicCAS(S.status, 0, EIK_EINVAL_DEV);
         return;
     }
     const int cx = (int)(i / R), cy = (int)(j / R), cz = (int)(k / R);
     const int x = (int)(i % R), y = (int)(j % R), z = (int)(k % R);
-    const int c = cx + P.ncx * (cy + P.ncy * cz);
+    const int lc = cx + S.ncx * (cy + S.ncy * cz);
     const int l = x + R * (y + R * z);
-    atomicMin((unsigned long long*)&P.u[(size_t)c * R3 + l], (unsigned long long)dbits(qv));
-    reinterpret_cast<FT*>(P.fw)[(size_t)c * R3 + l] = FT(-1);
+    atomicMin((unsigned long long*)&S.u[(size_t)lc * R3 + l], (unsigned long long)dbits(qv));
+    reinterpret_cast<FT*>(S.f)[(size_t)lc * R3 + l] = FT(-1);
     // Face copies of the exit node.
     const int fx[6] = {x == 0, x == R - 1, y == 0, y == R - 1, z == 0, z == R - 1};
     for (int f = 0; f < 6; ++f) {
         if (!fx[f]) continue;
         const int a = (f >> 1) == 0 ? y : x;
         const int b = (f >> 1) == 2 ? y : z;
-        atomicMin((unsigned long long*)&P.faces[((size_t)c * 6 + f) * R2 + a + R * b],
+        atomicMin((unsigned long long*)&S.faces[((size_t)lc * 6 + f) * R2 + a + R * b],
                   (unsigned long long)dbits(qv));
     }
-    // Round 0 uses control slot 0 and parity buffer 0.
-    tag_cell(P, &P.ctl[0], 0, c, FL_ALL, qv);
+    RoundCtl* ctl = &P.ctl[round & 3];
+    const int par = (int)(round & 1);
+    tag_cell(P, ctl, par, S.cell_base + lc, FL_ALL, qv);
     const int64_t nbr[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
                                {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
     for (int t = 0; t < 6; ++t) {
         const int64_t a = nbr[t][0], b = nbr[t][1], e = nbr[t][2];
-        if (a < 0 || a >= P.nx || b < 0 || b >= P.ny || e < 0 || e >= P.nz) continue;
-        const int nc = (int)(a / R) + P.ncx * ((int)(b / R) + P.ncy * (int)(e / R));
-        if (nc != c) tag_cell(P, &P.ctl[0], 0, nc, FL_ALL, qv);
+        if (a < 0 || a >= S.nx || b < 0 || b >= S.ny || e < 0 || e >= S.nz) continue;
+        const int nc = (int)(a / R) + S.ncx * ((int)(b / R) + S.ncy * (int)(e / R));
+        if (nc != lc) tag_cell(P, ctl, par, S.cell_base + nc, FL_ALL, qv);
     }
 }
 
-// Output (a8): cell-blocked u -> row-major u_out.
+// Output (a8): cell-blocked u of one slot -> row-major u_out.
 template <int R>
-__global__ void k_output(SolveParams P, double* __restrict__ out) {
+__global__ void k_output(Slot S, double* __restrict__ out) {
     constexpr int R3 = R * R * R;
-    const size_t total = (size_t)P.nx * P.ny * P.nz;
+    const size_t total = (size_t)S.nx * S.ny * S.nz;
     for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < total;
          g += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(g % P.nx);
-        const int j = (int)((g / P.nx) % P.ny);
-        const int k = (int)(g / ((size_t)P.nx * P.ny));
-        const int c = i / R + P.ncx * (j / R + P.ncy * (k / R));
+        const int i = (int)(g % S.nx);
+        const int j = (int)((g / S.nx) % S.ny);
+        const int k = (int)(g / ((size_t)S.nx * S.ny));
+        const int lc = i / R + S.ncx * (j / R + S.ncy * (k / R));
         const int l = i % R + R * (j % R + R * (k % R));
-        out[g] = P.u[(size_t)c * R3 + l];
+        out[g] = S.u[(size_t)lc * R3 + l];
     }
+}
+
+// Cells of each slot in the list of the next launch's first round (the host's test for
+// finished grids).
+__global__ void k_slot_counts_zero(int* counts, int nslots) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < nslots) counts[g] = 0;
+}
+__global__ void k_slot_counts(SolveParams P, int* counts) {
+    const int64_t round = *P.next_round;
+    const uint32_t n = P.ctl[round & 3].count;
+    const int32_t* lst = P.list[round & 1];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        atomicAdd(&counts[P.cell_slot[lst[i]]], 1);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1116,62 +1154,93 @@ static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int worker
 }
 
 template <int R, typename FT>
-static hipError_t launch_all_t(const SolveParams& P, const void* F, int64_t nsrc,
-                               const int64_t* idx3, const double* q, double* u_out,
-                               hipStream_t s, int workers, int* used, const LaunchEvents* ev,
-                               const SolveOrder* order) {
-    const int threads = 256;
-    const size_t nodes = (size_t)P.ncell * R * R * R;
-    int blocks = (int)((nodes + threads - 1) / threads);
-    if (blocks > 65536) blocks = 65536;
-    hipError_t e;
-    if (ev && ev->ev[0] && (e = hipEventRecord(ev->ev[0], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_init_cells<R>), dim3(blocks), dim3(threads), 0, s, P);
-    hipLaunchKernelGGL((k_init_nodes<R, FT>), dim3(blocks), dim3(threads), 0, s, P,
-                       reinterpret_cast<const FT*>(F));
-    if (nsrc > 0) {
-        const int sb = (int)((nsrc + 63) / 64);
-        hipLaunchKernelGGL((k_seed<R, FT>), dim3(sb), dim3(64), 0, s, P, nsrc, idx3, q);
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (ev && ev->ev[1] && (e = hipEventRecord(ev->ev[1], s)) != hipSuccess) return e;
-    if (nsrc > 0) {
-        if (order && order->after && (e = hipStreamWaitEvent(s, order->after, 0)) != hipSuccess)
-            return e;
-        if (P.inner == INNER_SWEEP)
-            e = launch_solve_t<R, FT, kWavesPerGroup, INNER_SWEEP>(P, s, workers, used);
-        else if (P.inner == INNER_LIST)
-            e = launch_solve_t<R, FT, kWavesPerGroup, INNER_LIST>(P, s, workers, used);
-        else
-            e = launch_solve_t<R, FT, kWavesPerGroupDual, INNER_DUAL>(P, s, workers, used);
-        if (e != hipSuccess) return e;
-        if (order && (e = hipEventRecord(order->done, s)) != hipSuccess) return e;
-    }
-    if (ev && ev->ev[2] && (e = hipEventRecord(ev->ev[2], s)) != hipSuccess) return e;
-    const size_t out_nodes = (size_t)P.nx * P.ny * P.nz;
-    int ob = (int)((out_nodes + threads - 1) / threads);
-    if (ob > 65536) ob = 65536;
-    hipLaunchKernelGGL((k_output<R>), dim3(ob), dim3(threads), 0, s, P, u_out);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (ev && ev->ev[3] && (e = hipEventRecord(ev->ev[3], s)) != hipSuccess) return e;
-    return hipSuccess;
+static hipError_t solve_rounds_t(const SolveParams& P, hipStream_t s, int workers, int* used) {
+    if (P.inner == INNER_SWEEP)
+        return launch_solve_t<R, FT, kWavesPerGroup, INNER_SWEEP>(P, s, workers, used);
+    if (P.inner == INNER_LIST)
+        return launch_solve_t<R, FT, kWavesPerGroup, INNER_LIST>(P, s, workers, used);
+    return launch_solve_t<R, FT, kWavesPerGroupDual, INNER_DUAL>(P, s, workers, used);
 }
 
-hipError_t launch_solve(const SolveParams& P, int cell, int f_dtype, const void* F,
-                        int64_t nsrc, const int64_t* idx3, const double* q, double* u_out,
-                        hipStream_t s, int workers, int* used, const LaunchEvents* ev,
-                        const SolveOrder* order) {
+static int blocks_for(size_t n, int threads) {
+    size_t b = (n + threads - 1) / threads;
+    if (b > 65536) b = 65536;
+    return b < 1 ? 1 : (int)b;
+}
+
+hipError_t launch_init_global(const SolveParams& P, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_global, dim3(1), dim3(64), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_slot(const SolveParams& P, const Slot& S, int slot, int cell, int f_dtype,
+                            const void* F, hipStream_t s) {
+    const int threads = 256;
+    const size_t nodes = (size_t)S.ncell * cell * cell * cell;
+    const int blocks = blocks_for(nodes, threads);
     if (cell == 8) {
-        return f_dtype == 1 ? launch_all_t<8, float>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev, order)
-                            : launch_all_t<8, double>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev, order);
+        hipLaunchKernelGGL((k_init_cells<8>), dim3(blocks), dim3(threads), 0, s, P, S, slot);
+        if (f_dtype == EIK_F32)
+            hipLaunchKernelGGL((k_init_nodes<8, float>), dim3(blocks), dim3(threads), 0, s, S,
+                               reinterpret_cast<const float*>(F));
+        else
+            hipLaunchKernelGGL((k_init_nodes<8, double>), dim3(blocks), dim3(threads), 0, s, S,
+                               reinterpret_cast<const double*>(F));
+    } else if (cell == 4) {
+        hipLaunchKernelGGL((k_init_cells<4>), dim3(blocks), dim3(threads), 0, s, P, S, slot);
+        if (f_dtype == EIK_F32)
+            hipLaunchKernelGGL((k_init_nodes<4, float>), dim3(blocks), dim3(threads), 0, s, S,
+                               reinterpret_cast<const float*>(F));
+        else
+            hipLaunchKernelGGL((k_init_nodes<4, double>), dim3(blocks), dim3(threads), 0, s, S,
+                               reinterpret_cast<const double*>(F));
+    } else {
+        return hipErrorInvalidValue;
     }
-    if (cell == 4) {
-        return f_dtype == 1 ? launch_all_t<4, float>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev, order)
-                            : launch_all_t<4, double>(P, F, nsrc, idx3, q, u_out, s, workers, used, ev, order);
-    }
+    return hipGetLastError();
+}
+
+hipError_t launch_seed(const SolveParams& P, const Slot& S, int cell, int f_dtype, int64_t round,
+                       int64_t nsrc, const int64_t* idx3, const double* q, hipStream_t s) {
+    if (nsrc <= 0) return hipSuccess;
+    const int sb = (int)((nsrc + 63) / 64);
+    if (cell == 8 && f_dtype == EIK_F32)
+        hipLaunchKernelGGL((k_seed<8, float>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc, idx3, q);
+    else if (cell == 8)
+        hipLaunchKernelGGL((k_seed<8, double>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc, idx3, q);
+    else if (f_dtype == EIK_F32)
+        hipLaunchKernelGGL((k_seed<4, float>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc, idx3, q);
+    else
+        hipLaunchKernelGGL((k_seed<4, double>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc, idx3, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipStream_t s,
+                               int workers, int* used) {
+    if (cell == 8)
+        return f_dtype == EIK_F32 ? solve_rounds_t<8, float>(P, s, workers, used)
+                                  : solve_rounds_t<8, double>(P, s, workers, used);
+    if (cell == 4)
+        return f_dtype == EIK_F32 ? solve_rounds_t<4, float>(P, s, workers, used)
+                                  : solve_rounds_t<4, double>(P, s, workers, used);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s) {
+    const int threads = 256;
+    const int ob = blocks_for((size_t)S.nx * S.ny * S.nz, threads);
+    if (cell == 8)
+        hipLaunchKernelGGL((k_output<8>), dim3(ob), dim3(threads), 0, s, S, u_out);
+    else
+        hipLaunchKernelGGL((k_output<4>), dim3(ob), dim3(threads), 0, s, S, u_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_counts(const SolveParams& P, int* counts, int nslots, hipStream_t s) {
+    hipLaunchKernelGGL(k_slot_counts_zero, dim3(blocks_for((size_t)nslots, 256)), dim3(256), 0,
+                       s, counts, nslots);
+    hipLaunchKernelGGL(k_slot_counts, dim3(64), dim3(256), 0, s, P, counts);
+    return hipGetLastError();
 }
 
 }  // namespace eik

@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeik.so")
 
 EIK_OK, EIK_EINVAL, EIK_ENOMEM, EIK_EHIP, EIK_ENOCONV, EIK_ECANCELLED = 0, -1, -2, -3, -4, -5
+EIK_EBUSY = -6
 EIK_F64, EIK_F32 = 0, 1
 EIK_MODE_FP64 = 0
 EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL = 1, 2, 3
@@ -39,6 +40,11 @@ class Options(ctypes.Structure):
                 ("inner", ctypes.c_int)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int64 * 3), ("h", ctypes.c_double), ("F", ctypes.c_void_p),
+                ("sources", Sources), ("u_out", ctypes.c_void_p), ("tol", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("rounds", "visits", "sweeps", "updates", "deferred", "requeued", "cells",
@@ -52,8 +58,11 @@ class Stats(ctypes.Structure):
 _lib = None
 
 # Every symbol declared in include/eik.h.
-EXPORTS = ("eik_solve", "eik_solve_ex", "eik_query_workspace", "eik_stream_status",
-           "eik_kernel_times", "eik_strerror", "eik_release", "eik_version")
+EXPORTS = ("eik_solve", "eik_solve_ex", "eik_query_workspace", "eik_problem_bytes",
+           "eik_stream_status", "eik_kernel_times", "eik_solve_batch", "eik_batch_status",
+           "eik_server_create", "eik_server_submit", "eik_server_step", "eik_server_poll",
+           "eik_server_load", "eik_server_destroy", "eik_strerror", "eik_release",
+           "eik_version")
 
 
 def load():
@@ -83,6 +92,27 @@ def load():
     lib.eik_release.restype = None
     lib.eik_version.argtypes = []
     lib.eik_version.restype = ctypes.c_char_p
+    lib.eik_problem_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.eik_problem_bytes.restype = i32
+    lib.eik_solve_batch.argtypes = [i32, ctypes.POINTER(Problem), i32, i32, vp,
+                                    ctypes.POINTER(Options)]
+    lib.eik_solve_batch.restype = i32
+    lib.eik_batch_status.argtypes = [vp, i32, vp]
+    lib.eik_batch_status.restype = i32
+    lib.eik_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, i64, i32, i32, i32, vp,
+                                      ctypes.POINTER(Options)]
+    lib.eik_server_create.restype = i32
+    lib.eik_server_submit.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(i64)]
+    lib.eik_server_submit.restype = i32
+    lib.eik_server_step.argtypes = [vp, i64, ctypes.POINTER(i32)]
+    lib.eik_server_step.restype = i32
+    lib.eik_server_poll.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i32)]
+    lib.eik_server_poll.restype = i32
+    lib.eik_server_load.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                    ctypes.POINTER(ctypes.c_size_t)]
+    lib.eik_server_load.restype = i32
+    lib.eik_server_destroy.argtypes = [vp]
+    lib.eik_server_destroy.restype = i32
     _lib = lib
     return lib
 
@@ -131,6 +161,64 @@ class _HostSources:
                               self.q.ctypes.data if self.q.size else None, 0)
 
 
+def _f_dtype(F):
+    import torch
+    if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dim() == 3 and F.is_contiguous()):
+        raise ValueError("F must be a contiguous 3-D CUDA tensor [nz, ny, nx]")
+    if F.dtype == torch.float32:
+        return EIK_F32
+    if F.dtype == torch.float64:
+        return EIK_F64
+    raise ValueError("F must be float32 or float64")
+
+
+def _out_tensor(F, u_out):
+    import torch
+    if u_out is None:
+        return torch.empty(F.shape, dtype=torch.float64, device=F.device)
+    if not (u_out.is_cuda and u_out.dtype == torch.float64 and u_out.shape == F.shape
+            and u_out.is_contiguous()):
+        raise ValueError("u_out must be a contiguous float64 CUDA tensor shaped like F")
+    return u_out
+
+
+def _sources(F, idx3, q, stream):
+    """(ctypes Sources, objects to keep alive while the library may read them)."""
+    import torch
+    if isinstance(idx3, torch.Tensor) and idx3.is_cuda:
+        idx3_t = idx3.to(torch.int64).contiguous()
+        q_t = torch.as_tensor(q, dtype=torch.float64, device=F.device).contiguous()
+        if stream is not None:
+            idx3_t.record_stream(stream)
+            q_t.record_stream(stream)
+        return Sources(idx3_t.shape[0], idx3_t.data_ptr(), q_t.data_ptr(), 1), (idx3_t, q_t)
+    keep = _HostSources(idx3, q)
+    return keep.struct, keep
+
+
+def _options(delta=0.0, max_rounds=0, max_sweeps=0, workers=0, shuffle=0, timing=False,
+             round_log=None, inner=0):
+    rl_ptr, rl_len = None, 0
+    if round_log is not None:
+        import torch
+        if not (round_log.is_cuda and round_log.dtype == torch.int64 and round_log.is_contiguous()):
+            raise ValueError("round_log must be a contiguous int64 CUDA tensor")
+        rl_ptr, rl_len = round_log.data_ptr(), round_log.numel() // 2
+    return Options(EIK_MODE_FP64, float(delta), int(max_rounds), int(max_sweeps), int(workers),
+                   int(shuffle), int(bool(timing)), rl_ptr, rl_len, int(inner))
+
+
+def _problem(F, h, idx3, q, tol, u_out, stream):
+    """(ctypes Problem, u_out tensor, keep-alive objects) of one grid."""
+    _f_dtype(F)
+    u_out = _out_tensor(F, u_out)
+    src, keep = _sources(F, idx3, q, stream)
+    nz, ny, nx = F.shape
+    pb = Problem((ctypes.c_int64 * 3)(nx, ny, nz), float(h), F.data_ptr(), src,
+                 u_out.data_ptr(), float(tol))
+    return pb, u_out, keep
+
+
 def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, stream=None,
           delta: float = 0.0, max_rounds: int = 0, max_sweeps: int = 0, workers: int = 0,
           shuffle: int = 0, timing: bool = False, round_log=None, inner: int = 0,
@@ -143,41 +231,12 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
     of F's shape.  The call returns after enqueueing; use ``status()`` to wait and read the
     device-side status and counters.
     """
-    import torch
     lib = load()
-    if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dim() == 3 and F.is_contiguous()):
-        raise ValueError("F must be a contiguous 3-D CUDA tensor [nz, ny, nx]")
-    if F.dtype == torch.float32:
-        f_dtype = EIK_F32
-    elif F.dtype == torch.float64:
-        f_dtype = EIK_F64
-    else:
-        raise ValueError("F must be float32 or float64")
+    f_dtype = _f_dtype(F)
+    u_out = _out_tensor(F, u_out)
+    src, keep = _sources(F, idx3, q, stream)
+    opts = _options(delta, max_rounds, max_sweeps, workers, shuffle, timing, round_log, inner)
     nz, ny, nx = F.shape
-    if u_out is None:
-        u_out = torch.empty(F.shape, dtype=torch.float64, device=F.device)
-    elif not (u_out.is_cuda and u_out.dtype == torch.float64 and u_out.shape == F.shape
-              and u_out.is_contiguous()):
-        raise ValueError("u_out must be a contiguous float64 CUDA tensor shaped like F")
-    keep = None
-    if isinstance(idx3, torch.Tensor) and idx3.is_cuda:
-        idx3_t = idx3.to(torch.int64).contiguous()
-        q_t = torch.as_tensor(q, dtype=torch.float64, device=F.device).contiguous()
-        src = Sources(idx3_t.shape[0], idx3_t.data_ptr(), q_t.data_ptr(), 1)
-        if stream is not None:
-            idx3_t.record_stream(stream)
-            q_t.record_stream(stream)
-        keep = (idx3_t, q_t)
-    else:
-        keep = _HostSources(idx3, q)
-        src = keep.struct
-    rl_ptr, rl_len = None, 0
-    if round_log is not None:
-        if not (round_log.is_cuda and round_log.dtype == torch.int64 and round_log.is_contiguous()):
-            raise ValueError("round_log must be a contiguous int64 CUDA tensor")
-        rl_ptr, rl_len = round_log.data_ptr(), round_log.numel() // 2
-    opts = Options(EIK_MODE_FP64, float(delta), int(max_rounds), int(max_sweeps), int(workers),
-                   int(shuffle), int(bool(timing)), rl_ptr, rl_len, int(inner))
     dims = _dims_array((nx, ny, nz))
     rc = lib.eik_solve_ex(ctypes.cast(dims, ctypes.c_void_p), float(h),
                           ctypes.c_void_p(F.data_ptr()), f_dtype, ctypes.byref(src),
@@ -187,6 +246,133 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
     if rc != EIK_OK and check:
         raise EikError(rc, "eik_solve: ")
     return u_out
+
+
+def problem_bytes(dims, cell: int = 8, f_dtype: int = EIK_F32) -> int:
+    """Device bytes of one grid's arrays inside a server pool (dims = (nx, ny, nz))."""
+    out = ctypes.c_size_t(0)
+    rc = load().eik_problem_bytes(ctypes.cast(_dims_array(dims), ctypes.c_void_p), int(cell),
+                                  int(f_dtype), ctypes.byref(out))
+    if rc != EIK_OK:
+        raise EikError(rc, "eik_problem_bytes: ")
+    return int(out.value)
+
+
+def solve_batch(problems, cell: int = 8, stream=None, check: bool = True, **opt):
+    """Enqueue one batched solve of independent grids on ``stream``.
+
+    problems: sequence of dicts with keys F, h, src (idx3), q and optional tol, u_out; every F
+    of one dtype.  Returns the list of u_out tensors; ``batch_status(len(problems))`` waits and
+    returns the per-problem status.
+    """
+    lib = load()
+    if not problems:
+        raise ValueError("empty batch")
+    f_dtype = _f_dtype(problems[0]["F"])
+    arr = (Problem * len(problems))()
+    outs, keep = [], []
+    for i, p in enumerate(problems):
+        if _f_dtype(p["F"]) != f_dtype:
+            raise ValueError("every F of a batch has the same dtype")
+        pb, u, k = _problem(p["F"], p["h"], p["src"], p["q"], p.get("tol", 0.0),
+                            p.get("u_out"), stream)
+        arr[i] = pb
+        outs.append(u)
+        keep.append(k)
+    opts = _options(**opt)
+    rc = lib.eik_solve_batch(len(problems), arr, f_dtype, int(cell), _stream_handle(stream),
+                             ctypes.byref(opts))
+    del keep
+    if rc != EIK_OK and check:
+        raise EikError(rc, "eik_solve_batch: ")
+    return outs
+
+
+def batch_status(n: int, stream=None):
+    """Wait for ``stream``; the device status of each problem of its last batch (numpy int32)."""
+    st = np.zeros(max(n, 0), dtype=np.int32)
+    got = load().eik_batch_status(_stream_handle(stream), int(n), st.ctypes.data)
+    if got < 0:
+        raise EikError(got, "eik_batch_status: ")
+    return st[:got]
+
+
+class Server:
+    """Continuous-batching server over the eik_server_* calls (one thread per server).
+
+    submit() admits a grid or returns None when it does not fit now (EIK_EBUSY); step() runs
+    one step and returns {ticket: (status, u_out)} for the grids retired in it.
+    """
+
+    def __init__(self, pool_bytes: int, max_cells: int, max_problems: int, cell: int = 8,
+                 f_dtype: int = EIK_F32, stream=None, **opt):
+        self._lib = load()
+        self._stream = stream
+        self._h = ctypes.c_void_p(None)
+        opts = _options(**opt)
+        rc = self._lib.eik_server_create(ctypes.byref(self._h), int(pool_bytes), int(max_cells),
+                                         int(max_problems), int(cell), int(f_dtype),
+                                         _stream_handle(stream), ctypes.byref(opts))
+        if rc != EIK_OK:
+            self._h = None
+            raise EikError(rc, "eik_server_create: ")
+        self._pending = {}   # ticket -> (u_out, keep-alive)
+        self._staged = []    # keep-alive of problems whose inputs the next step reads
+
+    def submit(self, F, h, idx3, q, tol=0.0, u_out=None):
+        pb, u, keep = _problem(F, h, idx3, q, tol, u_out, None)
+        t = ctypes.c_int64(-1)
+        rc = self._lib.eik_server_submit(self._h, ctypes.byref(pb), ctypes.byref(t))
+        if rc == EIK_EBUSY:
+            return None
+        if rc != EIK_OK:
+            raise EikError(rc, "eik_server_submit: ")
+        self._pending[int(t.value)] = (u, F)
+        self._staged.append(keep)
+        return int(t.value)
+
+    def step(self, rounds: int):
+        fin = ctypes.c_int(0)
+        rc = self._lib.eik_server_step(self._h, int(rounds), ctypes.byref(fin))
+        self._staged.clear()
+        if rc not in (EIK_OK, EIK_ECANCELLED):
+            raise EikError(rc, "eik_server_step: ")
+        out = {}
+        n = max(fin.value, 0)
+        while True:
+            m = max(n, 16)
+            tickets = np.zeros(m, dtype=np.int64)
+            st = np.zeros(m, dtype=np.int32)
+            got = ctypes.c_int(0)
+            prc = self._lib.eik_server_poll(self._h, m, tickets.ctypes.data, st.ctypes.data,
+                                            ctypes.byref(got))
+            if prc != EIK_OK:
+                raise EikError(prc, "eik_server_poll: ")
+            for t, s in zip(tickets[:got.value], st[:got.value]):
+                u, _ = self._pending.pop(int(t))
+                out[int(t)] = (int(s), u)
+            if got.value < m:
+                break
+        return out
+
+    def load(self):
+        np_, nc, pb = ctypes.c_int(0), ctypes.c_int64(0), ctypes.c_size_t(0)
+        rc = self._lib.eik_server_load(self._h, ctypes.byref(np_), ctypes.byref(nc),
+                                       ctypes.byref(pb))
+        if rc != EIK_OK:
+            raise EikError(rc, "eik_server_load: ")
+        return {"problems": np_.value, "cells": nc.value, "pool_bytes": pb.value}
+
+    def close(self):
+        if self._h:
+            self._lib.eik_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def status(stream=None):

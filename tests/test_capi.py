@@ -85,3 +85,83 @@ def test_stream_status_without_solve():
     # a stream handle that never had a solve: no workspace -> EIK_EINVAL, no device access
     assert lib.eik_stream_status(ctypes.c_void_p(0x1234), ctypes.byref(st)) in (eik.EIK_EINVAL,
                                                                                   eik.EIK_EHIP)
+
+
+def test_strerror_busy():
+    assert eik.strerror(eik.EIK_EBUSY).startswith("EIK_EBUSY")
+
+
+def test_problem_bytes():
+    """A grid's pool footprint: cell-blocked values (8 B), speeds (F dtype) and six face layers
+    per cell, each array rounded up to 256 B; it is the grid part of the workspace size."""
+    ncell = 9 ** 3  # 65 nodes per axis -> 9 cells of 8
+    want = sum(-(-b // 256) * 256 for b in (ncell * 512 * 8, ncell * 512 * 4, ncell * 384 * 8))
+    assert eik.problem_bytes((65, 65, 65), 8, eik.EIK_F32) == want
+    assert eik.query_workspace((65, 65, 65), 8, eik.EIK_F32) > want
+    with pytest.raises(eik.EikError):
+        eik.problem_bytes((65, 65, 65), 6, eik.EIK_F32)
+    with pytest.raises(eik.EikError):
+        eik.problem_bytes((65, 65, 65), 8, 3)
+
+
+def _problem(dims=(8, 8, 8), h=0.1, F=1, u=1, n=1, idx=None, q=None, tol=0.0):
+    idx = np.array([[0, 0, 0]] * max(n, 1), dtype=np.int64) if idx is None else idx
+    q = np.zeros(max(n, 1)) if q is None else q
+    src = eik.Sources(n, idx.ctypes.data, q.ctypes.data, 0)
+    pb = eik.Problem((ctypes.c_int64 * 3)(*dims), h, F, src, u, tol)
+    return pb, (idx, q)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dims=(1, 8, 8)), dict(h=-1.0), dict(F=0), dict(u=0), dict(tol=float("inf")),
+    dict(idx=np.array([[0, 0, 9]], dtype=np.int64)), dict(q=np.array([np.nan])),
+])
+def test_batch_with_one_invalid_problem_rejected(bad):
+    """eik_solve_batch validates every problem first: one invalid problem refuses the batch."""
+    lib = eik.load()
+    good, k1 = _problem()
+    badp, k2 = _problem(**bad)
+    arr = (eik.Problem * 3)(good, badp, good)
+    opts = eik._options()
+    assert lib.eik_solve_batch(3, arr, eik.EIK_F32, 8, None, ctypes.byref(opts)) == eik.EIK_EINVAL
+
+
+def test_batch_argument_checks():
+    lib = eik.load()
+    good, keep = _problem()
+    arr = (eik.Problem * 1)(good)
+    assert lib.eik_solve_batch(0, arr, eik.EIK_F32, 8, None, None) == eik.EIK_EINVAL
+    assert lib.eik_solve_batch(-2, arr, eik.EIK_F32, 8, None, None) == eik.EIK_EINVAL
+    assert lib.eik_solve_batch(1, None, eik.EIK_F32, 8, None, None) == eik.EIK_EINVAL
+    assert lib.eik_solve_batch(1, arr, eik.EIK_F32, 6, None, None) == eik.EIK_EINVAL
+    assert lib.eik_solve_batch(1, arr, 9, 8, None, None) == eik.EIK_EINVAL
+    bad_opt = eik._options(inner=9)
+    assert lib.eik_solve_batch(1, arr, eik.EIK_F32, 8, None, ctypes.byref(bad_opt)) == eik.EIK_EINVAL
+    assert lib.eik_batch_status(ctypes.c_void_p(0x4321), 1,
+                                np.zeros(1, np.int32).ctypes.data) in (eik.EIK_EINVAL, eik.EIK_EHIP)
+
+
+@pytest.mark.parametrize("args", [
+    (0, 100, 4, 8, eik.EIK_F32), (1 << 20, 0, 4, 8, eik.EIK_F32),
+    (1 << 20, 100, 0, 8, eik.EIK_F32), (1 << 20, 100, 4, 5, eik.EIK_F32),
+    (1 << 20, 100, 4, 8, 4), (1 << 20, 1 << 31, 4, 8, eik.EIK_F32),
+])
+def test_server_create_rejects_invalid(args):
+    lib = eik.load()
+    h = ctypes.c_void_p(None)
+    rc = lib.eik_server_create(ctypes.byref(h), args[0], args[1], args[2], args[3], args[4], None,
+                               None)
+    assert rc == eik.EIK_EINVAL and not h.value
+
+
+def test_server_calls_reject_null_server():
+    lib = eik.load()
+    t = ctypes.c_int64(0)
+    fin = ctypes.c_int(0)
+    pb, keep = _problem()
+    n = ctypes.c_int(0)
+    assert lib.eik_server_submit(None, ctypes.byref(pb), ctypes.byref(t)) == eik.EIK_EINVAL
+    assert lib.eik_server_step(None, 4, ctypes.byref(fin)) == eik.EIK_EINVAL
+    assert lib.eik_server_poll(None, 0, None, None, ctypes.byref(n)) == eik.EIK_EINVAL
+    assert lib.eik_server_load(None, None, None, None) == eik.EIK_EINVAL
+    assert lib.eik_server_destroy(None) == eik.EIK_EINVAL
