@@ -1,0 +1,239 @@
+"""Serving harness: a Poisson stream of Eikonal requests through the continuous-batching server
+(``eik_server_*``), measured against one-at-a-time solves of the same stream.
+
+The request mix is the mixed-size serving workload: request i has n nodes per side drawn
+uniformly from {33, 65, 129, 193, 257}, the barrier-maze speeds of ``workloads.maze_layout``
+drawn with seed 5000 + i (wall thickness and opening size scaled with (n-1)/512, floors 1 and
+2), 1-4 exit nodes drawn uniformly, q = 0, FP32 speeds, FP64 values, tol 0.  Speeds and result
+buffers of every request are resident in device memory before the clock starts (a serving
+process keeps its inputs in HBM); a request's latency runs from its arrival time to the end of
+the server step (or solve) after which its result is in its output buffer.
+
+Runs:
+  * saturated: every request arrives at time 0; gives the server's throughput (requests/s).
+  * Poisson arrivals at fractions (0.5, 0.8, 1.0) of that throughput: p50 / p99 latency.
+  * one-at-a-time: the same stream, FIFO, each request solved alone with ``eik_solve``.
+
+Usage: python -m paper_1306_4743_amd.serve [--requests N] [--rounds R] [--json]
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import sys
+import time
+
+import numpy as np
+
+SIZES = (33, 65, 129, 193, 257)
+
+
+@dataclasses.dataclass
+class Request:
+    i: int
+    n: int
+    seed: int
+    n_sources: int
+    F: object       # torch float32 [n, n, n] on the device
+    h: float
+    src: np.ndarray
+    q: np.ndarray
+    u: object       # torch float64 [n, n, n] on the device (the result buffer)
+
+    @property
+    def nodes(self) -> int:
+        return self.n ** 3
+
+
+def make_requests(count: int, device, seed: int = 1234, sizes=SIZES):
+    """The request stream: sizes and exit counts from ``seed``, maze i from seed 5000 + i."""
+    import torch
+    from . import workloads as W
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        n = int(sizes[int(rng.integers(len(sizes)))])
+        ns = int(rng.integers(1, 5))
+        F, h, src, q = W.maze_torch(n, 5000 + i, ns, device)
+        u = torch.empty(F.shape, dtype=torch.float64, device=device)
+        reqs.append(Request(i, n, 5000 + i, ns, F, h, src, q, u))
+    torch.cuda.synchronize(device)
+    return reqs
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = 99) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate, the first at 0."""
+    gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=count)
+    return np.concatenate([[0.0], np.cumsum(gaps[:-1])])
+
+
+def _summary(reqs, arrivals, finish, t_first, t_last):
+    lat = (finish - arrivals) * 1000.0
+    nodes = sum(r.nodes for r in reqs)
+    span = t_last - t_first
+    by = {}
+    for n in sorted({r.n for r in reqs}):
+        sel = np.array([r.n == n for r in reqs])
+        by[str(n)] = {"count": int(sel.sum()), "p50_ms": float(np.percentile(lat[sel], 50)),
+                      "p99_ms": float(np.percentile(lat[sel], 99))}
+    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "max_ms": float(lat.max()), "makespan_s": span,
+            "requests_per_s": len(reqs) / span, "solved_nodes_per_s": nodes / span,
+            "by_size": by}
+
+
+def pool_config(reqs, cell: int, pool_bytes: int):
+    from . import eik
+    per_cell = eik.problem_bytes((cell, cell, cell), cell, eik.EIK_F32)
+    biggest = max(eik.problem_bytes((r.n,) * 3, cell, eik.EIK_F32) for r in reqs)
+    pool_bytes = max(pool_bytes, biggest)
+    return pool_bytes, pool_bytes // per_cell + 1
+
+
+def run_server(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int = 16 << 30,
+               max_problems: int = 512, **opt):
+    """Feed ``reqs`` (arriving at ``arrivals`` seconds) to one server; returns the summary."""
+    import torch
+    from . import eik
+    pool_bytes, max_cells = pool_config(reqs, cell, pool_bytes)
+    srv = eik.Server(pool_bytes, max_cells, max_problems, cell=cell, f_dtype=eik.EIK_F32, **opt)
+    count = len(reqs)
+    finish = np.full(count, np.nan)
+    owner = {}
+    nxt, done, on_dev, steps = 0, 0, 0, 0
+    statuses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while done < count:
+        now = time.perf_counter() - t0
+        while nxt < count and arrivals[nxt] <= now:
+            r = reqs[nxt]
+            t = srv.submit(r.F, r.h, r.src, r.q, 0.0, r.u)
+            if t is None:
+                break  # no room now: the head of the queue waits for a retirement
+            owner[t] = nxt
+            nxt += 1
+            on_dev += 1
+        if on_dev == 0:
+            while time.perf_counter() - t0 < arrivals[nxt]:
+                pass
+            continue
+        out = srv.step(rounds)
+        steps += 1
+        tnow = time.perf_counter() - t0
+        for t, (status, _) in out.items():
+            finish[owner[t]] = tnow
+            statuses.append(status)
+            done += 1
+            on_dev -= 1
+    srv.close()
+    if any(s != 0 for s in statuses):
+        raise RuntimeError(f"server returned statuses {sorted(set(statuses))}")
+    res = _summary(reqs, arrivals, finish, 0.0, float(np.nanmax(finish)))
+    res["steps"] = steps
+    return res
+
+
+def run_sequential(reqs, arrivals, cell: int = 8, **opt):
+    """The same stream, FIFO, one ``eik_solve`` at a time (each waits for the previous)."""
+    import torch
+    from . import eik
+    count = len(reqs)
+    finish = np.full(count, np.nan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, r in enumerate(reqs):
+        while time.perf_counter() - t0 < arrivals[k]:
+            pass
+        eik.solve(r.F, r.h, r.src, r.q, cell=cell, tol=0.0, u_out=r.u, **opt)
+        rc, _ = eik.status()
+        if rc != 0:
+            raise RuntimeError(f"request {r.i}: {eik.strerror(rc)}")
+        finish[k] = time.perf_counter() - t0
+    return _summary(reqs, arrivals, finish, 0.0, float(finish.max()))
+
+
+def check_against_alone(reqs, sample: int = 10, cell: int = 8):
+    """Max relative difference between served results and the same requests solved alone."""
+    import torch
+    from . import eik
+    idx = np.linspace(0, len(reqs) - 1, min(sample, len(reqs))).astype(int)
+    worst = 0.0
+    for k in idx:
+        r = reqs[int(k)]
+        alone = eik.solve(r.F, r.h, r.src, r.q, cell=cell, tol=0.0)
+        rc, _ = eik.status()
+        if rc != 0:
+            raise RuntimeError(eik.strerror(rc))
+        a, b = alone.cpu().numpy(), r.u.cpu().numpy()
+        if not np.array_equal(np.isinf(a), np.isinf(b)):
+            return float("inf")
+        fin = np.isfinite(a) & (a > 0)
+        worst = max(worst, float(np.max(np.abs(a[fin] - b[fin]) / a[fin])))
+        del alone
+    torch.cuda.synchronize()
+    return worst
+
+
+def serve_benchmark(count: int = 2000, rounds: int = 8, cell: int = 8,
+                    fractions=(0.5, 0.8, 1.0), seq_fraction: float = 0.8,
+                    pool_bytes: int = 16 << 30, log=None):
+    """The whole serving measurement; returns a JSON-able dict."""
+    import torch
+    from . import eik
+    eik.load()
+    dev = torch.device("cuda:0")
+
+    def say(msg):
+        if log:
+            print(msg, file=log, flush=True)
+
+    t = time.perf_counter()
+    reqs = make_requests(count, dev)
+    say(f"serve: {count} requests generated in {time.perf_counter() - t:.1f} s")
+    # warm-up: a few requests through a server and alone
+    run_server(reqs[:8], np.zeros(8), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
+    run_sequential(reqs[:4], np.zeros(4), cell=cell)
+    sat = run_server(reqs, np.zeros(count), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
+    say(f"serve: saturated {sat['requests_per_s']:.1f} req/s, {sat['steps']} steps")
+    alone_diff = check_against_alone(reqs, cell=cell)
+    out = {"requests": count, "sizes": list(SIZES), "cell": cell, "rounds_per_step": rounds,
+           "pool_bytes": pool_bytes, "saturated": sat, "max_rel_diff_served_vs_alone": alone_diff,
+           "poisson": {}}
+    for f in fractions:
+        rate = f * sat["requests_per_s"]
+        res = run_server(reqs, poisson_arrivals(count, rate), cell=cell, rounds=rounds,
+                         pool_bytes=pool_bytes)
+        res["arrival_rate_per_s"] = rate
+        out["poisson"][str(f)] = res
+        say(f"serve: {f:.1f}x rate: p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms")
+    seq_sat = run_sequential(reqs, np.zeros(count), cell=cell)
+    out["one_at_a_time_saturated"] = seq_sat
+    say(f"serve: one-at-a-time {seq_sat['requests_per_s']:.1f} req/s")
+    rate = seq_fraction * sat["requests_per_s"]
+    seq = run_sequential(reqs, poisson_arrivals(count, rate), cell=cell)
+    seq["arrival_rate_per_s"] = rate
+    out["one_at_a_time_poisson"] = {str(seq_fraction): seq}
+    say(f"serve: one-at-a-time at {seq_fraction}x: p50 {seq['p50_ms']:.1f} p99 {seq['p99_ms']:.1f}")
+    del reqs
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--rounds", type=int, default=8, help="worklist rounds per server step")
+    ap.add_argument("--cell", type=int, default=8)
+    ap.add_argument("--pool-gib", type=float, default=16.0)
+    a = ap.parse_args()
+    res = serve_benchmark(a.requests, a.rounds, a.cell, pool_bytes=int(a.pool_gib * (1 << 30)),
+                          log=sys.stderr)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

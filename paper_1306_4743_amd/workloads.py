@@ -93,19 +93,18 @@ def curved(n: int = 129, cell: int = 8, tol: float = 0.0) -> Problem:
     return p
 
 
-def maze(n: int = 513, seed: int = 3, n_sources: int = 4, slabs_per_axis: int = 6,
-         thickness: int | None = None, gap: int | None = None, gaps_per_slab: int = 2,
-         barrier_speed: float = 0.01, cell: int = 8, tol: float = 0.0,
-         dtype=np.float32) -> Problem:
-    """Barrier maze: F = 1 except on axis-aligned slabs of low speed with square openings.
+def maze_layout(n: int = 513, seed: int = 3, n_sources: int = 4, slabs_per_axis: int = 6,
+                thickness: int | None = None, gap: int | None = None,
+                gaps_per_slab: int = 2) -> dict:
+    """The random part of the barrier maze, drawn once: slab positions, openings and sources.
 
     Slab m (m = 0..slabs_per_axis-1) on axis a covers the nodes [s_m, s_m + thickness) along
     a, s_m = round((m+1) (n-1) / (slabs_per_axis+1)) - thickness // 2, across the whole grid in
     the other two axes.  Each slab has ``gaps_per_slab`` openings of gap x gap nodes at uniform
-    random in-plane offsets; an opening restores F = 1 only inside its own slab.  At n = 513
-    thickness is 4 and gap 16; at other sizes both scale with (n-1)/512, floored at 1 and 2.
-    Sources: ``n_sources`` nodes drawn uniformly among the F = 1 nodes, q = 0.
-    F is returned in ``dtype`` (float32 by default) and both solvers read exactly those values.
+    random in-plane offsets (o1, o2) over the slab's two in-plane axes in increasing order; an
+    opening restores F = 1 only inside its own slab.  At n = 513 thickness is 4 and gap 16; at
+    other sizes both scale with (n-1)/512, floored at 1 and 2.  Sources: ``n_sources`` distinct
+    nodes drawn uniformly among the nodes outside every barrier.
     """
     scale = (n - 1) / 512.0
     if thickness is None:
@@ -113,36 +112,88 @@ def maze(n: int = 513, seed: int = 3, n_sources: int = 4, slabs_per_axis: int = 
     if gap is None:
         gap = max(2, int(round(16 * scale)))
     rng = np.random.default_rng(seed)
-    barrier = np.zeros((n, n, n), dtype=bool)
-    for axis in range(3):  # 0 = x, 1 = y, 2 = z
+    slabs = []  # (axis, start, [(o1, o2), ...]) with axis 0 = x, 1 = y, 2 = z
+    for axis in range(3):
         for m in range(slabs_per_axis):
             s = int(round((m + 1) * (n - 1) / (slabs_per_axis + 1))) - thickness // 2
             s = min(max(s, 0), n - thickness)
-            plane = np.ones((n, n), dtype=bool)  # indexed by the two in-plane axes in order
+            holes = []
             for _ in range(gaps_per_slab):
                 o1 = int(rng.integers(0, n - gap + 1))
                 o2 = int(rng.integers(0, n - gap + 1))
-                plane[o1:o1 + gap, o2:o2 + gap] = False
-            # storage order is [z][y][x]: axis x -> dim 2, y -> dim 1, z -> dim 0
-            if axis == 0:   # in-plane (y, z) -> plane[y, z]; view [z][y] needs transpose
-                barrier[:, :, s:s + thickness] |= plane.T[:, :, None]
-            elif axis == 1:  # in-plane (x, z) -> plane[x, z]; view [z][x]
-                barrier[:, s:s + thickness, :] |= plane.T[:, None, :]
-            else:            # in-plane (x, y) -> plane[x, y]; view [y][x]
-                barrier[s:s + thickness, :, :] |= plane.T[None, :, :]
-    F = np.where(barrier, dtype(barrier_speed), dtype(1.0)).astype(dtype)
+                holes.append((o1, o2))
+            slabs.append((axis, s, holes))
+
+    def in_barrier(i, j, k):
+        p = (i, j, k)
+        for axis, s, holes in slabs:
+            if not (s <= p[axis] < s + thickness):
+                continue
+            a, b = [p[x] for x in range(3) if x != axis]
+            if not any(o1 <= a < o1 + gap and o2 <= b < o2 + gap for o1, o2 in holes):
+                return True
+        return False
+
     src = []
     while len(src) < n_sources:
         i, j, k = (int(v) for v in rng.integers(0, n, size=3))
-        if barrier[k, j, i] or [i, j, k] in src:
+        if in_barrier(i, j, k) or [i, j, k] in src:
             continue
         src.append([i, j, k])
-    return Problem(f"maze{n}", F, _grid_h(n), np.array(src, dtype=np.int64),
-                   np.zeros(n_sources), cell, tol,
+    return {"n": n, "seed": seed, "thickness": thickness, "gap": gap, "slabs": slabs,
+            "slabs_per_axis": slabs_per_axis, "gaps_per_slab": gaps_per_slab,
+            "src": np.array(src, dtype=np.int64)}
+
+
+def _maze_barrier(layout, xp, zeros, ones):
+    """Boolean barrier mask [z][y][x] of a layout with array module ``xp`` (numpy or torch)."""
+    n, t, gap = layout["n"], layout["thickness"], layout["gap"]
+    barrier = zeros((n, n, n))
+    for axis, s, holes in layout["slabs"]:
+        plane = ones((n, n))  # indexed by the two in-plane axes in increasing order
+        for o1, o2 in holes:
+            plane[o1:o1 + gap, o2:o2 + gap] = False
+        pt = plane.T
+        # storage order is [z][y][x]: axis x -> dim 2, y -> dim 1, z -> dim 0
+        if axis == 0:    # plane[y, z] -> view [z][y]
+            barrier[:, :, s:s + t] |= pt[:, :, None]
+        elif axis == 1:  # plane[x, z] -> view [z][x]
+            barrier[:, s:s + t, :] |= pt[:, None, :]
+        else:            # plane[x, y] -> view [y][x]
+            barrier[s:s + t, :, :] |= pt[None, :, :]
+    return barrier
+
+
+def maze(n: int = 513, seed: int = 3, n_sources: int = 4, slabs_per_axis: int = 6,
+         thickness: int | None = None, gap: int | None = None, gaps_per_slab: int = 2,
+         barrier_speed: float = 0.01, cell: int = 8, tol: float = 0.0,
+         dtype=np.float32) -> Problem:
+    """Barrier maze: F = 1 except on axis-aligned slabs of speed ``barrier_speed`` with square
+    openings (layout in ``maze_layout``), q = 0 at the sources.  F is returned in ``dtype``
+    (float32 by default) and both solvers read exactly those values."""
+    L = maze_layout(n, seed, n_sources, slabs_per_axis, thickness, gap, gaps_per_slab)
+    barrier = _maze_barrier(L, np, lambda sh: np.zeros(sh, dtype=bool),
+                            lambda sh: np.ones(sh, dtype=bool))
+    F = np.where(barrier, dtype(barrier_speed), dtype(1.0)).astype(dtype)
+    return Problem(f"maze{n}", F, _grid_h(n), L["src"], np.zeros(n_sources), cell, tol,
                    {"workload": f"barrier maze {n}^3 ({slabs_per_axis} slabs/axis, thickness "
-                                f"{thickness}, {gaps_per_slab} gaps {gap}x{gap}, F=1/"
-                                f"{barrier_speed}), {n_sources} sources, seed {seed}",
-                    "seed": seed, "thickness": thickness, "gap": gap})
+                                f"{L['thickness']}, {gaps_per_slab} gaps {L['gap']}x{L['gap']}, "
+                                f"F=1/{barrier_speed}), {n_sources} sources, seed {seed}",
+                    "seed": seed, "thickness": L["thickness"], "gap": L["gap"]})
+
+
+def maze_torch(n: int, seed: int, n_sources: int, device, barrier_speed: float = 0.01):
+    """The same maze built directly in device memory (float32 F, bit-identical to ``maze``).
+
+    Returns (F tensor [n, n, n], h, sources int64 [k, 3], q float64 [k])."""
+    import torch
+    L = maze_layout(n, seed, n_sources)
+    barrier = _maze_barrier(L, torch,
+                            lambda sh: torch.zeros(sh, dtype=torch.bool, device=device),
+                            lambda sh: torch.ones(sh, dtype=torch.bool, device=device))
+    F = torch.where(barrier, torch.tensor(barrier_speed, dtype=torch.float32, device=device),
+                    torch.tensor(1.0, dtype=torch.float32, device=device))
+    return F.contiguous(), _grid_h(n), L["src"], np.zeros(n_sources)
 
 
 def bumps(n: int = 1025, seed: int = 4, n_bumps: int = 32, cell: int = 8, tol: float = 0.0,
