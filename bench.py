@@ -100,6 +100,10 @@ def main():
     ap.add_argument("--inner", type=int, default=0,
                     help="in-cell solver: 0 default, 1 sweeps, 2 active-list, 3 dual sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="requests of the mixed-size serving stream (0: skip the serving leg)")
+    ap.add_argument("--serving-rounds", type=int, default=16,
+                    help="worklist rounds per server step in the serving leg")
     ap.add_argument("--copy-reference-mib", type=int, default=0,
                     help="only run plain device-to-device copies of this many MiB (calibrates "
                          "the HBM byte counters of a profiler against a known size)")
@@ -207,7 +211,34 @@ def main():
                 raise SystemExit(f"sample solve failed: {eik.strerror(rcq)}")
             return uq.cpu().numpy()
         line["cpu_baseline"] = cpu_baseline(args, gpu_solve)
+    if args.serving_requests > 0:
+        del F, u
+        torch.cuda.empty_cache()
+        line["serving"] = serving_leg(args)
     print(json.dumps(line), flush=True)
+
+
+def serving_leg(args):
+    """The mixed-size request stream (33..257 nodes per side, barrier mazes, 1-4 exits) through
+    the continuous-batching server, against one-at-a-time solves of the same stream."""
+    from paper_1306_4743_amd import serve
+    r = serve.serve_benchmark(args.serving_requests, rounds=args.serving_rounds, cell=args.cell,
+                              log=sys.stderr)
+    sat, one = r["saturated"], r["one_at_a_time_saturated"]
+    pick = ("p50_ms", "p99_ms", "requests_per_s", "arrival_rate_per_s")
+    return {
+        "workload": f"{r['requests']} requests, n uniform over {r['sizes']}, barrier mazes seed "
+                    f"5000+i, 1-4 exits, FP32 speeds, FP64 values, tol 0, inputs resident",
+        "rounds_per_step": r["rounds_per_step"], "pool_bytes": r["pool_bytes"],
+        "saturated_requests_per_s": sat["requests_per_s"],
+        "saturated_solved_nodes_per_s": sat["solved_nodes_per_s"],
+        "poisson": {f: {k: v[k] for k in pick} for f, v in r["poisson"].items()},
+        "one_at_a_time_requests_per_s": one["requests_per_s"],
+        "one_at_a_time_solved_nodes_per_s": one["solved_nodes_per_s"],
+        "one_at_a_time_poisson": {f: {k: v[k] for k in pick}
+                                  for f, v in r["one_at_a_time_poisson"].items()},
+        "max_rel_diff_served_vs_alone": r["max_rel_diff_served_vs_alone"],
+    }
 
 
 if __name__ == "__main__":

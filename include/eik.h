@@ -164,6 +164,34 @@ int eik_stream_status(hipStream_t stream, eik_stats* stats);
  * negative code. */
 int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_ms);
 
+/* One configuration tried by eik_autotune and its time. */
+typedef struct eik_tune_entry {
+    int cell;             /* r: 4 or 8                                                        */
+    int inner;            /* EIK_INNER_SWEEP, EIK_INNER_LIST or EIK_INNER_DUAL                 */
+    int workers;          /* persistent workgroups (0 = as many as fit)                        */
+    double delta;         /* priority band width (0 = every queued cell each round)            */
+    double ms;            /* fastest of `reps` whole eik_solve_ex calls (stream events);       */
+                          /* +inf if the configuration did not finish with EIK_OK               */
+    int status;           /* device status of its last run                                    */
+} eik_tune_entry;
+
+/*
+ * eik_autotune -- time the solver's configurations on one problem and return the fastest.
+ * The best cell size, in-cell solver, worker count and priority band depend on the problem
+ * (Section 6 finds the best cell size problem-dependent), so they are measured, not guessed:
+ * every combination of r in {8, 4}, inner in {SWEEP, LIST, DUAL} and workers in {all, one
+ * workgroup per CU} with no band, then the best of those with bands of 4 and 16 cell crossings
+ * (delta = 4 r h, 16 r h).  Each configuration is solved once to warm up and `reps` (1..100)
+ * times timed; the problem's arguments are those of eik_solve_ex (u_out receives the result of
+ * the last run; every configuration computes the same U up to rounding).  Blocks until done.
+ * table (cap entries, may be NULL if cap = 0) receives every configuration tried, *n_out their
+ * number (may be NULL); *best the fastest one.  Returns EIK_OK, EIK_EINVAL (invalid problem or
+ * arguments), a host error, or EIK_ECANCELLED if no configuration finished with EIK_OK.
+ */
+int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
+                 const eik_sources* sources, double* u_out, double tol, hipStream_t stream,
+                 int reps, eik_tune_entry* table, int cap, int* n_out, eik_tune_entry* best);
+
 /* One problem of a batch or of a server: the arguments of eik_solve for one grid. */
 typedef struct eik_problem {
     int64_t dims[3];      /* as in eik_solve                                                  */

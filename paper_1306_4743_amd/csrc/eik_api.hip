@@ -577,6 +577,96 @@ int eik_solve_batch(int n, const eik_problem* problems, int f_dtype, int cell, h
     return solve_batch_impl(n, problems, f_dtype, cell, stream, options);
 }
 
+int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
+                 const eik_sources* sources, double* u_out, double tol, hipStream_t stream,
+                 int reps, eik_tune_entry* table, int cap, int* n_out, eik_tune_entry* best) {
+    if (!best || reps < 1 || reps > 100 || cap < 0 || (cap > 0 && !table)) return EIK_EINVAL;
+    int rc = EIK_OK;
+    // Synchronous validation of the problem once (cell 8 and 4 accept the same problems).
+    {
+        eik_problem pb;
+        std::memset(&pb, 0, sizeof(pb));
+        if (!dims || !sources) return EIK_EINVAL;
+        for (int a = 0; a < 3; ++a) pb.dims[a] = dims[a];
+        pb.h = h;
+        pb.F = F;
+        pb.sources = *sources;
+        pb.u_out = u_out;
+        pb.tol = tol;
+        if ((rc = validate_problem(pb, f_dtype)) != EIK_OK) return rc;
+    }
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (auto& x : ev)
+        if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(e);
+    std::vector<eik_tune_entry> cand;
+    const int cells[2] = {8, 4};
+    const int inners[3] = {EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL};
+    for (int cell : cells)
+        for (int inner : inners)
+            for (int workers : {0, ncu}) {
+                eik_tune_entry t;
+                std::memset(&t, 0, sizeof(t));
+                t.cell = cell;
+                t.inner = inner;
+                t.workers = workers;
+                t.delta = 0.0;
+                cand.push_back(t);
+            }
+    auto run = [&](eik_tune_entry& t) -> int {
+        eik_options o;
+        std::memset(&o, 0, sizeof(o));
+        o.inner = t.inner;
+        o.workers = t.workers;
+        o.delta = t.delta;
+        t.ms = INFINITY;
+        for (int k = 0; k <= reps; ++k) {  // run 0 warms up
+            hipError_t ee = hipEventRecord(ev[0], stream);
+            if (ee != hipSuccess) return hip_fail(ee);
+            int r = eik_solve_ex(dims, h, F, f_dtype, sources, u_out, t.cell, tol, stream, &o);
+            if (r != EIK_OK) return r;
+            if ((ee = hipEventRecord(ev[1], stream)) != hipSuccess) return hip_fail(ee);
+            const int st = eik_stream_status(stream, nullptr);
+            t.status = st;
+            if (st != EIK_OK) return EIK_OK;  // recorded; this candidate is not eligible
+            float ms = 0.f;
+            if ((ee = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess) return hip_fail(ee);
+            if (k > 0 && ms < t.ms) t.ms = ms;
+        }
+        return EIK_OK;
+    };
+    int ibest = -1;
+    for (size_t i = 0; i < cand.size() && rc == EIK_OK; ++i) {
+        rc = run(cand[i]);
+        if (rc == EIK_OK && cand[i].status == EIK_OK &&
+            (ibest < 0 || cand[i].ms < cand[(size_t)ibest].ms))
+            ibest = (int)i;
+    }
+    // Priority bands around the best configuration: widths of 4 and 16 cell crossings (r h).
+    if (rc == EIK_OK && ibest >= 0) {
+        const eik_tune_entry b = cand[(size_t)ibest];
+        for (double m : {4.0, 16.0}) {
+            eik_tune_entry t = b;
+            t.delta = m * b.cell * h;
+            rc = run(t);
+            if (rc != EIK_OK) break;
+            cand.push_back(t);
+            if (t.status == EIK_OK && t.ms < cand[(size_t)ibest].ms) ibest = (int)cand.size() - 1;
+        }
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (rc != EIK_OK) return rc;
+    if (ibest < 0) return EIK_ECANCELLED;
+    *best = cand[(size_t)ibest];
+    const int n = std::min<int>(cap, (int)cand.size());
+    for (int i = 0; i < n; ++i) table[i] = cand[(size_t)i];
+    if (n_out) *n_out = n;
+    return EIK_OK;
+}
+
 int eik_stream_status(hipStream_t stream, eik_stats* stats) {
     Workspace* w = find_workspace(stream);
     if (!w || !w->used) return EIK_EINVAL;

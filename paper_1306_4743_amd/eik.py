@@ -45,6 +45,14 @@ class Problem(ctypes.Structure):
                 ("sources", Sources), ("u_out", ctypes.c_void_p), ("tol", ctypes.c_double)]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_int), ("inner", ctypes.c_int), ("workers", ctypes.c_int),
+                ("delta", ctypes.c_double), ("ms", ctypes.c_double), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("rounds", "visits", "sweeps", "updates", "deferred", "requeued", "cells",
@@ -61,8 +69,8 @@ _lib = None
 EXPORTS = ("eik_solve", "eik_solve_ex", "eik_query_workspace", "eik_problem_bytes",
            "eik_stream_status", "eik_kernel_times", "eik_solve_batch", "eik_batch_status",
            "eik_server_create", "eik_server_submit", "eik_server_step", "eik_server_poll",
-           "eik_server_load", "eik_server_destroy", "eik_strerror", "eik_release",
-           "eik_version")
+           "eik_server_load", "eik_server_destroy", "eik_autotune", "eik_strerror",
+           "eik_release", "eik_version")
 
 
 def load():
@@ -111,6 +119,10 @@ def load():
     lib.eik_server_load.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64),
                                     ctypes.POINTER(ctypes.c_size_t)]
     lib.eik_server_load.restype = i32
+    lib.eik_autotune.argtypes = [vp, dbl, vp, i32, ctypes.POINTER(Sources), vp, dbl, vp, i32,
+                                 ctypes.POINTER(TuneEntry), i32, ctypes.POINTER(i32),
+                                 ctypes.POINTER(TuneEntry)]
+    lib.eik_autotune.restype = i32
     lib.eik_server_destroy.argtypes = [vp]
     lib.eik_server_destroy.restype = i32
     _lib = lib
@@ -246,6 +258,28 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
     if rc != EIK_OK and check:
         raise EikError(rc, "eik_solve: ")
     return u_out
+
+
+def autotune(F, h: float, idx3, q, tol: float = 0.0, reps: int = 2, u_out=None, stream=None):
+    """Time every solver configuration on this problem (eik_autotune); returns (best, table)
+    as dicts with keys cell, inner, workers, delta, ms, status.  Blocks until done."""
+    lib = load()
+    f_dtype = _f_dtype(F)
+    u_out = _out_tensor(F, u_out)
+    src, keep = _sources(F, idx3, q, stream)
+    nz, ny, nx = F.shape
+    dims = _dims_array((nx, ny, nz))
+    table = (TuneEntry * 32)()
+    n = ctypes.c_int(0)
+    best = TuneEntry()
+    rc = lib.eik_autotune(ctypes.cast(dims, ctypes.c_void_p), float(h),
+                          ctypes.c_void_p(F.data_ptr()), f_dtype, ctypes.byref(src),
+                          ctypes.c_void_p(u_out.data_ptr()), float(tol), _stream_handle(stream),
+                          int(reps), table, 32, ctypes.byref(n), ctypes.byref(best))
+    del keep
+    if rc != EIK_OK:
+        raise EikError(rc, "eik_autotune: ")
+    return best.as_dict(), [table[i].as_dict() for i in range(n.value)]
 
 
 def problem_bytes(dims, cell: int = 8, f_dtype: int = EIK_F32) -> int:

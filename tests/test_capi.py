@@ -165,3 +165,26 @@ def test_server_calls_reject_null_server():
     assert lib.eik_server_poll(None, 0, None, None, ctypes.byref(n)) == eik.EIK_EINVAL
     assert lib.eik_server_load(None, None, None, None) == eik.EIK_EINVAL
     assert lib.eik_server_destroy(None) == eik.EIK_EINVAL
+
+
+def test_autotune_rejects_invalid():
+    lib = eik.load()
+    idx = np.zeros((1, 3), dtype=np.int64)
+    q = np.zeros(1)
+    src = eik.Sources(1, idx.ctypes.data, q.ctypes.data, 0)
+    best = eik.TuneEntry()
+    n = ctypes.c_int(0)
+    table = (eik.TuneEntry * 4)()
+    d = (ctypes.c_int64 * 3)(8, 8, 8)
+    dp = ctypes.cast(d, ctypes.c_void_p)
+    call = lambda **k: lib.eik_autotune(
+        k.get("dims", dp), k.get("h", 0.1), ctypes.c_void_p(k.get("F", 1)), 0, ctypes.byref(src),
+        ctypes.c_void_p(1), 0.0, None, k.get("reps", 1), k.get("table", table), k.get("cap", 4),
+        ctypes.byref(n), k.get("best", ctypes.byref(best)))
+    assert call(reps=0) == eik.EIK_EINVAL
+    assert call(reps=101) == eik.EIK_EINVAL
+    assert call(best=None) == eik.EIK_EINVAL
+    assert call(table=None, cap=3) == eik.EIK_EINVAL
+    assert call(h=-1.0) == eik.EIK_EINVAL
+    assert call(F=0) == eik.EIK_EINVAL
+    assert call(dims=None) == eik.EIK_EINVAL

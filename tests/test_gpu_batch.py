@@ -231,3 +231,22 @@ def test_server_rejects_grid_that_never_fits(torch_dev):
     with pytest.raises(eik.EikError):
         srv.submit(torch.from_numpy(p.F).to(torch_dev), p.h, p.src, p.q)
     srv.close()
+
+
+def test_autotune_picks_a_valid_configuration(orc, torch_dev):
+    """The autotuner tries every configuration, each one reaches EIK_OK, the fastest is
+    returned, and the problem's result is the oracle's."""
+    import torch
+    from paper_1306_4743_amd import eik
+    p = W.maze(65, seed=4, n_sources=2)
+    F = torch.from_numpy(p.F).to(torch_dev)
+    best, table = eik.autotune(F, p.h, p.src, p.q, reps=1)
+    assert len(table) == 14
+    assert {(t["cell"], t["inner"]) for t in table} == {(c, i) for c in (8, 4) for i in (1, 2, 3)}
+    assert all(t["status"] == 0 and 0 < t["ms"] < 1e4 for t in table)
+    assert best["ms"] == min(t["ms"] for t in table)
+    u = eik.solve(F, p.h, p.src, p.q, cell=best["cell"], inner=best["inner"],
+                  workers=best["workers"], delta=best["delta"])
+    assert eik.status()[0] == 0
+    compare(u.cpu().numpy(), orc.fmm(p.F, p.h, p.src, p.q), p)
+    print("autotune best", best, flush=True)
