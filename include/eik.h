@@ -55,6 +55,16 @@ extern "C" {
 
 /* Arithmetic modes (eik_options.mode). */
 #define EIK_MODE_FP64 0  /* all storage and arithmetic in FP64                            */
+/* Values stored, swept and solved in FP32 throughout (the single-precision variant of Section 6:
+ * the same method with single-precision data and intermediates); the result is widened to FP64
+ * in u_out.  Its accuracy is that of FP32 arithmetic accumulated along characteristics (about
+ * 1e-6 relative on the grids here), not the FP64 bar; exit values are rounded to FP32. */
+#define EIK_MODE_FP32 1
+/* FP32 bulk, FP64 polish: the method runs in EIK_MODE_FP32, its result is lifted above the FP64
+ * solution (times 1 + 2^-12) and every cell is then swept again in FP64 from there (values only
+ * decrease, so the FP64 iteration ends at the FP64 solution).  Same accuracy as EIK_MODE_FP64.
+ * Single solves and batches only (not servers). */
+#define EIK_MODE_MIXED 2
 
 /* In-cell solvers (eik_options.inner).  All solve the cell sub-problem of Section 4 exactly:
  *   EIK_INNER_SWEEP  locking sweeps (Algorithm 3) in the 8 directions, each sweep visiting the
@@ -149,8 +159,9 @@ int eik_solve_ex(const int64_t dims[3], double h, const void* F, int f_dtype,
  * f_dtype as in eik_solve.  Returns EIK_OK or EIK_EINVAL. */
 int eik_query_workspace(const int64_t dims[3], int cell, int f_dtype, int mode, size_t* bytes);
 
-/* Device bytes of one grid's arrays inside a server pool (values, speeds, face copies). */
-int eik_problem_bytes(const int64_t dims[3], int cell, int f_dtype, size_t* bytes);
+/* Device bytes of one grid's arrays inside a server pool (values, speeds, face copies) in the
+ * given mode (EIK_MODE_*).  Returns EIK_OK or EIK_EINVAL. */
+int eik_problem_bytes(const int64_t dims[3], int cell, int f_dtype, int mode, size_t* bytes);
 
 /* Waits for all work on `stream`, then returns the device-side status of the last solve
  * enqueued on it (EIK_OK, EIK_EINVAL, EIK_ENOCONV, EIK_ECANCELLED) and, if stats != NULL,

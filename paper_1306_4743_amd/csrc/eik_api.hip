@@ -43,14 +43,20 @@ bool valid_dims(const int64_t* dims) {
 }
 
 // Cells and array sizes of one grid.
+// Mixed precision keeps FP32 copies of the values and faces (u32_bytes, faces32_bytes) for the
+// single-precision phase beside the FP64 ones.
 struct GridSize {
     int ncx = 0, ncy = 0, ncz = 0;
     int64_t ncell = 0;
-    size_t u_bytes = 0, f_bytes = 0, faces_bytes = 0;
-    size_t bytes() const { return align_up(u_bytes) + align_up(f_bytes) + align_up(faces_bytes); }
+    size_t u_bytes = 0, f_bytes = 0, faces_bytes = 0, u32_bytes = 0, faces32_bytes = 0;
+    size_t bytes() const {
+        return align_up(u_bytes) + align_up(f_bytes) + align_up(faces_bytes) +
+               align_up(u32_bytes) + align_up(faces32_bytes);
+    }
 };
 
-bool grid_size(const int64_t dims[3], int cell, int f_dtype, GridSize* g) {
+// Storage of a mode: FP32 values for EIK_MODE_FP32, FP64 otherwise (plus FP32 copies if mixed).
+bool grid_size(const int64_t dims[3], int cell, int f_dtype, int mode, GridSize* g) {
     const int64_t r = cell;
     g->ncx = (int)((dims[0] + r - 1) / r);
     g->ncy = (int)((dims[1] + r - 1) / r);
@@ -58,9 +64,12 @@ bool grid_size(const int64_t dims[3], int cell, int f_dtype, GridSize* g) {
     g->ncell = (int64_t)g->ncx * g->ncy * g->ncz;
     if (g->ncell * r * r * r >= (int64_t(1) << 31)) return false;
     const size_t n = (size_t)g->ncell, r3 = (size_t)(r * r * r), r2 = (size_t)(r * r);
-    g->u_bytes = n * r3 * 8;
+    const size_t su = mode == EIK_MODE_FP32 ? 4 : 8;
+    g->u_bytes = n * r3 * su;
     g->f_bytes = n * r3 * (f_dtype == EIK_F32 ? 4 : 8);
-    g->faces_bytes = n * 6 * r2 * 8;
+    g->faces_bytes = n * 6 * r2 * su;
+    g->u32_bytes = mode == EIK_MODE_MIXED ? n * r3 * 4 : 0;
+    g->faces32_bytes = mode == EIK_MODE_MIXED ? n * 6 * r2 * 4 : 0;
     return true;
 }
 
@@ -108,7 +117,8 @@ void bind_common(SolveParams* P, unsigned char* base, const CommonLayout& L, int
 int parse_options(const eik_options* options, int cell, eik_options* opt, SolveParams* P) {
     std::memset(opt, 0, sizeof(*opt));
     if (options) *opt = *options;
-    if (opt->mode != EIK_MODE_FP64) return EIK_EINVAL;
+    if (opt->mode != EIK_MODE_FP64 && opt->mode != EIK_MODE_FP32 && opt->mode != EIK_MODE_MIXED)
+        return EIK_EINVAL;
     if (std::isnan(opt->delta) || opt->max_rounds < 0 || opt->max_sweeps < 0 || opt->workers < 0)
         return EIK_EINVAL;
     if (opt->round_log_len < 0 || (opt->round_log_len > 0 && !opt->round_log)) return EIK_EINVAL;
@@ -120,6 +130,7 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
     const int inner = opt->inner ? opt->inner : (cell == 8 ? EIK_INNER_SWEEP : EIK_INNER_LIST);
     P->inner = inner == EIK_INNER_SWEEP ? 0 : (inner == EIK_INNER_LIST ? 1 : 2);
     P->delta = opt->delta > 0.0 ? opt->delta : 0.0;
+    P->fp32 = opt->mode == EIK_MODE_FP32 ? 1 : 0;
     P->shuffle = opt->shuffle;
     P->watchdog_polls = 1ull << 23;  // several seconds of polling
     P->round_log = opt->round_log;
@@ -149,7 +160,7 @@ int validate_problem(const eik_problem& pb, int f_dtype) {
 }
 
 Slot make_slot(const eik_problem& pb, const GridSize& g, int cell_base, unsigned char* mem,
-               int* status_dev) {
+               int* status_dev, int fp32) {
     Slot S;
     std::memset(&S, 0, sizeof(S));
     S.nx = (int)pb.dims[0];
@@ -166,8 +177,24 @@ Slot make_slot(const eik_problem& pb, const GridSize& g, int cell_base, unsigned
     S.f = mem + align_up(g.u_bytes);
     S.faces = (double*)(mem + align_up(g.u_bytes) + align_up(g.f_bytes));
     S.status = status_dev;
+    S.fp32 = fp32;
     return S;
 }
+
+// The single-precision twin of a mixed-precision slot: same grid, speeds and cells, FP32 values.
+Slot fp32_twin(const Slot& S64, const GridSize& g) {
+    Slot S = S64;
+    unsigned char* mem = (unsigned char*)S64.u;
+    S.u = mem + align_up(g.u_bytes) + align_up(g.f_bytes) + align_up(g.faces_bytes);
+    S.faces = (unsigned char*)S.u + align_up(g.u32_bytes);
+    S.fp32 = 1;
+    return S;
+}
+
+// Relative margin of the lift from the FP32 result to an FP64 starting point above the
+// solution: 2^-12, about twenty times the largest relative FP32 error measured on the grids
+// here (1.3e-5).
+constexpr double kLiftFactor = 1.0 + 1.0 / 4096.0;
 
 // Pinned staging of host-side data (sources, slot tables); one buffer, reused after its last
 // copy finished.
@@ -369,13 +396,15 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
     int64_t nsrc_total = 0;
     for (int i = 0; i < n; ++i) {
         if ((rc = validate_problem(pbs[i], f_dtype)) != EIK_OK) return rc;
-        if (!grid_size(pbs[i].dims, cell, f_dtype, &gs[i])) return EIK_EINVAL;
+        if (!grid_size(pbs[i].dims, cell, f_dtype, opt.mode, &gs[i])) return EIK_EINVAL;
         cells += gs[i].ncell;
         grid_bytes += gs[i].bytes();
         nsrc_total += pbs[i].sources.n;
     }
     if (cells >= (int64_t(1) << 31)) return EIK_EINVAL;
-    const CommonLayout L = common_layout(cells, n);
+    const bool mixed = opt.mode == EIK_MODE_MIXED;
+    const int ntab = mixed ? 2 * n : n;  // slot table entries (FP64 slots, then FP32 twins)
+    const CommonLayout L = common_layout(cells, ntab);
 
     Workspace* w = get_workspace(stream, &rc);
     if (!w) return rc;
@@ -387,11 +416,12 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
     int* slot_status = (int*)(base + L.off_slot_status);
 
     // Slot table, built on the host and copied with the sources through one pinned buffer.
-    std::vector<Slot> slots((size_t)n);
+    std::vector<Slot> slots((size_t)ntab);
     size_t off = L.total;
     int64_t cell_base = 0;
     for (int i = 0; i < n; ++i) {
-        slots[i] = make_slot(pbs[i], gs[i], (int)cell_base, base + off, slot_status + i);
+        slots[i] = make_slot(pbs[i], gs[i], (int)cell_base, base + off, slot_status + i, P.fp32);
+        if (mixed) slots[(size_t)n + i] = fp32_twin(slots[i], gs[i]);
         off += gs[i].bytes();
         cell_base += gs[i].ncell;
     }
@@ -414,21 +444,45 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
         ev = &w->ring[4 * (w->timed % Workspace::kRing)];
         w->timed++;
     }
+    // Mixed precision runs the method twice: in FP32 on the twins, then lifted and polished in
+    // FP64 (every cell queued with all nodes active, exits re-seeded with their exact values).
+    SolveParams P1 = P;
+    const Slot* first = slots.data();
+    if (mixed) {
+        P1.fp32 = 1;
+        P1.slots = P.slots + n;
+        first = slots.data() + n;
+    }
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return hip_fail(e);
     if ((e = eik::launch_init_global(P, stream)) != hipSuccess) return hip_fail(e);
     for (int i = 0; i < n; ++i) {
-        e = eik::launch_init_slot(P, slots[i], i, cell, f_dtype, pbs[i].F, stream);
+        e = eik::launch_init_slot(P1, first[i], i, cell, f_dtype, pbs[i].F, stream);
         if (e != hipSuccess) return hip_fail(e);
-        e = eik::launch_seed(P, slots[i], cell, f_dtype, 0, pbs[i].sources.n, refs[i].idx3,
+        e = eik::launch_seed(P1, first[i], cell, f_dtype, 0, pbs[i].sources.n, refs[i].idx3,
                              refs[i].q, stream);
         if (e != hipSuccess) return hip_fail(e);
     }
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return hip_fail(e);
     if (nsrc_total > 0) {
-        P.round_begin = 0;
-        P.round_end = P.max_rounds;
-        rc = ordered_solve(w->device, P, cell, f_dtype, stream, opt.workers);
+        P1.round_begin = 0;
+        P1.round_end = P1.max_rounds;
+        rc = ordered_solve(w->device, P1, cell, f_dtype, stream, opt.workers);
         if (rc != EIK_OK) return rc;
+        if (mixed) {
+            if ((e = eik::launch_reset_rounds(P, stream)) != hipSuccess) return hip_fail(e);
+            for (int i = 0; i < n; ++i) {
+                if ((e = eik::launch_lift(first[i], slots[i], cell, kLiftFactor, stream)) !=
+                        hipSuccess ||
+                    (e = eik::launch_seed(P, slots[i], cell, f_dtype, 0, pbs[i].sources.n,
+                                          refs[i].idx3, refs[i].q, stream)) != hipSuccess ||
+                    (e = eik::launch_queue_all(P, slots[i], 0, stream)) != hipSuccess)
+                    return hip_fail(e);
+            }
+            P.round_begin = 0;
+            P.round_end = P.max_rounds;
+            rc = ordered_solve(w->device, P, cell, f_dtype, stream, opt.workers);
+            if (rc != EIK_OK) return rc;
+        }
     }
     if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return hip_fail(e);
     for (int i = 0; i < n; ++i)
@@ -530,24 +584,24 @@ const char* eik_strerror(int code) {
 
 const char* eik_version(void) { return "eik-mi355x 0.2 (gfx950)"; }
 
-int eik_problem_bytes(const int64_t dims[3], int cell, int f_dtype, size_t* bytes) {
+int eik_problem_bytes(const int64_t dims[3], int cell, int f_dtype, int mode, size_t* bytes) {
     if (!bytes || !valid_dims(dims) || (cell != 4 && cell != 8) ||
-        (f_dtype != EIK_F32 && f_dtype != EIK_F64))
+        (f_dtype != EIK_F32 && f_dtype != EIK_F64) ||
+        (mode != EIK_MODE_FP64 && mode != EIK_MODE_FP32 && mode != EIK_MODE_MIXED))
         return EIK_EINVAL;
     GridSize g;
-    if (!grid_size(dims, cell, f_dtype, &g)) return EIK_EINVAL;
+    if (!grid_size(dims, cell, f_dtype, mode, &g)) return EIK_EINVAL;
     *bytes = g.bytes();
     return EIK_OK;
 }
 
 int eik_query_workspace(const int64_t dims[3], int cell, int f_dtype, int mode, size_t* bytes) {
-    if (mode != EIK_MODE_FP64) return EIK_EINVAL;
     size_t grid = 0;
-    int rc = eik_problem_bytes(dims, cell, f_dtype, &grid);
+    int rc = eik_problem_bytes(dims, cell, f_dtype, mode, &grid);
     if (rc != EIK_OK) return rc;
     GridSize g;
-    grid_size(dims, cell, f_dtype, &g);
-    *bytes = common_layout(g.ncell, 1).total + grid;
+    grid_size(dims, cell, f_dtype, mode, &g);
+    *bytes = common_layout(g.ncell, mode == EIK_MODE_MIXED ? 2 : 1).total + grid;
     return EIK_OK;
 }
 
@@ -776,6 +830,7 @@ int eik_server_create(eik_server** out, size_t pool_bytes, int64_t max_cells, in
         return EIK_EINVAL;
     eik_server* s = new eik_server();
     int rc = parse_options(options, cell, &s->opt, &s->P);
+    if (rc == EIK_OK && s->opt.mode == EIK_MODE_MIXED) rc = EIK_EINVAL;  // one precision per server
     if (rc != EIK_OK) { delete s; return rc; }
     hipError_t e = hipGetDevice(&s->device);
     if (e != hipSuccess) { delete s; return hip_fail(e); }
@@ -810,7 +865,7 @@ int eik_server_submit(eik_server* s, const eik_problem* pb, int64_t* ticket) {
     int rc = validate_problem(*pb, s->f_dtype);
     if (rc != EIK_OK) return rc;
     GridSize g;
-    if (!grid_size(pb->dims, s->cell, s->f_dtype, &g)) return EIK_EINVAL;
+    if (!grid_size(pb->dims, s->cell, s->f_dtype, s->opt.mode, &g)) return EIK_EINVAL;
     if (g.ncell > s->max_cells || g.bytes() > s->pool_bytes) return EIK_EINVAL;  // never fits
     int slot = -1;
     for (int i = 0; i < s->max_problems; ++i)
@@ -831,7 +886,7 @@ int eik_server_submit(eik_server* s, const eik_problem* pb, int64_t* ticket) {
     p.g = g;
     p.pool_off = poff;
     int* slot_status = (int*)((unsigned char*)s->base + s->layout.off_slot_status) + slot;
-    p.slot = make_slot(*pb, g, (int)cbase, (unsigned char*)s->pool + poff, slot_status);
+    p.slot = make_slot(*pb, g, (int)cbase, (unsigned char*)s->pool + poff, slot_status, s->P.fp32);
     s->fresh.push_back(slot);
     s->pool_used += g.bytes();
     s->cells_used += g.ncell;

@@ -61,16 +61,19 @@ struct Slot {
     int cell_base;         // global id of the slot's cell 0
     int ncell;             // ncx * ncy * ncz
     double h, tol;
-    double* u;             // [ncell][r^3] cell-blocked values
+    void* u;               // [ncell][r^3] cell-blocked values (FP64, or FP32 if fp32)
     void* f;               // [ncell][r^3] cell-blocked speeds (F dtype); 0 padding, <0 exit
-    double* faces;         // [ncell][6][r^2] border layers
+    void* faces;           // [ncell][6][r^2] border layers (value type of u)
     int* status;           // this grid's status word (device)
-    int pad[2];
+    int fp32;              // values stored and computed in single precision
+    int pad;
 };
 
 struct SolveParams {
     int max_sweeps;
     int inner;             // in-cell solver: 0 sweeps, 1 active-list relaxation, 2 dual sweeps
+    int fp32;              // value type of every slot of the launch: 1 FP32, 0 FP64
+    int pad0;
     int64_t round_begin;   // first round of this launch
     int64_t round_end;     // the launch stops after round round_end - 1 (end of an epoch)
     int64_t max_rounds;    // absolute cap on rounds -> EIK_ENOCONV
@@ -100,6 +103,12 @@ hipError_t launch_seed(const SolveParams& P, const Slot& S, int cell, int f_dtyp
 hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipStream_t s,
                                int workers, int* used);
 hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s);
+// Mixed precision: FP64 values (and faces) of S64 <- FP32 ones of S32 times factor.
+hipError_t launch_lift(const Slot& S32, const Slot& S64, int cell, double factor, hipStream_t s);
+// Every cell of slot S queued for round `round` with all nodes active.
+hipError_t launch_queue_all(const SolveParams& P, const Slot& S, int64_t round, hipStream_t s);
+// Round lists emptied and the round counter reset (launch status and counters kept).
+hipError_t launch_reset_rounds(const SolveParams& P, hipStream_t s);
 // Cells of each slot queued for the first round of the next launch (P.next_round).
 hipError_t launch_slot_counts(const SolveParams& P, int* counts, int nslots, hipStream_t s);
 

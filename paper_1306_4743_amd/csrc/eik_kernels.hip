@@ -138,6 +138,18 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 __device__ __forceinline__ double wave_min(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
@@ -196,26 +208,62 @@ __device__ __forceinline__ double vmin_abs(double a, double b) {
     return r;
 }
 
+__device__ __forceinline__ float vmin(float a, float b) {
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float vmax(float a, float b) {
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float vmin_abs(float a, float b) {
+    float r;
+    asm("v_min_f32 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // Local solve of eq. (2): the smallest U with sum_k max(U - m_k, 0)^2 = s^2 given the upwind
-// axis values m_k (+inf when absent).  Sorted a <= b <= c: the one-term root a + s holds if it
-// does not exceed b, else the two-term root if it does not exceed c, else the three-term root.
-// The discriminants are in difference form (no cancellation of O(U^2) quantities); the
-// three-term one is symmetric in the m_k, so it is formed from the unsorted values in parallel
-// with the sort.  All three candidates are computed and the valid one selected; a candidate
-// whose guard fails may be NaN (when b or c is +inf) and is never selected.
+// axis values m_k (+inf when absent).  With a <= b <= c sorted, g(U) = sum_k max(U - m_k, 0)^2
+// is increasing, so the root uses exactly the values below it: one term (a + s) if that does
+// not exceed b, else two terms if g restricted to {a, b} reaches s^2 at c, i.e.
+// (c - a)^2 + (c - b)^2 >= s^2, else three.  The term count is decided first, so one square
+// root serves all cases.  Discriminants are in difference form (no cancellation of O(U^2)
+// quantities): k s^2 - sum over pairs of the used values of (m_i - m_j)^2.  With b or c = +inf
+// the comparisons select the terms that stay finite.
 __device__ __forceinline__ double local_solve(double m0, double m1, double m2, double s) {
     const double t1 = vmin(m0, m1), t2 = vmax(m0, m1);
     const double t3 = vmin(t2, m2), c = vmax(t2, m2);
     const double a = vmin(t1, t3), b = vmax(t1, t3);
     const double ss = s * s;
-    const double d01 = m0 - m1, d02 = m0 - m2, d12 = m1 - m2;
-    const double d3 = vmax(fma(3.0, ss, -fma(d01, d01, fma(d02, d02, d12 * d12))), 0.0);
-    const double u3 = (m0 + m1 + m2 + disc_sqrt(d3)) * (1.0 / 3.0);
-    const double dab = a - b;
-    const double d2 = fma(2.0, ss, -dab * dab);
-    const double u2 = 0.5 * (a + b + disc_sqrt(d2));
     const double u1 = a + s;
-    return u1 <= b ? u1 : (u2 <= c ? u2 : u3);
+    const double dab = b - a, dca = c - a, dcb = c - b;
+    const bool two = fma(dca, dca, dcb * dcb) >= ss;
+    const double d2 = fma(-dab, dab, 2.0 * ss);
+    const double d3 = fma(-dca, dca, fma(-dcb, dcb, fma(-dab, dab, 3.0 * ss)));
+    const double sum = two ? a + b : (a + b) + c;
+    const double u = (sum + disc_sqrt(two ? d2 : d3)) * (two ? 0.5 : (1.0 / 3.0));
+    return u1 <= b ? u1 : u;
+}
+
+// The same local solve in single precision throughout (the single-precision variant of
+// Section 6): same term selection, same difference-form discriminants, hardware square root
+// (within one ulp of the FP32 result).
+__device__ __forceinline__ float fsqrt_pos(float d) { return d > 0.f ? __builtin_amdgcn_sqrtf(d) : 0.f; }
+__device__ __forceinline__ float local_solve(float m0, float m1, float m2, float s) {
+    const float t1 = vmin(m0, m1), t2 = vmax(m0, m1);
+    const float t3 = vmin(t2, m2), c = vmax(t2, m2);
+    const float a = vmin(t1, t3), b = vmax(t1, t3);
+    const float ss = s * s;
+    const float u1 = a + s;
+    const float dab = b - a, dca = c - a, dcb = c - b;
+    const bool two = fmaf(dca, dca, dcb * dcb) >= ss;
+    const float d2 = fmaf(-dab, dab, 2.f * ss);
+    const float d3 = fmaf(-dca, dca, fmaf(-dcb, dcb, fmaf(-dab, dab, 3.f * ss)));
+    const float sum = two ? a + b : (a + b) + c;
+    const float u = (sum + fsqrt_pos(two ? d2 : d3)) * (two ? 0.5f : (1.f / 3.f));
+    return u1 <= b ? u1 : u;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -268,12 +316,12 @@ constexpr int INNER_SWEEP = 0;  // locking sweeps in diagonal-plane order (Algor
 constexpr int INNER_LIST = 1;   // relaxation over a compacted list of active nodes
 constexpr int INNER_DUAL = 2;   // two sweep streams on one cell, half a sweep apart
 
-template <int R, int INNER>
+template <int R, int INNER, typename UT>
 struct WaveLds {
     static constexpr int B = R + 2;
     static constexpr int BOX = B * B * B;
-    double U[BOX];        // cell values with a one-node halo (edges/corners unused)
-    double S[R * R * R];  // s = h/F; -1 marks an exit node, 0 a padding node
+    UT U[BOX];            // cell values with a one-node halo (edges/corners unused)
+    UT S[R * R * R];      // s = h/F; -1 marks an exit node, 0 a padding node
     int32_t q[64];        // cells newly queued for the next round, not yet published
     uint16_t lst[INNER == INNER_LIST ? 2 : 0][R * R * R];  // lists of the list relaxation
     uint8_t A[INNER == INNER_DUAL ? ((BOX + 7) & ~7) : 0];  // active flags of the dual sweep
@@ -322,6 +370,7 @@ __device__ __forceinline__ void load_plane_regs(PlaneRegs<R>& pr, int lane) {
 }
 
 __device__ __forceinline__ bool is_active(double v) { return __double_as_longlong(v) < 0; }
+__device__ __forceinline__ bool is_active(float v) { return __float_as_int(v) < 0; }
 
 // ------------------------------------------------------------------------------------------
 // Tagging a neighbour cell for the next round (Algorithm 2 "for each c_k in DN", with Set Cell
@@ -348,9 +397,9 @@ struct WaveQueue {
     double minkey;  // per-lane smallest value tagged this round (used with a priority band)
 };
 
-template <int R, int INNER>
+template <int R, int INNER, typename UT>
 __device__ __forceinline__ void queue_flush(const SolveParams& P, int nxt, RoundCtl* ctl_next,
-                                            WaveLds<R, INNER>& L, int lane, WaveQueue& wq) {
+                                            WaveLds<R, INNER, UT>& L, int lane, WaveQueue& wq) {
     if (wq.n == 0) return;
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&ctl_next->count, (uint32_t)wq.n);
@@ -362,9 +411,9 @@ __device__ __forceinline__ void queue_flush(const SolveParams& P, int nxt, Round
 
 // Every lane with do_tag set tags one cell (any lanes, in parallel): cell value <- min(value),
 // flags |= bits | QUEUED, and the cell joins the next round's list unless already queued.
-template <int R, int INNER>
+template <int R, int INNER, typename UT>
 __device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCtl* ctl_next,
-                                          WaveLds<R, INNER>& L, int lane, WaveQueue& wq, bool do_tag,
+                                          WaveLds<R, INNER, UT>& L, int lane, WaveQueue& wq, bool do_tag,
                                           int target, uint32_t bits, double value) {
     bool newq = false;
     if (do_tag) {
@@ -376,7 +425,7 @@ __device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCt
     const uint64_t mask = __ballot(newq);
     const int k = __popcll(mask);
     if (k == 0) return;
-    if (wq.n + k > 64) queue_flush<R, INNER>(P, nxt, ctl_next, L, lane, wq);
+    if (wq.n + k > 64) queue_flush<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq);
     if (newq) {
         const int rank = __popcll(mask & ((1ull << lane) - 1ull));
         L.q[wq.n + rank] = target;
@@ -404,22 +453,24 @@ __device__ __forceinline__ int face_step(int f) {
     return dir * (axis == 0 ? 1 : (axis == 1 ? B : B * B));
 }
 
-template <int R, typename FT, int INNER>
+template <int R, typename FT, int INNER, typename UT>
 __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t fl,
-                                           double popped_key, WaveLds<R, INNER>& L,
+                                           double popped_key, WaveLds<R, INNER, UT>& L,
                                            const PlaneRegs<R>& pr, int lane,
                                            RoundCtl* ctl_next, int nxt, VisitCounters& cnt,
                                            WaveQueue& wq) {
     constexpr int R2 = R * R, R3 = R * R * R, B = R + 2, NP = 3 * R - 2;
     constexpr int BOFF = 1 + B + B * B;
-    const double INF = __builtin_inf();
+    const UT INF = (UT)__builtin_inf();
     const unsigned long long t0 = cycles();
     // The cell's grid (slot) and its local index there; c itself is a global cell id.
     c = __builtin_amdgcn_readfirstlane(c);
     const Slot S = P.slots[P.cell_slot[c]];
     const int lc = c - S.cell_base;
     const CellXYZ cc = cell_coords(S, lc);
-    const double* __restrict__ ug = S.u + (size_t)lc * R3;
+    const UT* __restrict__ ug = reinterpret_cast<const UT*>(S.u) + (size_t)lc * R3;
+    const UT* __restrict__ faces = reinterpret_cast<const UT*>(S.faces);
+    const UT hh = (UT)S.h;
     const FT* __restrict__ fg = reinterpret_cast<const FT*>(S.f) + (size_t)lc * R3;
 
     // Stage in: cell values and s = h/F.
@@ -427,7 +478,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         const int x = l % R, y = (l / R) % R, z = l / R2;
         L.U[box_index<R>(x, y, z)] = ug[l];
         const FT fv = fg[l];
-        L.S[l] = fv > FT(0) ? S.h / (double)fv : (fv < FT(0) ? -1.0 : 0.0);
+        L.S[l] = fv > FT(0) ? hh / (UT)fv : (fv < FT(0) ? UT(-1) : UT(0));
     }
     // Halo: the neighbour's opposite face copy, +inf beyond the grid.
 #pragma unroll
@@ -436,7 +487,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         if (lane < R2) {
             int x, y, z;
             face_node<R>(f, lane % R, lane / R, x, y, z);
-            const double v = nb >= 0 ? S.faces[((size_t)nb * 6 + (f ^ 1)) * R2 + lane] : INF;
+            const UT v = nb >= 0 ? faces[((size_t)nb * 6 + (f ^ 1)) * R2 + lane] : INF;
             L.U[box_index<R>(x, y, z) + face_step<R>(f)] = v;
         }
     }
@@ -444,7 +495,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     // Border values before the visit (to detect which border nodes decrease), then the initial
     // active set: every node on a first / re-queued visit, otherwise the layer next to each face
     // that received new inflow.
-    double before[6];
+    UT before[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         before[f] = INF;
@@ -461,13 +512,13 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         else L.U[b] = -fabs(L.U[b]);
     };
     if constexpr (INNER == INNER_DUAL) {
-        for (int b = lane; b < WaveLds<R, INNER>::BOX; b += 64) L.A[b] = 0;
+        for (int b = lane; b < WaveLds<R, INNER, UT>::BOX; b += 64) L.A[b] = 0;
         wave_sync();
     }
     if (fl & FL_ALL) {
         for (int l = lane; l < R3; l += 64) {
             const int x = l % R, y = (l / R) % R, z = l / R2;
-            if (L.S[l] > 0.0) activate(box_index<R>(x, y, z));
+            if (L.S[l] > UT(0)) activate(box_index<R>(x, y, z));
         }
     } else {
 #pragma unroll
@@ -475,7 +526,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
             if ((fl & (1u << f)) && lane < R2) {
                 int x, y, z;
                 face_node<R>(f, lane % R, lane / R, x, y, z);
-                if (L.S[x + R * (y + R * z)] > 0.0) activate(box_index<R>(x, y, z));
+                if (L.S[x + R * (y + R * z)] > UT(0)) activate(box_index<R>(x, y, z));
             }
         }
     }
@@ -500,7 +551,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
             if (d < 0) d = kGray[(ci++) & 7];
             const int mx = (d & 1) ? R - 1 : 0, my = (d & 2) ? R - 1 : 0, mz = (d & 4) ? R - 1 : 0;
             bool changed = false;
-            double maxdec = 0.0;
+            UT maxdec = UT(0);
     #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 uint32_t e = (pr.pk[p >> 1] >> ((p & 1) * 16)) & 0xFFFFu;
@@ -511,11 +562,11 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                           z = (int)((e >> 10) & 31u) ^ mz;
                 const int b = x + B * (y + B * z) + BOFF;
                 const int l = x + R * (y + R * z);
-                double raw = L.U[b];
-                double s = L.S[l];
-                double xm = L.U[b - 1], xp = L.U[b + 1];
-                double ym = L.U[b - B], yp = L.U[b + B];
-                double zm = L.U[b - B * B], zp = L.U[b + B * B];
+                UT raw = L.U[b];
+                UT s = L.S[l];
+                UT xm = L.U[b - 1], xp = L.U[b + 1];
+                UT ym = L.U[b - B], yp = L.U[b + B];
+                UT zm = L.U[b - B * B], zp = L.U[b + B * B];
                 // Issue every LDS read of the step before the activity test: one LDS round trip.
                 asm volatile("" : "+v"(raw), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
                              "+v"(zm), "+v"(zp));
@@ -527,17 +578,19 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                     // a halo edge, which no node reads.  Two lanes never store different values
                     // to one node in one step (a plane's nodes are not neighbours of each other;
                     // activations of a shared neighbour agree).
-                    const double old = fabs(raw);
-                    xm = fabs(xm); xp = fabs(xp); ym = fabs(ym);
-                    yp = fabs(yp); zm = fabs(zm); zp = fabs(zp);
-                    const double g = local_solve(vmin(xm, xp), vmin(ym, yp), vmin(zm, zp), s);
-                    const bool live = act && s > 0.0;
+                    // Neighbour values are read through |.| (the abs modifier of the min); a
+                    // neighbour is activated if it is inactive (sign clear) and larger than the
+                    // new value, which the raw value tells in one comparison.
+                    const UT old = fabs(raw);
+                    const UT g = local_solve(vmin_abs(xm, xp), vmin_abs(ym, yp),
+                                             vmin_abs(zm, zp), s);
+                    const bool live = act && s > UT(0);
                     const bool dec = live && g < old;
                     upd += live ? 1u : 0u;
                     const int dm = pr.dummy;
                     L.U[act ? b : dm] = dec ? g : old;
                     changed |= dec;
-                    if (track_dec && dec) maxdec = fmax(maxdec, old - g);
+                    if (track_dec && dec) maxdec = vmax(maxdec, old - g);
                     L.U[(dec && xm > g) ? b - 1 : dm] = -xm;
                     L.U[(dec && xp > g) ? b + 1 : dm] = -xp;
                     L.U[(dec && ym > g) ? b - B : dm] = -ym;
@@ -559,7 +612,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                 left |= is_active(L.U[box_index<R>(x, y, z)]);
             }
             if (!__any(left)) break;
-            if (track_dec && wave_max(maxdec) <= S.tol) break;
+            if (track_dec && (double)wave_max(maxdec) <= S.tol) break;
             if (nsweeps >= P.max_sweeps) { requeue = true; break; }
         }
     } else if constexpr (INNER == INNER_DUAL) {
@@ -587,7 +640,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         int d1 = next_dir();
         if (__popc((uint32_t)(d0 ^ d1)) == 3) d1 = d0;
         bool done = false;
-        double maxdec = 0.0, dec_prev = 0.0;
+        UT maxdec = UT(0), dec_prev = UT(0);
         bool changed = false;
         const int dm = pr.dummy;
         while (!done) {
@@ -609,22 +662,22 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                 const int z = (int)((e >> 10) & 31u) ^ ((dd & 4) ? R - 1 : 0);
                 const int b = x + B * (y + B * z) + BOFF;
                 const int l = x + R * (y + R * z);
-                double old = L.U[b];
-                double s = L.S[l];
-                double xm = L.U[b - 1], xp = L.U[b + 1];
-                double ym = L.U[b - B], yp = L.U[b + B];
-                double zm = L.U[b - B * B], zp = L.U[b + B * B];
+                UT old = L.U[b];
+                UT s = L.S[l];
+                UT xm = L.U[b - 1], xp = L.U[b + 1];
+                UT ym = L.U[b - B], yp = L.U[b + B];
+                UT zm = L.U[b - B * B], zp = L.U[b + B * B];
                 uint32_t af = L.A[b];
                 asm volatile("" : "+v"(old), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
                              "+v"(zm), "+v"(zp), "+v"(af));
                 const bool act = ((pr.valid >> t) & 1u) && af != 0u;
                 if (__any(act)) {
-                    const double g = local_solve(vmin(xm, xp), vmin(ym, yp), vmin(zm, zp), s);
-                    const bool live = act && s > 0.0;
+                    const UT g = local_solve(vmin(xm, xp), vmin(ym, yp), vmin(zm, zp), s);
+                    const bool live = act && s > UT(0);
                     const bool dec = live && g < old;
                     upd += live ? 1u : 0u;
                     changed |= dec;
-                    if (track_dec && dec) maxdec = fmax(maxdec, old - g);
+                    if (track_dec && dec) maxdec = vmax(maxdec, old - g);
                     L.U[dec ? b : dm] = g;
                     L.A[act ? b : dm] = 0;
                     L.A[(dec && xm > g) ? b - 1 : dm] = 1;
@@ -647,8 +700,9 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                     }
                     // The tol test needs a complete sweep: the last NP steps hold one for the
                     // stream whose sweep began NP steps ago.
-                    const double dec_half = track_dec ? wave_max(maxdec) : 0.0;
-                    const bool small = track_dec && nsweeps >= 2 && fmax(dec_half, dec_prev) <= S.tol;
+                    const UT dec_half = track_dec ? wave_max(maxdec) : UT(0);
+                    const bool small =
+                        track_dec && nsweeps >= 2 && (double)vmax(dec_half, dec_prev) <= S.tol;
                     dec_prev = dec_half;
                     if (!__any(left) || small) {
                         done = true;
@@ -662,7 +716,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                         break;
                     }
                     changed = false;
-                    maxdec = 0.0;
+                    maxdec = UT(0);
                 }
             }
         }
@@ -691,29 +745,29 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         while (n_cur > 0) {
             int n_next = 0;
             bool changed = false;
-            double maxdec = 0.0;
+            UT maxdec = UT(0);
             for (int base = 0; base < n_cur; base += 64) {
                 const bool valid = base + lane < n_cur;
                 const int l = valid ? (int)L.lst[cur][base + lane] : 0;
                 const int x = l % R, y = (l / R) % R, z = l / R2;
                 const int b = x + B * (y + B * z) + BOFF;
-                double raw = L.U[b];
-                double s = L.S[l];
-                double xm = L.U[b - 1], xp = L.U[b + 1];
-                double ym = L.U[b - B], yp = L.U[b + B];
-                double zm = L.U[b - B * B], zp = L.U[b + B * B];
+                UT raw = L.U[b];
+                UT s = L.S[l];
+                UT xm = L.U[b - 1], xp = L.U[b + 1];
+                UT ym = L.U[b - B], yp = L.U[b + B];
+                UT zm = L.U[b - B * B], zp = L.U[b + B * B];
                 asm volatile("" : "+v"(raw), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
                              "+v"(zm), "+v"(zp));
-                const double old = fabs(raw);
+                const UT old = fabs(raw);
                 xm = fabs(xm); xp = fabs(xp); ym = fabs(ym);
                 yp = fabs(yp); zm = fabs(zm); zp = fabs(zp);
-                const double g = local_solve(fmin(xm, xp), fmin(ym, yp), fmin(zm, zp), s);
-                const bool live = valid && s > 0.0;
+                const UT g = local_solve(fmin(xm, xp), fmin(ym, yp), fmin(zm, zp), s);
+                const bool live = valid && s > UT(0);
                 const bool dec = live && g < old;
                 upd += live ? 1u : 0u;
                 L.U[valid ? b : 0] = dec ? g : old;  // positive: no longer listed
                 if (dec) {
-                    maxdec = fmax(maxdec, old - g);
+                    maxdec = vmax(maxdec, old - g);
                     changed = true;
                 }
                 // Queue the larger in-cell neighbours (halo nodes belong to other cells).
@@ -726,7 +780,9 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                 for (int k = 0; k < 6; ++k) {
                     bool app = false;
                     if (want[k]) {
-                        unsigned int* hi = reinterpret_cast<unsigned int*>(&L.U[b + off[k]]) + 1;
+                        // the word that holds the sign bit
+                        unsigned int* hi = reinterpret_cast<unsigned int*>(&L.U[b + off[k]]) +
+                                           (sizeof(UT) == 8 ? 1 : 0);
                         app = !(atomicOr(hi, 0x80000000u) & 0x80000000u);
                     }
                     const uint64_t m = __ballot(app);
@@ -740,7 +796,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
             visit_changed |= any_changed;
             cur ^= 1;
             n_cur = n_next;
-            if (track_dec && wave_max(maxdec) <= S.tol) break;
+            if (track_dec && (double)wave_max(maxdec) <= S.tol) break;
             if (n_cur > 0 && nsweeps >= P.max_sweeps) { requeue = true; break; }
         }
     }
@@ -754,9 +810,10 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     bool my_tag = false;
     int my_target = 0;
     uint32_t my_bits = 0;
-    double my_value = INF;
+    double my_value = __builtin_inf();
     if (visit_changed) {
-        double* __restrict__ uw = S.u + (size_t)lc * R3;
+        UT* __restrict__ uw = reinterpret_cast<UT*>(S.u) + (size_t)lc * R3;
+        UT* __restrict__ fw = reinterpret_cast<UT*>(S.faces);
         for (int l = lane; l < R3; l += 64) {
             const int x = l % R, y = (l / R) % R, z = l / R2;
             uw[l] = fabs(L.U[box_index<R>(x, y, z)]);
@@ -765,7 +822,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         for (int f = 0; f < 6; ++f) {
             const int nb = cell_neighbour(S, lc, cc, f);
             bool ch = false, inflow = false;
-            double v = INF;
+            UT v = INF;
             if (lane < R2) {
                 int x, y, z;
                 face_node<R>(f, lane % R, lane / R, x, y, z);
@@ -775,9 +832,9 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                 inflow = ch && v < fabs(L.U[b + face_step<R>(f)]);
             }
             if (__any(ch) && lane < R2)
-                S.faces[((size_t)lc * 6 + f) * R2 + lane] = v;
+                fw[((size_t)lc * 6 + f) * R2 + lane] = v;
             if (nb >= 0 && __any(inflow)) {
-                const double kv = wave_min(inflow ? v : INF);
+                const double kv = (double)wave_min(inflow ? v : INF);
                 if (lane == f) {
                     const int g = f ^ 1;
                     my_tag = true;
@@ -797,7 +854,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         }
         cnt.requeued += 1;
     }
-    tag_lanes<R, INNER>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits, my_value);
+    tag_lanes<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits, my_value);
     const unsigned long long t3 = cycles();
     cnt.cyc_stage += t1 - t0;
     cnt.cyc_sweep += t2 - t1;
@@ -845,12 +902,12 @@ __device__ bool grid_barrier(const SolveParams& P) {
 // The solver.  Each wave is an independent worker; each workgroup holds `W` workers.  One
 // launch runs every round (persistent, grid barrier between rounds).
 
-template <int R, typename FT, int W, int INNER>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3)))
+template <int R, typename FT, int W, int INNER, typename UT>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(sizeof(UT) == 4 ? 4 : 3)))
 k_solve(SolveParams P) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    WaveLds<R, INNER>& L = reinterpret_cast<WaveLds<R, INNER>*>(lds_raw)[wave];
+    WaveLds<R, INNER, UT>& L = reinterpret_cast<WaveLds<R, INNER, UT>*>(lds_raw)[wave];
     VisitCounters cnt{0, 0, 0, 0, 0, 0};
     unsigned long long cyc_pop = 0, cyc_wait = 0;
     PlaneRegs<R> pr;
@@ -904,7 +961,7 @@ k_solve(SolveParams P) {
             // Cells outside the lowest band go straight back to the next round's list.
             const bool defer = (uint32_t)lane < cnt_here && !(bitsd(my_kb) < thr);
             deferred += __popcll(__ballot(defer));
-            tag_lanes<R, INNER>(P, nxt, ctl_next, L, lane, wq, defer, my_c, my_fl & ~FL_QUEUED,
+            tag_lanes<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq, defer, my_c, my_fl & ~FL_QUEUED,
                          bitsd(my_kb));
             cyc_pop += cycles() - tp0;
             for (uint32_t j = 0; j < cnt_here; ++j) {
@@ -913,11 +970,11 @@ k_solve(SolveParams P) {
                 const double key = bitsd(__shfl(my_kb, (int)j, 64));
                 if (!(key < thr)) continue;
                 ++visits;
-                visit_cell<R, FT, INNER>(P, c, fl, key, L, pr, lane, ctl_next, nxt, cnt, wq);
+                visit_cell<R, FT, INNER, UT>(P, c, fl, key, L, pr, lane, ctl_next, nxt, cnt, wq);
             }
         }
         const unsigned long long tw0 = cycles();
-        queue_flush<R, INNER>(P, nxt, ctl_next, L, lane, wq);
+        queue_flush<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq);
         if (P.delta > 0.0) {
             const double mk = wave_min(wq.minkey);
             if (lane == 0 && mk < __builtin_inf())
@@ -966,12 +1023,13 @@ k_solve(SolveParams P) {
 // (NaN on padding).  Speeds that are not finite and positive set the slot's status to
 // EIK_EINVAL.
 
-template <int R, typename FT>
+template <int R, typename FT, typename UT>
 __global__ void k_init_nodes(Slot S, const FT* __restrict__ F) {
     constexpr int R3 = R * R * R;
     const size_t total = (size_t)S.ncell * R3;
-    const double INF = __builtin_inf();
+    const UT INF = (UT)__builtin_inf();
     FT* fb = reinterpret_cast<FT*>(S.f);
+    UT* ub = reinterpret_cast<UT*>(S.u);
     for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < total;
          g += (size_t)gridDim.x * blockDim.x) {
         const int lc = (int)(g / R3), l = (int)(g % R3);
@@ -990,19 +1048,20 @@ __global__ void k_init_nodes(Slot S, const FT* __restrict__ F) {
         fb[g] = fv;
         // Padding nodes hold NaN: the minimum ignores them (like +inf beyond the grid) and
         // every comparison with them is false, so they are never activated or used as inflow.
-        S.u[g] = fv == FT(0) ? __builtin_nan("") : INF;
+        ub[g] = fv == FT(0) ? (UT)__builtin_nan("") : INF;
     }
 }
 
 // The slot's face copies <- +inf, its cells' state cleared and mapped to the slot.
-template <int R>
+template <int R, typename UT>
 __global__ void k_init_cells(SolveParams P, Slot S, int slot) {
     constexpr int R2 = R * R;
     const size_t nf = (size_t)S.ncell * 6 * R2;
     const double INF = __builtin_inf();
+    UT* faces = reinterpret_cast<UT*>(S.faces);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t g0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    for (size_t g = g0; g < nf; g += stride) S.faces[g] = INF;
+    for (size_t g = g0; g < nf; g += stride) faces[g] = (UT)INF;
     for (size_t g = g0; g < (size_t)S.ncell; g += stride) {
         const size_t c = (size_t)S.cell_base + g;
         P.key[0][c] = dbits(INF);
@@ -1035,7 +1094,15 @@ __global__ void k_init_global(SolveParams P) {
 // array, copied into their cell's face layers; their cells and the cells of their six grid
 // neighbours are queued for round `round` with every node active and cell value q (the initial
 // cell values of Section 4).
-template <int R, typename FT>
+// Atomic minimum of a value >= +0 (or +inf) through its bit pattern, which orders like the value.
+__device__ __forceinline__ void atomic_min_val(double* p, double v) {
+    atomicMin((unsigned long long*)p, (unsigned long long)dbits(v));
+}
+__device__ __forceinline__ void atomic_min_val(float* p, float v) {
+    atomicMin((unsigned int*)p, __float_as_uint(v));
+}
+
+template <int R, typename FT, typename UT>
 __global__ void k_seed(SolveParams P, Slot S, int64_t round, int64_t nsrc,
                        const int64_t* __restrict__ idx3, const double* __restrict__ q) {
     constexpr int R2 = R * R, R3 = R * R * R;
@@ -1043,8 +1110,9 @@ __global__ void k_seed(SolveParams P, Slot S, int64_t round, int64_t nsrc,
     if (n >= nsrc) return;
     const int64_t i = idx3[3 * n], j = idx3[3 * n + 1], k = idx3[3 * n + 2];
     const double qv = q[n] + 0.0;  // -0.0 -> +0.0 so that bit order is value order
+    const UT qu = (UT)qv;           // the exit value in the storage precision
     if (i < 0 || i >= S.nx || j < 0 || j >= S.ny || k < 0 || k >= S.nz || !(qv >= 0.0) ||
-        !(qv <= 1.7976931348623157e308)) {
+        !(qu <= (UT)1.7976931348623157e308)) {
         atomicCAS(S.status, 0, EIK_EINVAL_DEV);
         return;
     }
@@ -1052,7 +1120,7 @@ __global__ void k_seed(SolveParams P, Slot S, int64_t round, int64_t nsrc,
     const int x = (int)(i % R), y = (int)(j % R), z = (int)(k % R);
     const int lc = cx + S.ncx * (cy + S.ncy * cz);
     const int l = x + R * (y + R * z);
-    atomicMin((unsigned long long*)&S.u[(size_t)lc * R3 + l], (unsigned long long)dbits(qv));
+    atomic_min_val(reinterpret_cast<UT*>(S.u) + (size_t)lc * R3 + l, qu);
     reinterpret_cast<FT*>(S.f)[(size_t)lc * R3 + l] = FT(-1);
     // Face copies of the exit node.
     const int fx[6] = {x == 0, x == R - 1, y == 0, y == R - 1, z == 0, z == R - 1};
@@ -1060,25 +1128,25 @@ __global__ void k_seed(SolveParams P, Slot S, int64_t round, int64_t nsrc,
         if (!fx[f]) continue;
         const int a = (f >> 1) == 0 ? y : x;
         const int b = (f >> 1) == 2 ? y : z;
-        atomicMin((unsigned long long*)&S.faces[((size_t)lc * 6 + f) * R2 + a + R * b],
-                  (unsigned long long)dbits(qv));
+        atomic_min_val(reinterpret_cast<UT*>(S.faces) + ((size_t)lc * 6 + f) * R2 + a + R * b, qu);
     }
     RoundCtl* ctl = &P.ctl[round & 3];
     const int par = (int)(round & 1);
-    tag_cell(P, ctl, par, S.cell_base + lc, FL_ALL, qv);
+    tag_cell(P, ctl, par, S.cell_base + lc, FL_ALL, (double)qu);
     const int64_t nbr[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
                                {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
     for (int t = 0; t < 6; ++t) {
         const int64_t a = nbr[t][0], b = nbr[t][1], e = nbr[t][2];
         if (a < 0 || a >= S.nx || b < 0 || b >= S.ny || e < 0 || e >= S.nz) continue;
         const int nc = (int)(a / R) + S.ncx * ((int)(b / R) + S.ncy * (int)(e / R));
-        if (nc != lc) tag_cell(P, ctl, par, S.cell_base + nc, FL_ALL, qv);
+        if (nc != lc) tag_cell(P, ctl, par, S.cell_base + nc, FL_ALL, (double)qu);
     }
 }
 
 // Output (a8): cell-blocked u of one slot -> row-major u_out.
-template <int R>
+template <int R, typename UT>
 __global__ void k_output(Slot S, double* __restrict__ out) {
+    const UT* ub = reinterpret_cast<const UT*>(S.u);
     constexpr int R3 = R * R * R;
     const size_t total = (size_t)S.nx * S.ny * S.nz;
     for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < total;
@@ -1088,8 +1156,47 @@ __global__ void k_output(Slot S, double* __restrict__ out) {
         const int k = (int)(g / ((size_t)S.nx * S.ny));
         const int lc = i / R + S.ncx * (j / R + S.ncy * (k / R));
         const int l = i % R + R * (j % R + R * (k % R));
-        out[g] = S.u[(size_t)lc * R3 + l];
+        out[g] = (double)ub[(size_t)lc * R3 + l];
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// Mixed precision: the single-precision result lifted to an FP64 starting point for the
+// double-precision polish.  Values only decrease under the method's updates, so the polish
+// reaches the FP64 solution from any starting point at or above it; the FP32 values are
+// multiplied by `factor` (a bound on their relative error, plus margin) to start above it.
+
+template <int R>
+__global__ void k_lift(Slot S32, Slot S64, double factor) {
+    constexpr int R3 = R * R * R, R2 = R * R;
+    const size_t nodes = (size_t)S64.ncell * R3, nf = (size_t)S64.ncell * 6 * R2;
+    const float* u32 = reinterpret_cast<const float*>(S32.u);
+    const float* f32 = reinterpret_cast<const float*>(S32.faces);
+    double* u64 = reinterpret_cast<double*>(S64.u);
+    double* f64 = reinterpret_cast<double*>(S64.faces);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t g0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    for (size_t g = g0; g < nodes; g += stride) u64[g] = (double)u32[g] * factor;
+    for (size_t g = g0; g < nf; g += stride) f64[g] = (double)f32[g] * factor;
+}
+
+// Every cell of a slot joins the list of round `round` with all nodes active.
+__global__ void k_queue_all(SolveParams P, Slot S, int64_t round) {
+    RoundCtl* ctl = &P.ctl[round & 3];
+    const int par = (int)(round & 1);
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < S.ncell; g += gridDim.x * blockDim.x)
+        tag_cell(P, ctl, par, S.cell_base + g, FL_ALL, 0.0);
+}
+
+// Empty round lists and round counter 0 for a following launch (status and counters kept).
+__global__ void k_reset_rounds(SolveParams P) {
+    const int g0 = threadIdx.x;
+    if (g0 < 4) {
+        P.ctl[g0].count = 0;
+        P.ctl[g0].cursor = 0;
+        P.ctl[g0].minkey = dbits(__builtin_inf());
+    }
+    if (g0 == 0) *P.next_round = 0;
 }
 
 // Cells of each slot in the list of the next launch's first round (the host's test for
@@ -1109,13 +1216,13 @@ __global__ void k_slot_counts(SolveParams P, int* counts) {
 // ------------------------------------------------------------------------------------------
 // Host-side launchers.
 
-template <int R, int W, int INNER>
-constexpr size_t solve_lds_bytes() { return sizeof(WaveLds<R, INNER>) * W; }
+template <int R, int W, int INNER, typename UT>
+constexpr size_t solve_lds_bytes() { return sizeof(WaveLds<R, INNER, UT>) * W; }
 
-template <int R, typename FT, int W, int INNER>
+template <int R, typename FT, int W, int INNER, typename UT>
 static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int workers, int* used) {
-    const size_t lds = solve_lds_bytes<R, W, INNER>();
-    auto kern = k_solve<R, FT, W, INNER>;
+    const size_t lds = solve_lds_bytes<R, W, INNER, UT>();
+    auto kern = k_solve<R, FT, W, INNER, UT>;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -1153,13 +1260,19 @@ static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int worker
     return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(64 * W), args, lds, s);
 }
 
+template <int R, typename FT, typename UT>
+static hipError_t solve_rounds_ut(const SolveParams& P, hipStream_t s, int workers, int* used) {
+    if (P.inner == INNER_SWEEP)
+        return launch_solve_t<R, FT, kWavesPerGroup, INNER_SWEEP, UT>(P, s, workers, used);
+    if (P.inner == INNER_LIST)
+        return launch_solve_t<R, FT, kWavesPerGroup, INNER_LIST, UT>(P, s, workers, used);
+    return launch_solve_t<R, FT, kWavesPerGroupDual, INNER_DUAL, UT>(P, s, workers, used);
+}
+
 template <int R, typename FT>
 static hipError_t solve_rounds_t(const SolveParams& P, hipStream_t s, int workers, int* used) {
-    if (P.inner == INNER_SWEEP)
-        return launch_solve_t<R, FT, kWavesPerGroup, INNER_SWEEP>(P, s, workers, used);
-    if (P.inner == INNER_LIST)
-        return launch_solve_t<R, FT, kWavesPerGroup, INNER_LIST>(P, s, workers, used);
-    return launch_solve_t<R, FT, kWavesPerGroupDual, INNER_DUAL>(P, s, workers, used);
+    return P.fp32 ? solve_rounds_ut<R, FT, float>(P, s, workers, used)
+                  : solve_rounds_ut<R, FT, double>(P, s, workers, used);
 }
 
 static int blocks_for(size_t n, int threads) {
@@ -1173,45 +1286,51 @@ hipError_t launch_init_global(const SolveParams& P, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int R, typename UT>
+static void init_slot_t(const SolveParams& P, const Slot& S, int slot, int f_dtype,
+                        const void* F, int blocks, int threads, hipStream_t s) {
+    hipLaunchKernelGGL((k_init_cells<R, UT>), dim3(blocks), dim3(threads), 0, s, P, S, slot);
+    if (f_dtype == EIK_F32)
+        hipLaunchKernelGGL((k_init_nodes<R, float, UT>), dim3(blocks), dim3(threads), 0, s, S,
+                           reinterpret_cast<const float*>(F));
+    else
+        hipLaunchKernelGGL((k_init_nodes<R, double, UT>), dim3(blocks), dim3(threads), 0, s, S,
+                           reinterpret_cast<const double*>(F));
+}
+
 hipError_t launch_init_slot(const SolveParams& P, const Slot& S, int slot, int cell, int f_dtype,
                             const void* F, hipStream_t s) {
     const int threads = 256;
     const size_t nodes = (size_t)S.ncell * cell * cell * cell;
     const int blocks = blocks_for(nodes, threads);
-    if (cell == 8) {
-        hipLaunchKernelGGL((k_init_cells<8>), dim3(blocks), dim3(threads), 0, s, P, S, slot);
-        if (f_dtype == EIK_F32)
-            hipLaunchKernelGGL((k_init_nodes<8, float>), dim3(blocks), dim3(threads), 0, s, S,
-                               reinterpret_cast<const float*>(F));
-        else
-            hipLaunchKernelGGL((k_init_nodes<8, double>), dim3(blocks), dim3(threads), 0, s, S,
-                               reinterpret_cast<const double*>(F));
-    } else if (cell == 4) {
-        hipLaunchKernelGGL((k_init_cells<4>), dim3(blocks), dim3(threads), 0, s, P, S, slot);
-        if (f_dtype == EIK_F32)
-            hipLaunchKernelGGL((k_init_nodes<4, float>), dim3(blocks), dim3(threads), 0, s, S,
-                               reinterpret_cast<const float*>(F));
-        else
-            hipLaunchKernelGGL((k_init_nodes<4, double>), dim3(blocks), dim3(threads), 0, s, S,
-                               reinterpret_cast<const double*>(F));
-    } else {
-        return hipErrorInvalidValue;
-    }
+    if (cell == 8 && S.fp32) init_slot_t<8, float>(P, S, slot, f_dtype, F, blocks, threads, s);
+    else if (cell == 8) init_slot_t<8, double>(P, S, slot, f_dtype, F, blocks, threads, s);
+    else if (cell == 4 && S.fp32) init_slot_t<4, float>(P, S, slot, f_dtype, F, blocks, threads, s);
+    else if (cell == 4) init_slot_t<4, double>(P, S, slot, f_dtype, F, blocks, threads, s);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+template <int R, typename UT>
+static void seed_t(const SolveParams& P, const Slot& S, int f_dtype, int64_t round, int64_t nsrc,
+                   const int64_t* idx3, const double* q, hipStream_t s) {
+    const int sb = (int)((nsrc + 63) / 64);
+    if (f_dtype == EIK_F32)
+        hipLaunchKernelGGL((k_seed<R, float, UT>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc,
+                           idx3, q);
+    else
+        hipLaunchKernelGGL((k_seed<R, double, UT>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc,
+                           idx3, q);
 }
 
 hipError_t launch_seed(const SolveParams& P, const Slot& S, int cell, int f_dtype, int64_t round,
                        int64_t nsrc, const int64_t* idx3, const double* q, hipStream_t s) {
     if (nsrc <= 0) return hipSuccess;
-    const int sb = (int)((nsrc + 63) / 64);
-    if (cell == 8 && f_dtype == EIK_F32)
-        hipLaunchKernelGGL((k_seed<8, float>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc, idx3, q);
-    else if (cell == 8)
-        hipLaunchKernelGGL((k_seed<8, double>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc, idx3, q);
-    else if (f_dtype == EIK_F32)
-        hipLaunchKernelGGL((k_seed<4, float>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc, idx3, q);
-    else
-        hipLaunchKernelGGL((k_seed<4, double>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc, idx3, q);
+    if (cell == 8 && S.fp32) seed_t<8, float>(P, S, f_dtype, round, nsrc, idx3, q, s);
+    else if (cell == 8) seed_t<8, double>(P, S, f_dtype, round, nsrc, idx3, q, s);
+    else if (cell == 4 && S.fp32) seed_t<4, float>(P, S, f_dtype, round, nsrc, idx3, q, s);
+    else if (cell == 4) seed_t<4, double>(P, S, f_dtype, round, nsrc, idx3, q, s);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1229,10 +1348,35 @@ hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipS
 hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s) {
     const int threads = 256;
     const int ob = blocks_for((size_t)S.nx * S.ny * S.nz, threads);
-    if (cell == 8)
-        hipLaunchKernelGGL((k_output<8>), dim3(ob), dim3(threads), 0, s, S, u_out);
+    if (cell == 8 && S.fp32)
+        hipLaunchKernelGGL((k_output<8, float>), dim3(ob), dim3(threads), 0, s, S, u_out);
+    else if (cell == 8)
+        hipLaunchKernelGGL((k_output<8, double>), dim3(ob), dim3(threads), 0, s, S, u_out);
+    else if (S.fp32)
+        hipLaunchKernelGGL((k_output<4, float>), dim3(ob), dim3(threads), 0, s, S, u_out);
     else
-        hipLaunchKernelGGL((k_output<4>), dim3(ob), dim3(threads), 0, s, S, u_out);
+        hipLaunchKernelGGL((k_output<4, double>), dim3(ob), dim3(threads), 0, s, S, u_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lift(const Slot& S32, const Slot& S64, int cell, double factor, hipStream_t s) {
+    const int threads = 256;
+    const int blocks = blocks_for((size_t)S64.ncell * cell * cell * cell, threads);
+    if (cell == 8)
+        hipLaunchKernelGGL((k_lift<8>), dim3(blocks), dim3(threads), 0, s, S32, S64, factor);
+    else
+        hipLaunchKernelGGL((k_lift<4>), dim3(blocks), dim3(threads), 0, s, S32, S64, factor);
+    return hipGetLastError();
+}
+
+hipError_t launch_queue_all(const SolveParams& P, const Slot& S, int64_t round, hipStream_t s) {
+    hipLaunchKernelGGL(k_queue_all, dim3(blocks_for((size_t)S.ncell, 256)), dim3(256), 0, s, P, S,
+                       round);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_rounds(const SolveParams& P, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_rounds, dim3(1), dim3(64), 0, s, P);
     return hipGetLastError();
 }
 

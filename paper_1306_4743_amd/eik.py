@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libeik.so")
 EIK_OK, EIK_EINVAL, EIK_ENOMEM, EIK_EHIP, EIK_ENOCONV, EIK_ECANCELLED = 0, -1, -2, -3, -4, -5
 EIK_EBUSY = -6
 EIK_F64, EIK_F32 = 0, 1
-EIK_MODE_FP64 = 0
+EIK_MODE_FP64, EIK_MODE_FP32, EIK_MODE_MIXED = 0, 1, 2
 EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL = 1, 2, 3
 
 
@@ -100,7 +100,7 @@ def load():
     lib.eik_release.restype = None
     lib.eik_version.argtypes = []
     lib.eik_version.restype = ctypes.c_char_p
-    lib.eik_problem_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.eik_problem_bytes.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.eik_problem_bytes.restype = i32
     lib.eik_solve_batch.argtypes = [i32, ctypes.POINTER(Problem), i32, i32, vp,
                                     ctypes.POINTER(Options)]
@@ -209,14 +209,14 @@ def _sources(F, idx3, q, stream):
 
 
 def _options(delta=0.0, max_rounds=0, max_sweeps=0, workers=0, shuffle=0, timing=False,
-             round_log=None, inner=0):
+             round_log=None, inner=0, mode=EIK_MODE_FP64):
     rl_ptr, rl_len = None, 0
     if round_log is not None:
         import torch
         if not (round_log.is_cuda and round_log.dtype == torch.int64 and round_log.is_contiguous()):
             raise ValueError("round_log must be a contiguous int64 CUDA tensor")
         rl_ptr, rl_len = round_log.data_ptr(), round_log.numel() // 2
-    return Options(EIK_MODE_FP64, float(delta), int(max_rounds), int(max_sweeps), int(workers),
+    return Options(int(mode), float(delta), int(max_rounds), int(max_sweeps), int(workers),
                    int(shuffle), int(bool(timing)), rl_ptr, rl_len, int(inner))
 
 
@@ -234,7 +234,7 @@ def _problem(F, h, idx3, q, tol, u_out, stream):
 def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, stream=None,
           delta: float = 0.0, max_rounds: int = 0, max_sweeps: int = 0, workers: int = 0,
           shuffle: int = 0, timing: bool = False, round_log=None, inner: int = 0,
-          check: bool = True):
+          mode: int = EIK_MODE_FP64, check: bool = True):
     """Enqueue one solve of eq. (2) on ``stream`` (torch stream; default: current stream).
 
     F: torch CUDA tensor [nz, ny, nx] of float32 or float64 speeds (contiguous).
@@ -247,7 +247,8 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
     f_dtype = _f_dtype(F)
     u_out = _out_tensor(F, u_out)
     src, keep = _sources(F, idx3, q, stream)
-    opts = _options(delta, max_rounds, max_sweeps, workers, shuffle, timing, round_log, inner)
+    opts = _options(delta, max_rounds, max_sweeps, workers, shuffle, timing, round_log, inner,
+                    mode)
     nz, ny, nx = F.shape
     dims = _dims_array((nx, ny, nz))
     rc = lib.eik_solve_ex(ctypes.cast(dims, ctypes.c_void_p), float(h),
@@ -282,11 +283,11 @@ def autotune(F, h: float, idx3, q, tol: float = 0.0, reps: int = 2, u_out=None, 
     return best.as_dict(), [table[i].as_dict() for i in range(n.value)]
 
 
-def problem_bytes(dims, cell: int = 8, f_dtype: int = EIK_F32) -> int:
+def problem_bytes(dims, cell: int = 8, f_dtype: int = EIK_F32, mode: int = EIK_MODE_FP64) -> int:
     """Device bytes of one grid's arrays inside a server pool (dims = (nx, ny, nz))."""
     out = ctypes.c_size_t(0)
     rc = load().eik_problem_bytes(ctypes.cast(_dims_array(dims), ctypes.c_void_p), int(cell),
-                                  int(f_dtype), ctypes.byref(out))
+                                  int(f_dtype), int(mode), ctypes.byref(out))
     if rc != EIK_OK:
         raise EikError(rc, "eik_problem_bytes: ")
     return int(out.value)

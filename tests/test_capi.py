@@ -188,3 +188,21 @@ def test_autotune_rejects_invalid():
     assert call(h=-1.0) == eik.EIK_EINVAL
     assert call(F=0) == eik.EIK_EINVAL
     assert call(dims=None) == eik.EIK_EINVAL
+
+
+def test_mode_sizes_and_server_mode():
+    """FP32 mode halves the value and face arrays; mixed keeps both; servers take one precision."""
+    d = (65, 65, 65)
+    b64 = eik.problem_bytes(d, 8, eik.EIK_F32, eik.EIK_MODE_FP64)
+    b32 = eik.problem_bytes(d, 8, eik.EIK_F32, eik.EIK_MODE_FP32)
+    bmx = eik.problem_bytes(d, 8, eik.EIK_F32, eik.EIK_MODE_MIXED)
+    ncell = 9 ** 3
+    assert b64 - b32 == ncell * (512 + 384) * 4
+    assert bmx - b64 == ncell * (512 + 384) * 4
+    with pytest.raises(eik.EikError):
+        eik.problem_bytes(d, 8, eik.EIK_F32, 3)
+    lib = eik.load()
+    h = ctypes.c_void_p(None)
+    opts = eik._options(mode=eik.EIK_MODE_MIXED)
+    assert lib.eik_server_create(ctypes.byref(h), 1 << 20, 100, 4, 8, eik.EIK_F32, None,
+                                 ctypes.byref(opts)) == eik.EIK_EINVAL
