@@ -372,6 +372,15 @@ __device__ __forceinline__ void load_plane_regs(PlaneRegs<R>& pr, int lane) {
 __device__ __forceinline__ bool is_active(double v) { return __double_as_longlong(v) < 0; }
 __device__ __forceinline__ bool is_active(float v) { return __float_as_int(v) < 0; }
 
+// Marks the LDS node p active given its (non-negative) value v: only the word that holds the
+// sign bit is written.  Lanes that mark the same node in one step write the same word.
+__device__ __forceinline__ void mark_active(double* p, double v) {
+    reinterpret_cast<uint32_t*>(p)[1] = (uint32_t)(__double_as_longlong(v) >> 32) | 0x80000000u;
+}
+__device__ __forceinline__ void mark_active(float* p, float v) {
+    *reinterpret_cast<uint32_t*>(p) = __float_as_uint(v) | 0x80000000u;
+}
+
 // ------------------------------------------------------------------------------------------
 // Tagging a neighbour cell for the next round (Algorithm 2 "for each c_k in DN", with Set Cell
 // Value = atomic min of the cell value and Add Cell = append to the next round's list unless
@@ -572,31 +581,29 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                              "+v"(zm), "+v"(zp));
                 const bool act = ((pr.valid >> p) & 1u) && is_active(raw);
                 if (__any(act)) {
-                    // Every lane runs the same instructions: an active lane stores its value
-                    // back (|raw| clears the flag) and an activation stores -|v| into the
-                    // neighbour; stores with nothing to do go to the lane's own scratch slot on
-                    // a halo edge, which no node reads.  Two lanes never store different values
-                    // to one node in one step (a plane's nodes are not neighbours of each other;
-                    // activations of a shared neighbour agree).
-                    // Neighbour values are read through |.| (the abs modifier of the min); a
-                    // neighbour is activated if it is inactive (sign clear) and larger than the
-                    // new value, which the raw value tells in one comparison.
+                    // An active lane stores its value back (|raw| clears the flag); a decrease
+                    // activates every neighbour that is inactive (sign clear) and larger than
+                    // the new value, which the raw value tells in one comparison.  Neighbour
+                    // values enter the local solve through |.| (the abs modifier of the min).
+                    // Two lanes never store different values to one node in one step (a plane's
+                    // nodes are not neighbours of each other; activations of a shared neighbour
+                    // agree).  The stores are predicated, at fixed offsets from the lane's node.
                     const UT old = fabs(raw);
                     const UT g = local_solve(vmin_abs(xm, xp), vmin_abs(ym, yp),
                                              vmin_abs(zm, zp), s);
                     const bool live = act && s > UT(0);
                     const bool dec = live && g < old;
                     upd += live ? 1u : 0u;
-                    const int dm = pr.dummy;
-                    L.U[act ? b : dm] = dec ? g : old;
+                    UT* const ub = &L.U[b];
+                    if (act) ub[0] = dec ? g : old;
                     changed |= dec;
                     if (track_dec && dec) maxdec = vmax(maxdec, old - g);
-                    L.U[(dec && xm > g) ? b - 1 : dm] = -xm;
-                    L.U[(dec && xp > g) ? b + 1 : dm] = -xp;
-                    L.U[(dec && ym > g) ? b - B : dm] = -ym;
-                    L.U[(dec && yp > g) ? b + B : dm] = -yp;
-                    L.U[(dec && zm > g) ? b - B * B : dm] = -zm;
-                    L.U[(dec && zp > g) ? b + B * B : dm] = -zp;
+                    if (dec && xm > g) mark_active(ub - 1, xm);
+                    if (dec && xp > g) mark_active(ub + 1, xp);
+                    if (dec && ym > g) mark_active(ub - B, ym);
+                    if (dec && yp > g) mark_active(ub + B, yp);
+                    if (dec && zm > g) mark_active(ub - B * B, zm);
+                    if (dec && zp > g) mark_active(ub + B * B, zp);
                 }
                 wave_sync();
             }
