@@ -13,6 +13,8 @@ constexpr uint32_t FL_FACES = 0x3Fu;      // bit f: face f received new inflow (
 constexpr uint32_t FL_ALL = 1u << 6;      // every node active (first visit / re-queue)
 constexpr uint32_t FL_QUEUED = 1u << 7;   // already in that round's list
 constexpr int FL_DIR_SHIFT = 8;           // bits 8..15: preferred sweep directions
+constexpr int FL_GRAY_SHIFT = 16;         // bits 16..18: Gray-cycle position to resume at
+constexpr uint32_t FL_GRAY_SET = 1u << 19;  // bits 16..18 are valid (a capped visit resumes)
 
 // Device status values are the public codes.
 constexpr int EIK_EINVAL_DEV = EIK_EINVAL;

@@ -511,7 +511,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         if (lane < R2) {
             int x, y, z;
             face_node<R>(f, lane % R, lane / R, x, y, z);
-            before[f] = L.U[box_index<R>(x, y, z)];
+            before[f] = fabs(L.U[box_index<R>(x, y, z)]);
         }
     }
     wave_sync();
@@ -543,21 +543,29 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
 
     const unsigned long long t1 = cycles();
     bool visit_changed = false, requeue = false;
+    uint32_t requeue_bits = INNER == INNER_DUAL ? FL_ALL : 0u;  // how a capped visit resumes
     unsigned int upd = 0;
     int nsweeps = 0;
     const bool track_dec = S.tol > 0.0;
     if constexpr (INNER == INNER_SWEEP) {
         // Sweeps: preferred directions first (Gray order), then the default Gray cycle.  A sweep in
         // direction d visits the planes of the reflected coordinates x ^ mx etc. in increasing order.
+        // A visit resumed after the sweep cap continues the Gray cycle where the capped one
+        // stopped.
         const uint32_t pref = (fl >> FL_DIR_SHIFT) & 0xFFu;
-        int pi = 0, ci = 0;
+        int pi = 0, ci = (fl & FL_GRAY_SET) ? (int)((fl >> FL_GRAY_SHIFT) & 7u) : 0;
+        int last_gi = 0;
         for (;;) {
             int d = -1;
             while (pi < 8) {
-                const int cand = kGray[pi++];
-                if (pref & (1u << cand)) { d = cand; break; }
+                const int gi = pi++;
+                if (pref & (1u << kGray[gi])) { d = kGray[gi]; last_gi = gi; break; }
             }
-            if (d < 0) d = kGray[(ci++) & 7];
+            if (d < 0) {
+                last_gi = ci & 7;
+                d = kGray[last_gi];
+                ++ci;
+            }
             const int mx = (d & 1) ? R - 1 : 0, my = (d & 2) ? R - 1 : 0, mz = (d & 4) ? R - 1 : 0;
             bool changed = false;
             UT maxdec = UT(0);
@@ -620,7 +628,11 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
             }
             if (!__any(left)) break;
             if (track_dec && (double)wave_max(maxdec) <= S.tol) break;
-            if (nsweeps >= P.max_sweeps) { requeue = true; break; }
+            if (nsweeps >= P.max_sweeps) {
+                requeue = true;
+                requeue_bits = FL_GRAY_SET | ((uint32_t)((last_gi + 1) & 7) << FL_GRAY_SHIFT);
+                break;
+            }
         }
     } else if constexpr (INNER == INNER_DUAL) {
         // Two sweep streams on the cell at once, half a sweep apart: at step t stream 0
@@ -819,11 +831,16 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     uint32_t my_bits = 0;
     double my_value = __builtin_inf();
     if (visit_changed) {
+        // A visit cut short by the sweep cap keeps its active flags (the sign bits) in the
+        // stored values, so the next visit resumes with the same active set.  Only the cell's
+        // own visits read them; face copies and the output are taken through |.|.
+        const bool keep_active = requeue && INNER != INNER_DUAL;
         UT* __restrict__ uw = reinterpret_cast<UT*>(S.u) + (size_t)lc * R3;
         UT* __restrict__ fw = reinterpret_cast<UT*>(S.faces);
         for (int l = lane; l < R3; l += 64) {
             const int x = l % R, y = (l / R) % R, z = l / R2;
-            uw[l] = fabs(L.U[box_index<R>(x, y, z)]);
+            const UT v = L.U[box_index<R>(x, y, z)];
+            uw[l] = keep_active ? v : fabs(v);
         }
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
@@ -856,7 +873,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         if (lane == 6) {
             my_tag = true;
             my_target = c;
-            my_bits = FL_ALL;
+            my_bits = requeue_bits;
             my_value = popped_key;
         }
         cnt.requeued += 1;
@@ -1163,7 +1180,7 @@ __global__ void k_output(Slot S, double* __restrict__ out) {
         const int k = (int)(g / ((size_t)S.nx * S.ny));
         const int lc = i / R + S.ncx * (j / R + S.ncy * (k / R));
         const int l = i % R + R * (j % R + R * (k % R));
-        out[g] = (double)ub[(size_t)lc * R3 + l];
+        out[g] = fabs((double)ub[(size_t)lc * R3 + l]);
     }
 }
 
@@ -1183,7 +1200,7 @@ __global__ void k_lift(Slot S32, Slot S64, double factor) {
     double* f64 = reinterpret_cast<double*>(S64.faces);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t g0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    for (size_t g = g0; g < nodes; g += stride) u64[g] = (double)u32[g] * factor;
+    for (size_t g = g0; g < nodes; g += stride) u64[g] = fabs((double)u32[g]) * factor;
     for (size_t g = g0; g < nf; g += stride) f64[g] = (double)f32[g] * factor;
 }
 
