@@ -191,8 +191,8 @@ typedef struct eik_tune_entry {
  * The best cell size, in-cell solver, worker count and priority band depend on the problem
  * (Section 6 finds the best cell size problem-dependent), so they are measured, not guessed:
  * every combination of r in {8, 4}, inner in {SWEEP, LIST, DUAL} and workers in {all, one
- * workgroup per CU} with no band, then the best of those with bands of 4 and 16 cell crossings
- * (delta = 4 r h, 16 r h).  Each configuration is solved once to warm up and `reps` (1..100)
+ * workgroup per CU} with no band, then the best of those with bands of 4, 16 and 64 cell
+ * crossings (delta = 4 r h, 16 r h, 64 r h).  Each configuration is solved once to warm up and `reps` (1..100)
  * times timed; the problem's arguments are those of eik_solve_ex (u_out receives the result of
  * the last run; every configuration computes the same U up to rounding).  Blocks until done.
  * table (cap entries, may be NULL if cap = 0) receives every configuration tried, *n_out their

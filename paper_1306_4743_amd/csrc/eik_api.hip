@@ -699,10 +699,10 @@ int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
             (ibest < 0 || cand[i].ms < cand[(size_t)ibest].ms))
             ibest = (int)i;
     }
-    // Priority bands around the best configuration: widths of 4 and 16 cell crossings (r h).
+    // Priority bands around the best configuration: widths of 4, 16 and 64 cell crossings (r h).
     if (rc == EIK_OK && ibest >= 0) {
         const eik_tune_entry b = cand[(size_t)ibest];
-        for (double m : {4.0, 16.0}) {
+        for (double m : {4.0, 16.0, 64.0}) {
             eik_tune_entry t = b;
             t.delta = m * b.cell * h;
             rc = run(t);

@@ -17,6 +17,7 @@ Workloads (the paper's benchmark problems and the synthetic stand-ins derived fr
                       (barriers of low speed whose openings pinch the level sets).
 * ``bumps``        -- 1 + a sum of Gaussian bumps, clamped (precision workload).
 * ``checkerboard`` -- the K^3 checkerboard with F in {1, 2} ("checkerboard speed functions").
+* ``shell_maze``   -- the spherical-shell maze of the "maze speed functions" subsection.
 
 Every generator is deterministic in its arguments (numpy PCG64 seeded generators).
 """
@@ -196,6 +197,32 @@ def maze_torch(n: int, seed: int, n_sources: int, device, barrier_speed: float =
     return F.contiguous(), _grid_h(n), L["src"], np.zeros(n_sources)
 
 
+def shell_maze(n: int = 257, cell: int = 8, tol: float = 0.0, dtype=np.float32,
+               barrier_speed: float = 0.001, t: float = 1.0 / 12.0, w: float = 0.1) -> Problem:
+    """The spherical-shell maze of the "maze speed functions" subsection of Section 6.
+
+    Domain [-1, 1]^3 with n nodes per side (h = 2 / (n - 1)), one exit node at the origin
+    (q = 0).  F = 1 except inside four concentric shells of thickness t with inner radii 0.3,
+    0.5, 0.7, 0.9, where F = ``barrier_speed``; each shell has a cylindrical opening
+    x^2 + y^2 < w on alternating sides (z < 0 for the first and third, z > 0 for the second and
+    fourth).  F is returned in ``dtype`` and both solvers read exactly those values.
+    """
+    c = np.linspace(-1.0, 1.0, n)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    rad = np.sqrt(x * x + y * y + z * z)
+    hole = x * x + y * y < w
+    barrier = np.zeros((n, n, n), dtype=bool)
+    for k, r0 in enumerate((0.3, 0.5, 0.7, 0.9)):
+        side = (z < 0) if k % 2 == 0 else (z > 0)
+        barrier |= (rad > r0) & (rad < r0 + t) & ~(hole & side)
+    F = np.where(barrier, dtype(barrier_speed), dtype(1.0)).astype(dtype)
+    m = (n - 1) // 2
+    src = np.array([[m, m, m]], dtype=np.int64)
+    return Problem(f"shellmaze{n}", F, 2.0 / (n - 1), src, np.zeros(1), cell, tol,
+                   {"workload": f"spherical-shell maze {n}^3 on [-1,1]^3 (4 shells, t=1/12, "
+                                f"w=1/10, F=1/{barrier_speed}), exit at the origin"})
+
+
 def bumps(n: int = 1025, seed: int = 4, n_bumps: int = 32, cell: int = 8, tol: float = 0.0,
           dtype=np.float32, device=None) -> Problem:
     """F = clamp(1 + sum_m A_m exp(-|x - c_m|^2 / (2 w_m^2)), 0.2, 2) with c_m ~ U[0,1]^3,
@@ -260,5 +287,5 @@ def random_small(n: int, seed: int, n_sources: int = 3, fmin: float = 0.2, fmax:
 
 def by_name(name: str, **kw) -> Problem:
     table = {"constant": constant, "oscillatory": oscillatory, "curved": curved, "maze": maze,
-             "bumps": bumps, "checkerboard": checkerboard}
+             "bumps": bumps, "checkerboard": checkerboard, "shell_maze": shell_maze}
     return table[name](**kw)

@@ -313,3 +313,35 @@ def test_mixed_mode_batch(orc, torch_dev):
     assert list(eik.batch_status(len(ps))) == [0, 0]
     for p, u in zip(ps, outs):
         compare(u.cpu().numpy(), orc.fmm(p.F, p.h, p.src, p.q), p)
+
+
+@pytest.mark.parametrize("inner", INNERS)
+@pytest.mark.parametrize("cell", [8, 4])
+@pytest.mark.parametrize("name", ["shell_maze", "curved", "checker11", "checker41"])
+def test_paper_workloads(orc, torch_dev, name, cell, inner):
+    """The paper's other speed functions: the spherical-shell maze (F = 0.001 in the shells),
+    Example 3 and the K = 11 / 41 checkerboards."""
+    p = {"shell_maze": lambda: W.shell_maze(81),
+         "curved": lambda: W.curved(65),
+         "checker11": lambda: W.checkerboard(89, K=11),
+         "checker41": lambda: W.checkerboard(83, K=41)}[name]()
+    check(orc, torch_dev, p, cell=cell, tol=0.0, inner=inner)
+
+
+@pytest.mark.parametrize("inner", INNERS)
+def test_early_termination_kappa(orc, torch_dev, inner):
+    """In-cell stop when a sweep's largest decrease is <= kappa = 1e-8 (the early-termination
+    variant of Section 6): values only decrease from +inf, so the result stays an upper bound of
+    the solution; its error is small and it needs no more sweeps than kappa = 0."""
+    p = W.oscillatory(97, periods=4)
+    want = orc.fmm(p.F, p.h, p.src, p.q)
+    got, rc, st = run_gpu(torch_dev, p, tol=1e-8, inner=inner)
+    assert rc == 0
+    exact, rc0, st0 = run_gpu(torch_dev, p, tol=0.0, inner=inner)
+    fin = np.isfinite(want) & (want > 0)
+    assert np.all(got[fin] >= want[fin] * (1 - 1e-13))
+    rel = float(np.max((got[fin] - want[fin]) / want[fin]))
+    assert rel <= 1e-5
+    assert st["sweeps"] <= st0["sweeps"]
+    print(f"kappa 1e-8 inner {inner}: max rel err {rel:.2e}, sweeps {st['sweeps']} vs "
+          f"{st0['sweeps']}, updates {st['updates']} vs {st0['updates']}", flush=True)

@@ -40,3 +40,26 @@ def test_generators_deterministic():
     assert np.array_equal(a.F, b.F) and np.array_equal(a.src, b.src)
     c = W.maze(33, seed=10, n_sources=3)
     assert not np.array_equal(a.F, c.F) or not np.array_equal(a.src, c.src)
+
+
+def test_shell_maze_recipe():
+    """Four shells of speed 0.001 between radii r0 and r0 + 1/12 (r0 = .3, .5, .7, .9), openings
+    x^2 + y^2 < 1/10 on alternating sides, exit at the origin."""
+    p = W.shell_maze(65)
+    n = 65
+    c = np.linspace(-1, 1, n)
+    assert p.h == 2.0 / 64 and list(p.src[0]) == [32, 32, 32]
+    assert p.F[32, 32, 32] == 1.0
+    # along the x axis (y = z = 0) the openings never apply (they need x^2 < 1/10 and z != 0)
+    line = p.F[32, 32, :]
+    for i, v in enumerate(c):
+        in_shell = any(r0 < abs(v) < r0 + 1 / 12 for r0 in (0.3, 0.5, 0.7, 0.9))
+        assert line[i] == (np.float32(0.001) if in_shell else 1.0), (i, v)
+    # along -z through the first shell's opening (x = y = 0, z < 0): open; along +z: closed
+    colz = p.F[:, 32, 32]
+    for k, v in enumerate(c):
+        r = abs(v)
+        if 0.3 < r < 0.3 + 1 / 12:
+            assert colz[k] == (1.0 if v < 0 else np.float32(0.001))
+        if 0.5 < r < 0.5 + 1 / 12:
+            assert colz[k] == (1.0 if v > 0 else np.float32(0.001))
