@@ -55,10 +55,11 @@ extern "C" {
 
 /* Arithmetic modes (eik_options.mode). */
 #define EIK_MODE_FP64 0  /* all storage and arithmetic in FP64                            */
-/* Values stored, swept and solved in FP32 throughout (the single-precision variant of Section 6:
- * the same method with single-precision data and intermediates); the result is widened to FP64
- * in u_out.  Its accuracy is that of FP32 arithmetic accumulated along characteristics (about
- * 1e-6 relative on the grids here), not the FP64 bar; exit values are rounded to FP32. */
+/* Values stored and swept in FP32 (half the value and face bytes, FP32 comparisons and sorting,
+ * FP32 one- and two-term roots) with the three-term root of eq. (2) computed in FP64 from the
+ * FP32 inputs and rounded once; the result is widened to FP64 in u_out.  Accuracy is that of
+ * FP32 storage accumulated along characteristics (max relative error about 1e-5, mean about
+ * 1e-7 on the grids here), not the FP64 bar; exit values are rounded to FP32. */
 #define EIK_MODE_FP32 1
 /* FP32 bulk, FP64 polish: the method runs in EIK_MODE_FP32, its result is lifted above the FP64
  * solution (times 1 + 2^-12) and every cell is then swept again in FP64 from there (values only

@@ -247,9 +247,10 @@ __device__ __forceinline__ double local_solve(double m0, double m1, double m2, d
     return u1 <= b ? u1 : u;
 }
 
-// The same local solve in single precision throughout (the single-precision variant of
-// Section 6): same term selection, same difference-form discriminants, hardware square root
-// (within one ulp of the FP32 result).
+// The local solve in the single-precision mode: FP32 values, sort, term selection and two-term
+// root; the three-term root -- the step whose rounding dominates the FP32 error, because its sum
+// a + b + c and discriminant are formed at the scale of U -- in FP64 from the FP32 inputs,
+// rounded once to FP32.  Hardware FP32 square root (within one ulp).
 __device__ __forceinline__ float fsqrt_pos(float d) { return d > 0.f ? __builtin_amdgcn_sqrtf(d) : 0.f; }
 __device__ __forceinline__ float local_solve(float m0, float m1, float m2, float s) {
     const float t1 = vmin(m0, m1), t2 = vmax(m0, m1);
@@ -259,11 +260,12 @@ __device__ __forceinline__ float local_solve(float m0, float m1, float m2, float
     const float u1 = a + s;
     const float dab = b - a, dca = c - a, dcb = c - b;
     const bool two = fmaf(dca, dca, dcb * dcb) >= ss;
-    const float d2 = fmaf(-dab, dab, 2.f * ss);
-    const float d3 = fmaf(-dca, dca, fmaf(-dcb, dcb, fmaf(-dab, dab, 3.f * ss)));
-    const float sum = two ? a + b : (a + b) + c;
-    const float u = (sum + fsqrt_pos(two ? d2 : d3)) * (two ? 0.5f : (1.f / 3.f));
-    return u1 <= b ? u1 : u;
+    const float u2 = (a + b + fsqrt_pos(fmaf(-dab, dab, 2.f * ss))) * 0.5f;
+    const double ad = a, bd = b, cd = c, sd = s;
+    const double e1 = bd - ad, e2 = cd - ad, e3 = cd - bd;
+    const double d3 = fma(-e2, e2, fma(-e3, e3, fma(-e1, e1, 3.0 * sd * sd)));
+    const float u3 = (float)(((ad + bd) + cd + disc_sqrt(d3)) * (1.0 / 3.0));
+    return u1 <= b ? u1 : (two ? u2 : u3);
 }
 
 // ------------------------------------------------------------------------------------------
