@@ -95,9 +95,10 @@ typedef struct eik_options {
                              of the priority worklist): cells with value < min + delta are
                              swept, the rest wait.  0 = default (+inf: every queued cell)    */
     int64_t max_rounds;   /* cap on worklist rounds; 0 = default (1 << 20)                    */
-    int max_sweeps;       /* cap on sweeps per cell visit before the cell is re-queued;
-                             0 = default (512)                                              */
-    int workers;          /* persistent workgroups; 0 = as many as fit on the device         */
+    int max_sweeps;       /* cap on sweeps (list passes) per cell visit: a visit that reaches
+                             it publishes its changes, keeps its active nodes and re-queues
+                             the cell; 0 = default (8 for sweeps, 512 otherwise)            */
+    int workers;          /* persistent workgroups (one fills a CU); 0 = one per CU          */
     uint64_t shuffle;     /* 0 = natural order; otherwise seed of a pseudo-random permutation
                              of the order in which queued cells are taken (order tests)     */
     int timing;           /* 1: record HIP events around the solve kernel and the whole solve
@@ -126,6 +127,8 @@ typedef struct eik_stats {
     int64_t cycles_sweep; /*   in-cell sweeps                                                 */
     int64_t cycles_write; /*   write-back and tagging of neighbour cells                      */
     int64_t cycles_wait;  /*   publishing the next list and waiting at the round barrier      */
+    int64_t sweep_hist[32];             /* visits by sweep count (bucket 31: 31 or more)      */
+    int64_t visit_cycles_log2_hist[32]; /* visits by duration, bucket floor(log2(cycles))     */
 } eik_stats;
 
 /*
@@ -180,7 +183,7 @@ int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_
 typedef struct eik_tune_entry {
     int cell;             /* r: 4 or 8                                                        */
     int inner;            /* EIK_INNER_SWEEP, EIK_INNER_LIST or EIK_INNER_DUAL                 */
-    int workers;          /* persistent workgroups (0 = as many as fit)                        */
+    int workers;          /* persistent workgroups (0 = one per CU)                            */
     double delta;         /* priority band width (0 = every queued cell each round)            */
     double ms;            /* fastest of `reps` whole eik_solve_ex calls (stream events);       */
                           /* +inf if the configuration did not finish with EIK_OK               */
@@ -191,8 +194,8 @@ typedef struct eik_tune_entry {
  * eik_autotune -- time the solver's configurations on one problem and return the fastest.
  * The best cell size, in-cell solver, worker count and priority band depend on the problem
  * (Section 6 finds the best cell size problem-dependent), so they are measured, not guessed:
- * every combination of r in {8, 4}, inner in {SWEEP, LIST, DUAL} and workers in {all, one
- * workgroup per CU} with no band, then the best of those with bands of 4, 16 and 64 cell
+ * every combination of r in {8, 4}, inner in {SWEEP, LIST, DUAL} and workers in {all, half the
+ * CUs} with no band, then the best of those with bands of 4, 16 and 64 cell
  * crossings (delta = 4 r h, 16 r h, 64 r h).  Each configuration is solved once to warm up and `reps` (1..100)
  * times timed; the problem's arguments are those of eik_solve_ex (u_out receives the result of
  * the last run; every configuration computes the same U up to rounding).  Blocks until done.

@@ -125,9 +125,12 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
     if (opt->inner < 0 || opt->inner > EIK_INNER_DUAL) return EIK_EINVAL;
     std::memset(P, 0, sizeof(*P));
     P->max_rounds = opt->max_rounds > 0 ? opt->max_rounds : (int64_t(1) << 20);
-    P->max_sweeps = opt->max_sweeps > 0 ? opt->max_sweeps : 512;
     // default in-cell solver: sweeps at r = 8, the list relaxation at r = 4 (measured fastest)
     const int inner = opt->inner ? opt->inner : (cell == 8 ? EIK_INNER_SWEEP : EIK_INNER_LIST);
+    // default sweep cap: 8 directional sweeps (one Gray cycle) per visit for the sweeps -- a
+    // longer visit publishes what it has and resumes next round, which keeps rounds short --
+    // and effectively none for the others (their passes are short)
+    P->max_sweeps = opt->max_sweeps > 0 ? opt->max_sweeps : (inner == EIK_INNER_SWEEP ? 8 : 512);
     P->inner = inner == EIK_INNER_SWEEP ? 0 : (inner == EIK_INNER_LIST ? 1 : 2);
     P->delta = opt->delta > 0.0 ? opt->delta : 0.0;
     P->fp32 = opt->mode == EIK_MODE_FP32 ? 1 : 0;
@@ -661,7 +664,7 @@ int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
     const int inners[3] = {EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL};
     for (int cell : cells)
         for (int inner : inners)
-            for (int workers : {0, ncu}) {
+            for (int workers : {0, ncu / 2}) {
                 eik_tune_entry t;
                 std::memset(&t, 0, sizeof(t));
                 t.cell = cell;
@@ -728,7 +731,7 @@ int eik_stream_status(hipStream_t stream, eik_stats* stats) {
     if (e != hipSuccess) return hip_fail(e);
     unsigned char* base = (unsigned char*)w->base;
     int status = 0;
-    unsigned long long st[eik::ST_COUNT];
+    unsigned long long st[eik::ST_TOTAL];
     e = hipMemcpy(&status, base + w->layout.off_small + kSmallStatus, sizeof(int),
                   hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e);
@@ -758,6 +761,10 @@ int eik_stream_status(hipStream_t stream, eik_stats* stats) {
         stats->cycles_sweep = (int64_t)st[eik::ST_CYC_SWEEP];
         stats->cycles_write = (int64_t)st[eik::ST_CYC_WRITE];
         stats->cycles_wait = (int64_t)st[eik::ST_CYC_WAIT];
+        for (int i = 0; i < 32; ++i) {
+            stats->sweep_hist[i] = (int64_t)st[eik::ST_HIST_SWEEPS + i];
+            stats->visit_cycles_log2_hist[i] = (int64_t)st[eik::ST_HIST_CYCLES + i];
+        }
     }
     return status;
 }

@@ -21,17 +21,15 @@ constexpr int EIK_EINVAL_DEV = EIK_EINVAL;
 constexpr int EIK_ENOCONV_DEV = EIK_ENOCONV;
 constexpr int EIK_ECANCELLED_DEV = EIK_ECANCELLED;
 
-// Persistent workers per workgroup (each wave64 is one worker); the dual sweep keeps one more
-// byte array per worker in LDS, so three workers per group keep twelve workers per CU.
-constexpr int kWavesPerGroup = 4;
-constexpr int kWavesPerGroupDual = 3;
 
 // Counter slots.
 enum {
     ST_ROUNDS = 0, ST_VISITS, ST_SWEEPS, ST_UPDATES, ST_DEFERRED, ST_REQUEUED,
     // shader-clock cycles summed over workers, by phase
     ST_CYC_POP, ST_CYC_STAGE, ST_CYC_SWEEP, ST_CYC_WRITE, ST_CYC_WAIT, ST_WORKERS,
-    ST_COUNT = 16
+    ST_COUNT = 16,
+    // histograms over visits: sweeps (bucket min(n, 31)) and duration (bucket floor(log2 cycles))
+    ST_HIST_SWEEPS = 16, ST_HIST_CYCLES = 48, ST_TOTAL = 80
 };
 
 // Per-round control block: pop cursor, list length and smallest cell value in the list, each
@@ -51,7 +49,7 @@ constexpr size_t kSmallCtl = 0;        // 4 x RoundCtl
 constexpr size_t kSmallBar = 1024;     // barrier: arrivals at [0], generation at [64] (uint32)
 constexpr size_t kSmallStatus = 2048;  // int
 constexpr size_t kSmallNextRound = 2112;  // int64: first round of the next launch
-constexpr size_t kSmallStats = 2304;   // ST_COUNT x uint64
+constexpr size_t kSmallStats = 2304;   // ST_TOTAL x uint64
 constexpr size_t kSmallBytes = 4096;
 constexpr int kBarGen = 64;            // index of the generation word in the barrier array
 
@@ -90,7 +88,7 @@ struct SolveParams {
     RoundCtl* ctl;         // [4] control blocks, slot = round & 3
     uint32_t* bar;         // grid barrier: bar[0] arrivals, bar[kBarGen] generation
     int* status;           // device status word of the launch (watchdog, round cap)
-    unsigned long long* stats;  // [ST_COUNT]
+    unsigned long long* stats;  // [ST_TOTAL]
     int64_t* next_round;   // written when the launch ends: the first round of the next launch
     int64_t* round_log;    // optional [2 * round_log_len]
     int64_t round_log_len;

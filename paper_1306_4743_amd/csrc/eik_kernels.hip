@@ -503,20 +503,8 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         }
     }
     wave_sync();
-    // Border values before the visit (to detect which border nodes decrease), then the initial
-    // active set: every node on a first / re-queued visit, otherwise the layer next to each face
+    // The initial active set: every node on a first / re-queued visit, otherwise the layer next to each face
     // that received new inflow.
-    UT before[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        before[f] = INF;
-        if (lane < R2) {
-            int x, y, z;
-            face_node<R>(f, lane % R, lane / R, x, y, z);
-            before[f] = fabs(L.U[box_index<R>(x, y, z)]);
-        }
-    }
-    wave_sync();
     // Marks node b active: the sign bit of its value, or its flag byte for the dual sweep.
     auto activate = [&](int b) {
         if constexpr (INNER == INNER_DUAL) L.A[b] = 1;
@@ -545,7 +533,9 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
 
     const unsigned long long t1 = cycles();
     bool visit_changed = false, requeue = false;
-    uint32_t requeue_bits = INNER == INNER_DUAL ? FL_ALL : 0u;  // how a capped visit resumes
+    // How a capped visit resumes: with its stored active flags, or (dual sweeps) with every node
+    // active.
+    uint32_t requeue_bits = INNER == INNER_DUAL ? FL_ALL : 0u;
     unsigned int upd = 0;
     int nsweeps = 0;
     const bool track_dec = S.tol > 0.0;
@@ -832,11 +822,15 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     int my_target = 0;
     uint32_t my_bits = 0;
     double my_value = __builtin_inf();
+    // A visit publishes every border node below its published face copy (the border at the
+    // last publication) and tags the neighbours across those faces.  A visit cut short by the
+    // sweep cap (sweeps and list relaxation) also stores its values with their active flags
+    // (sign bits), so the next visit resumes with the same active set.  Only the cell's own
+    // visits read the stored flags; face copies and the output are taken through |.|.
+    // (Publishing the partial result lets the neighbours start a round earlier; measured, that
+    // beats holding it back until the cell completes.)
+    const bool keep_active = requeue && INNER != INNER_DUAL;
     if (visit_changed) {
-        // A visit cut short by the sweep cap keeps its active flags (the sign bits) in the
-        // stored values, so the next visit resumes with the same active set.  Only the cell's
-        // own visits read them; face copies and the output are taken through |.|.
-        const bool keep_active = requeue && INNER != INNER_DUAL;
         UT* __restrict__ uw = reinterpret_cast<UT*>(S.u) + (size_t)lc * R3;
         UT* __restrict__ fw = reinterpret_cast<UT*>(S.faces);
         for (int l = lane; l < R3; l += 64) {
@@ -844,29 +838,31 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
             const UT v = L.U[box_index<R>(x, y, z)];
             uw[l] = keep_active ? v : fabs(v);
         }
+        {
 #pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            const int nb = cell_neighbour(S, lc, cc, f);
-            bool ch = false, inflow = false;
-            UT v = INF;
-            if (lane < R2) {
-                int x, y, z;
-                face_node<R>(f, lane % R, lane / R, x, y, z);
-                const int b = box_index<R>(x, y, z);
-                v = fabs(L.U[b]);
-                ch = v < before[f];
-                inflow = ch && v < fabs(L.U[b + face_step<R>(f)]);
-            }
-            if (__any(ch) && lane < R2)
-                fw[((size_t)lc * 6 + f) * R2 + lane] = v;
-            if (nb >= 0 && __any(inflow)) {
-                const double kv = (double)wave_min(inflow ? v : INF);
-                if (lane == f) {
-                    const int g = f ^ 1;
-                    my_tag = true;
-                    my_target = S.cell_base + nb;
-                    my_bits = (1u << g) | (pref_mask_for_face(g) << FL_DIR_SHIFT);
-                    my_value = kv;
+            for (int f = 0; f < 6; ++f) {
+                const int nb = cell_neighbour(S, lc, cc, f);
+                bool ch = false, inflow = false;
+                UT v = INF;
+                UT* const fp = fw + ((size_t)lc * 6 + f) * R2 + lane;
+                if (lane < R2) {
+                    int x, y, z;
+                    face_node<R>(f, lane % R, lane / R, x, y, z);
+                    const int b = box_index<R>(x, y, z);
+                    v = fabs(L.U[b]);
+                    ch = v < *fp;
+                    inflow = ch && v < fabs(L.U[b + face_step<R>(f)]);
+                }
+                if (__any(ch) && lane < R2) *fp = v;
+                if (nb >= 0 && __any(inflow)) {
+                    const double kv = (double)wave_min(inflow ? v : INF);
+                    if (lane == f) {
+                        const int g = f ^ 1;
+                        my_tag = true;
+                        my_target = S.cell_base + nb;
+                        my_bits = (1u << g) | (pref_mask_for_face(g) << FL_DIR_SHIFT);
+                        my_value = kv;
+                    }
                 }
             }
         }
@@ -940,6 +936,10 @@ k_solve(SolveParams P) {
     load_plane_regs<R, INNER>(pr, lane);
     unsigned long long visits = 0, deferred = 0;
     int rounds_done = 0;
+    // Per-workgroup histograms of visits (sweeps; log2 of cycles), flushed at the end.
+    __shared__ unsigned int s_hist[64];
+    if (threadIdx.x < 64) s_hist[threadIdx.x] = 0u;
+    __syncthreads();
 
     const int nwaves_total = (int)gridDim.x * W;
     for (int64_t t = P.round_begin;; ++t) {
@@ -961,13 +961,16 @@ k_solve(SolveParams P) {
                              : (n >= (uint32_t)nwaves_total * 8u ? 4u
                              : (n >= (uint32_t)nwaves_total * 2u ? 2u : 1u));
         WaveQueue wq{0, __builtin_inf()};
+        uint32_t chunk_now = chunk;
         for (;;) {
             const unsigned long long tp0 = cycles();
             uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&ctl_cur->cursor, chunk);
+            if (lane == 0) base = atomicAdd(&ctl_cur->cursor, chunk_now);
             base = __shfl(base, 0, 64);
             if (base >= n) { cyc_pop += cycles() - tp0; break; }
-            const uint32_t cnt_here = n - base < chunk ? n - base : chunk;
+            const uint32_t cnt_here = n - base < chunk_now ? n - base : chunk_now;
+            // The last cells of the round go one per pop, so that the round's tail is short.
+            if (n - base < (uint32_t)nwaves_total * 2u) chunk_now = 1u;
             // Lanes j < cnt_here take cell j of the chunk: its flags and value are exchanged
             // for empty ones (the removal of Algorithm 2 with V^c <- +inf).
             int my_c = 0;
@@ -996,7 +999,14 @@ k_solve(SolveParams P) {
                 const double key = bitsd(__shfl(my_kb, (int)j, 64));
                 if (!(key < thr)) continue;
                 ++visits;
+                const unsigned long long sw0 = cnt.sweeps, tv0 = cycles();
                 visit_cell<R, FT, INNER, UT>(P, c, fl, key, L, pr, lane, ctl_next, nxt, cnt, wq);
+                if (lane == 0) {
+                    const unsigned long long dsw = cnt.sweeps - sw0, dt = cycles() - tv0;
+                    atomicAdd(&s_hist[dsw < 31 ? dsw : 31], 1u);
+                    const int lg = dt ? 63 - __builtin_clzll(dt) : 0;
+                    atomicAdd(&s_hist[32 + (lg < 31 ? lg : 31)], 1u);
+                }
             }
         }
         const unsigned long long tw0 = cycles();
@@ -1042,6 +1052,10 @@ k_solve(SolveParams P) {
         atomicAdd(&P.stats[ST_WORKERS], 1ull);
         if (blockIdx.x == 0 && wave == 0) atomicAdd(&P.stats[ST_ROUNDS], (unsigned long long)rounds_done);
     }
+    // Every workgroup leaves the round loop in the same round, so all its waves get here.
+    __syncthreads();
+    if (threadIdx.x < 64 && s_hist[threadIdx.x])
+        atomicAdd(&P.stats[ST_HIST_SWEEPS + threadIdx.x], (unsigned long long)s_hist[threadIdx.x]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1113,7 +1127,7 @@ __global__ void k_init_global(SolveParams P) {
         *P.status = 0;
         *P.next_round = 0;
     }
-    if (g0 < ST_COUNT) P.stats[g0] = 0;
+    for (int g = g0; g < ST_TOTAL; g += 64) P.stats[g] = 0;
 }
 
 // Seed (a2): exit nodes fixed at q (min over duplicates), marked as exits in the blocked speed
@@ -1264,7 +1278,7 @@ static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int worker
     e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
     if (e != hipSuccess) return e;
     const size_t granule = 2048;
-    const size_t lds_alloc = (lds + 256 + granule - 1) / granule * granule;
+    const size_t lds_alloc = (lds + 1024 + granule - 1) / granule * granule;  // + static LDS
     const int per_cu_lds = (int)((size_t)lds_cu / lds_alloc);
     if (per_cu_lds < per_cu) per_cu = per_cu_lds;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
@@ -1286,13 +1300,27 @@ static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int worker
     return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(64 * W), args, lds, s);
 }
 
+// Workers (waves) per workgroup: one workgroup fills a CU -- as many waves as the register
+// budget allows (three per SIMD in FP64, four in FP32), bounded by the CU's LDS -- so a round
+// barrier has one arrival and one release/acquire pair per CU (each of those costs
+// microseconds per round at hundreds of workgroups).
+template <int R, int INNER, typename UT>
+constexpr int waves_per_group() {
+    constexpr int by_regs = sizeof(UT) == 4 ? 16 : 12;
+    constexpr int by_lds = (int)((150u * 1024u) / sizeof(WaveLds<R, INNER, UT>));
+    return by_regs < by_lds ? by_regs : by_lds;
+}
+
 template <int R, typename FT, typename UT>
 static hipError_t solve_rounds_ut(const SolveParams& P, hipStream_t s, int workers, int* used) {
     if (P.inner == INNER_SWEEP)
-        return launch_solve_t<R, FT, kWavesPerGroup, INNER_SWEEP, UT>(P, s, workers, used);
+        return launch_solve_t<R, FT, waves_per_group<R, INNER_SWEEP, UT>(), INNER_SWEEP, UT>(
+            P, s, workers, used);
     if (P.inner == INNER_LIST)
-        return launch_solve_t<R, FT, kWavesPerGroup, INNER_LIST, UT>(P, s, workers, used);
-    return launch_solve_t<R, FT, kWavesPerGroupDual, INNER_DUAL, UT>(P, s, workers, used);
+        return launch_solve_t<R, FT, waves_per_group<R, INNER_LIST, UT>(), INNER_LIST, UT>(
+            P, s, workers, used);
+    return launch_solve_t<R, FT, waves_per_group<R, INNER_DUAL, UT>(), INNER_DUAL, UT>(
+        P, s, workers, used);
 }
 
 template <int R, typename FT>

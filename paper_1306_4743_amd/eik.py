@@ -57,10 +57,14 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("rounds", "visits", "sweeps", "updates", "deferred", "requeued", "cells",
                  "status", "workers", "cycles_pop", "cycles_stage", "cycles_sweep",
-                 "cycles_write", "cycles_wait")]
+                 "cycles_write", "cycles_wait")] + [
+                ("sweep_hist", ctypes.c_int64 * 32), ("visit_cycles_log2_hist", ctypes.c_int64 * 32)]
 
     def as_dict(self):
-        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+        d = {n: int(getattr(self, n)) for n, t in self._fields_ if t is ctypes.c_int64}
+        d["sweep_hist"] = [int(v) for v in self.sweep_hist]
+        d["visit_cycles_log2_hist"] = [int(v) for v in self.visit_cycles_log2_hist]
+        return d
 
 
 _lib = None

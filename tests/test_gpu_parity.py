@@ -196,12 +196,13 @@ def test_round_cap_gives_upper_bound(orc, torch_dev):
     compare(got2, want, p)
 
 
+@pytest.mark.parametrize("cap", [1, 3])
 @pytest.mark.parametrize("inner", INNERS)
-def test_sweep_cap_requeues(orc, torch_dev, inner):
-    """A cap of one sweep (one pass) per visit forces productive visits to re-queue their cell;
-    the answer is unchanged."""
+def test_sweep_cap_requeues(orc, torch_dev, inner, cap):
+    """A cap of one or three sweeps (passes) per visit forces productive visits to publish,
+    keep their active nodes and re-queue their cell; the answer is unchanged."""
     p = W.oscillatory(49, periods=3)
-    _, stats = check(orc, torch_dev, p, tol=0.0, max_sweeps=1, inner=inner)
+    _, stats = check(orc, torch_dev, p, tol=0.0, max_sweeps=cap, inner=inner)
     assert stats["requeued"] > 0
 
 
@@ -345,3 +346,15 @@ def test_early_termination_kappa(orc, torch_dev, inner):
     assert st["sweeps"] <= st0["sweeps"]
     print(f"kappa 1e-8 inner {inner}: max rel err {rel:.2e}, sweeps {st['sweeps']} vs "
           f"{st0['sweeps']}, updates {st['updates']} vs {st0['updates']}", flush=True)
+
+
+def test_visit_histograms_account_for_every_visit(torch_dev):
+    """The per-visit histograms count every visit once; the sweep histogram reproduces the
+    sweep total below its last bucket."""
+    p = W.maze(65, seed=5, n_sources=2)
+    _, rc, st = run_gpu(torch_dev, p, tol=0.0)
+    assert rc == 0
+    h = st["sweep_hist"]
+    assert sum(h) == st["visits"] == sum(st["visit_cycles_log2_hist"])
+    if h[31] == 0:
+        assert sum(i * c for i, c in enumerate(h)) == st["sweeps"]
