@@ -104,6 +104,8 @@ def main():
                     help="requests of the mixed-size serving stream (0: skip the serving leg)")
     ap.add_argument("--serving-rounds", type=int, default=16,
                     help="worklist rounds per server step in the serving leg")
+    ap.add_argument("--precision-n", type=int, default=1025,
+                    help="side of the Gaussian-bumps grid of the precision leg (0: skip it)")
     ap.add_argument("--copy-reference-mib", type=int, default=0,
                     help="only run plain device-to-device copies of this many MiB (calibrates "
                          "the HBM byte counters of a profiler against a known size)")
@@ -211,11 +213,54 @@ def main():
                 raise SystemExit(f"sample solve failed: {eik.strerror(rcq)}")
             return uq.cpu().numpy()
         line["cpu_baseline"] = cpu_baseline(args, gpu_solve)
-    if args.serving_requests > 0:
-        del F, u
+    del F, u
+    torch.cuda.empty_cache()
+    if args.precision_n > 0:
+        line["precision"] = precision_leg(args, dev)
         torch.cuda.empty_cache()
+    if args.serving_requests > 0:
         line["serving"] = serving_leg(args)
     print(json.dumps(line), flush=True)
+
+
+def precision_leg(args, dev):
+    """The precision workload: Gaussian bumps (32 bumps, clamp [0.2, 2], centre exit, seed 4)
+    at n^3, FP32 speeds, solved in FP64, FP32 and mixed precision; differences to the FP64
+    result (which the test suite holds to eq. (2) at every node)."""
+    import torch
+    from paper_1306_4743_amd import eik, workloads as W
+    p = W.bumps(args.precision_n, seed=4, device=dev)
+    F = torch.from_numpy(p.F).to(dev)
+    nodes = p.nodes
+    del p.F
+    out = {"workload": f"Gaussian bumps {args.precision_n}^3, 32 bumps, seed 4, FP32 speeds, "
+                       f"cell {args.cell}, tol 0"}
+    ref = None
+    for name, mode in (("fp64", eik.EIK_MODE_FP64), ("fp32", eik.EIK_MODE_FP32),
+                       ("mixed", eik.EIK_MODE_MIXED)):
+        u = eik.solve(F, p.h, p.src, p.q, cell=args.cell, mode=mode)  # warm-up (workspace)
+        eik.status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = eik.solve(F, p.h, p.src, p.q, cell=args.cell, mode=mode, u_out=u, timing=True)
+        rc, st = eik.status()
+        wall = time.perf_counter() - t0
+        if rc != 0:
+            raise SystemExit(f"precision leg ({name}) failed: {eik.strerror(rc)}")
+        ks, _ = eik.kernel_times(1)
+        r = {"ms": 1000.0 * wall, "solved_nodes_per_s": nodes / wall,
+             "solve_kernel_ms": float(ks[0]), "visits_per_cell": st["visits"] / st["cells"]}
+        if ref is None:
+            ref = u
+        else:
+            fin = ref > 0
+            rel = (u[fin] - ref[fin]).abs() / ref[fin]
+            r["max_rel_diff_vs_fp64"] = float(rel.max())
+            r["mean_rel_diff_vs_fp64"] = float(rel.mean())
+            del rel, fin, u
+        out[name] = r
+    del ref, F
+    return out
 
 
 def serving_leg(args):

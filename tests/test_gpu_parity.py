@@ -358,3 +358,38 @@ def test_visit_histograms_account_for_every_visit(torch_dev):
     assert sum(h) == st["visits"] == sum(st["visit_cycles_log2_hist"])
     if h[31] == 0:
         assert sum(i * c for i, c in enumerate(h)) == st["sweeps"]
+
+
+def test_bumps_1025_precision_modes(orc, torch_dev):
+    """The precision workload at its full size: 1025^3 Gaussian bumps (32 bumps, clamp
+    [0.2, 2], centre exit), FP32 speeds.  FP64: eq. (2) at every node (rho <= 1e-13), exact exit,
+    every node reached.  Mixed precision: within 1e-10 of the FP64 result.  FP32 mode: within
+    the single-precision bound of it."""
+    import torch
+    from paper_1306_4743_amd import eik
+    p = W.bumps(1025, seed=4, device=torch_dev)
+    F = torch.from_numpy(p.F).to(torch_dev)
+    u64 = eik.solve(F, p.h, p.src, p.q, cell=8, tol=0.0)
+    rc, st = eik.status()
+    assert rc == 0
+    ref = u64.cpu().numpy()
+    del u64
+    assert np.all(np.isfinite(ref))
+    s = p.src
+    assert np.array_equal(ref[s[:, 2], s[:, 1], s[:, 0]], p.q)
+    rho, nbad = orc.residual(p.F, p.h, p.src, p.q, ref, 1e-13)
+    print(f"bumps 1025^3 FP64: residual {rho:.2e}, bad {nbad}, rounds {st['rounds']}, "
+          f"visits/cell {st['visits'] / st['cells']:.2f}", flush=True)
+    assert nbad == 0 and rho <= 1e-13
+    fin = ref > 0
+    for mode, tol in ((eik.EIK_MODE_MIXED, REL_TOL), (eik.EIK_MODE_FP32, fp32_tolerance(p))):
+        u = eik.solve(F, p.h, p.src, p.q, cell=8, tol=0.0, mode=mode)
+        rc, st = eik.status()
+        assert rc == 0
+        got = u.cpu().numpy()
+        del u
+        err = float(np.max(np.abs(got[fin] - ref[fin]) / ref[fin]))
+        print(f"bumps 1025^3 mode {mode}: max rel diff to FP64 {err:.2e} (bound {tol:.1e})",
+              flush=True)
+        assert err <= tol
+        del got
