@@ -62,9 +62,12 @@ extern "C" {
  * 1e-7 on the grids here), not the FP64 bar; exit values are rounded to FP32. */
 #define EIK_MODE_FP32 1
 /* FP32 bulk, FP64 polish: the method runs in EIK_MODE_FP32, its result is lifted above the FP64
- * solution (times 1 + 2^-12) and every cell is then swept again in FP64 from there (values only
- * decrease, so the FP64 iteration ends at the FP64 solution).  Same accuracy as EIK_MODE_FP64.
- * Single solves and batches only (not servers). */
+ * solution (times 1 + 2^-12), exits are re-seeded exactly, and every cell is queued again with
+ * all nodes active and the smallest of its values as cell value; the FP64 method then runs from
+ * there with a priority band of 8 r h (or options.delta), so cells are polished in the order of
+ * their values.  Values only decrease, so it ends at the FP64 solution: same accuracy as
+ * EIK_MODE_FP64.  Slower than EIK_MODE_FP64 on every workload measured (the polish needs at
+ * least as many dependent rounds as the FP64 solve).  Single solves and batches only. */
 #define EIK_MODE_MIXED 2
 
 /* In-cell solvers (eik_options.inner).  All solve the cell sub-problem of Section 4 exactly:

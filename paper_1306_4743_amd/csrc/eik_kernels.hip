@@ -1220,12 +1220,23 @@ __global__ void k_lift(Slot S32, Slot S64, double factor) {
     for (size_t g = g0; g < nf; g += stride) f64[g] = (double)f32[g] * factor;
 }
 
-// Every cell of a slot joins the list of round `round` with all nodes active.
+// Every cell of a slot joins the list of round `round` with all nodes active and, as its cell
+// value, the smallest of its (lifted) values, so that a priority band polishes the cells in the
+// order of their values.  One wave per cell.
+template <int R>
 __global__ void k_queue_all(SolveParams P, Slot S, int64_t round) {
+    constexpr int R3 = R * R * R;
     RoundCtl* ctl = &P.ctl[round & 3];
     const int par = (int)(round & 1);
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < S.ncell; g += gridDim.x * blockDim.x)
-        tag_cell(P, ctl, par, S.cell_base + g, FL_ALL, 0.0);
+    const int lane = threadIdx.x & 63;
+    const int waves = (int)(gridDim.x * blockDim.x) >> 6;
+    const double* u = reinterpret_cast<const double*>(S.u);
+    for (int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); c < S.ncell; c += waves) {
+        double m = __builtin_inf();
+        for (int l = lane; l < R3; l += 64) m = fmin(m, fabs(u[(size_t)c * R3 + l]));  // NaN pads
+        m = wave_min(m);
+        if (lane == 0) tag_cell(P, ctl, par, S.cell_base + c, FL_ALL, m);
+    }
 }
 
 // Empty round lists and round counter 0 for a following launch (status and counters kept).
@@ -1423,9 +1434,13 @@ hipError_t launch_lift(const Slot& S32, const Slot& S64, int cell, double factor
     return hipGetLastError();
 }
 
-hipError_t launch_queue_all(const SolveParams& P, const Slot& S, int64_t round, hipStream_t s) {
-    hipLaunchKernelGGL(k_queue_all, dim3(blocks_for((size_t)S.ncell, 256)), dim3(256), 0, s, P, S,
-                       round);
+hipError_t launch_queue_all(const SolveParams& P, const Slot& S, int cell, int64_t round,
+                            hipStream_t s) {
+    const int blocks = blocks_for((size_t)S.ncell * 64, 256);
+    if (cell == 8)
+        hipLaunchKernelGGL((k_queue_all<8>), dim3(blocks), dim3(256), 0, s, P, S, round);
+    else
+        hipLaunchKernelGGL((k_queue_all<4>), dim3(blocks), dim3(256), 0, s, P, S, round);
     return hipGetLastError();
 }
 
