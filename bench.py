@@ -25,6 +25,14 @@ if ROOT not in sys.path:
 METRIC = "grid-node updates/s and solved nodes/s at 1e-10 rel err; serving p50/p99"
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 FP64_VECTOR_PEAK_TF = 78.6   # MI355X FP64 vector, published
+# LDS: 256 CUs x 128 bytes per clock x 2.4 GHz
+LDS_PEAK_GBS = 256 * 128 * 2.4
+
+
+def lds_bytes_per_update(s_u: int = 8) -> int:
+    """Algorithmic LDS bytes of one local solve in a sweep step: the node, its six neighbours
+    and s read, the node written back (the activations of neighbours are extra)."""
+    return s_u * 9
 
 
 def bytes_per_visit(cell: int, s_u: int = 8, s_f: int = 4) -> int:
@@ -203,6 +211,10 @@ def main():
                      "traffic": traffic, "bytes_per_visit": bpv, "visits_per_launch": visits,
                      "frac_at_one_visit_per_cell": floor_bytes / (kern_ms / 1000.0) / 1e9
                      / HBM_PEAK_GBS},
+        "lds_roofline": {"achieved": st["updates"] * lds_bytes_per_update() / (kern_ms / 1000.0)
+                         / 1e9, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                         "frac": st["updates"] * lds_bytes_per_update() / (kern_ms / 1000.0) / 1e9
+                         / LDS_PEAK_GBS, "bytes_per_update": lds_bytes_per_update()},
     }
     if not args.no_cpu_baseline:
         def gpu_solve(q):
