@@ -503,8 +503,21 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         }
     }
     wave_sync();
-    // The initial active set: every node on a first / re-queued visit, otherwise the layer next to each face
-    // that received new inflow.
+    // Border values before the visit (every visit publishes its border, so these equal the
+    // published face copies; a border node below them has decreased), then the initial active
+    // set: every node on a first visit, otherwise the layer next to each face that received new
+    // inflow (plus, after a capped visit, the active flags it stored).
+    UT before[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        before[f] = INF;
+        if (lane < R2) {
+            int x, y, z;
+            face_node<R>(f, lane % R, lane / R, x, y, z);
+            before[f] = fabs(L.U[box_index<R>(x, y, z)]);
+        }
+    }
+    wave_sync();
     // Marks node b active: the sign bit of its value, or its flag byte for the dual sweep.
     auto activate = [&](int b) {
         if constexpr (INNER == INNER_DUAL) L.A[b] = 1;
@@ -822,8 +835,8 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     int my_target = 0;
     uint32_t my_bits = 0;
     double my_value = __builtin_inf();
-    // A visit publishes every border node below its published face copy (the border at the
-    // last publication) and tags the neighbours across those faces.  A visit cut short by the
+    // A visit publishes every border node that decreased (below its value at stage-in, which is
+    // the published face copy) and tags the neighbours across those faces.  A visit cut short by the
     // sweep cap (sweeps and list relaxation) also stores its values with their active flags
     // (sign bits), so the next visit resumes with the same active set.  Only the cell's own
     // visits read the stored flags; face copies and the output are taken through |.|.
@@ -844,16 +857,15 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                 const int nb = cell_neighbour(S, lc, cc, f);
                 bool ch = false, inflow = false;
                 UT v = INF;
-                UT* const fp = fw + ((size_t)lc * 6 + f) * R2 + lane;
                 if (lane < R2) {
                     int x, y, z;
                     face_node<R>(f, lane % R, lane / R, x, y, z);
                     const int b = box_index<R>(x, y, z);
                     v = fabs(L.U[b]);
-                    ch = v < *fp;
+                    ch = v < before[f];
                     inflow = ch && v < fabs(L.U[b + face_step<R>(f)]);
                 }
-                if (__any(ch) && lane < R2) *fp = v;
+                if (__any(ch) && lane < R2) fw[((size_t)lc * 6 + f) * R2 + lane] = v;
                 if (nb >= 0 && __any(inflow)) {
                     const double kv = (double)wave_min(inflow ? v : INF);
                     if (lane == f) {
