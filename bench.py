@@ -289,6 +289,7 @@ def serving_leg(args):
         "rounds_per_step": r["rounds_per_step"], "pool_bytes": r["pool_bytes"],
         "saturated_requests_per_s": sat["requests_per_s"],
         "saturated_solved_nodes_per_s": sat["solved_nodes_per_s"],
+        "saturated_fp32_mode_requests_per_s": r["saturated_fp32_mode"]["requests_per_s"],
         "poisson": {f: {k: v[k] for k in pick} for f, v in r["poisson"].items()},
         "one_at_a_time_requests_per_s": one["requests_per_s"],
         "one_at_a_time_solved_nodes_per_s": one["solved_nodes_per_s"],

@@ -12,6 +12,7 @@ the server step (or solve) after which its result is in its output buffer.
 Runs:
   * saturated: every request arrives at time 0; gives the server's throughput (requests/s).
   * Poisson arrivals at fractions (0.5, 0.8, 1.0) of that throughput: p50 / p99 latency.
+  * saturated in FP32 mode (for context: values about 1e-5 relative, not the FP64 bar).
   * one-at-a-time: the same stream, FIFO, each request solved alone with ``eik_solve``.
 
 Usage: python -m paper_1306_4743_amd.serve [--requests N] [--rounds R] [--json]
@@ -84,10 +85,10 @@ def _summary(reqs, arrivals, finish, t_first, t_last):
             "by_size": by}
 
 
-def pool_config(reqs, cell: int, pool_bytes: int):
+def pool_config(reqs, cell: int, pool_bytes: int, mode: int = 0):
     from . import eik
-    per_cell = eik.problem_bytes((cell, cell, cell), cell, eik.EIK_F32)
-    biggest = max(eik.problem_bytes((r.n,) * 3, cell, eik.EIK_F32) for r in reqs)
+    per_cell = eik.problem_bytes((cell, cell, cell), cell, eik.EIK_F32, mode)
+    biggest = max(eik.problem_bytes((r.n,) * 3, cell, eik.EIK_F32, mode) for r in reqs)
     pool_bytes = max(pool_bytes, biggest)
     return pool_bytes, pool_bytes // per_cell + 1
 
@@ -97,7 +98,7 @@ def run_server(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int =
     """Feed ``reqs`` (arriving at ``arrivals`` seconds) to one server; returns the summary."""
     import torch
     from . import eik
-    pool_bytes, max_cells = pool_config(reqs, cell, pool_bytes)
+    pool_bytes, max_cells = pool_config(reqs, cell, pool_bytes, opt.get("mode", 0))
     srv = eik.Server(pool_bytes, max_cells, max_problems, cell=cell, f_dtype=eik.EIK_F32, **opt)
     count = len(reqs)
     finish = np.full(count, np.nan)
@@ -209,6 +210,11 @@ def serve_benchmark(count: int = 2000, rounds: int = 8, cell: int = 8,
         res["arrival_rate_per_s"] = rate
         out["poisson"][str(f)] = res
         say(f"serve: {f:.1f}x rate: p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms")
+    # The same stream served in single precision (values ~1e-5 relative, not the FP64 bar).
+    sat32 = run_server(reqs, np.zeros(count), cell=cell, rounds=rounds, pool_bytes=pool_bytes,
+                       mode=eik.EIK_MODE_FP32)
+    out["saturated_fp32_mode"] = sat32
+    say(f"serve: saturated, FP32 mode {sat32['requests_per_s']:.1f} req/s")
     seq_sat = run_sequential(reqs, np.zeros(count), cell=cell)
     out["one_at_a_time_saturated"] = seq_sat
     say(f"serve: one-at-a-time {seq_sat['requests_per_s']:.1f} req/s")

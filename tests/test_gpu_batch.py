@@ -250,3 +250,33 @@ def test_autotune_picks_a_valid_configuration(orc, torch_dev):
     assert eik.status()[0] == 0
     compare(u.cpu().numpy(), orc.fmm(p.F, p.h, p.src, p.q), p)
     print("autotune best", best, flush=True)
+
+
+def test_fp32_mode_batch_and_server(orc, torch_dev):
+    """FP32 mode through a batch and a server: each grid within the single-precision bound of
+    the oracle (4 n 2^-24), same +inf mask."""
+    import torch
+    from paper_1306_4743_amd import eik
+    ps = mixed_problems()[:5]
+    bound = lambda p: 4.0 * max(p.dims) * 2.0 ** -24
+    outs = eik.solve_batch(as_dicts(ps, torch_dev), cell=8, mode=eik.EIK_MODE_FP32)
+    assert list(eik.batch_status(len(ps))) == [0] * len(ps)
+    for p, u in zip(ps, outs):
+        want = orc.fmm(p.F, p.h, p.src, p.q)
+        got = u.cpu().numpy()
+        assert np.array_equal(np.isinf(got), np.isinf(want))
+        fin = np.isfinite(want) & (want > 0)
+        assert float(np.max(np.abs(got[fin] - want[fin]) / want[fin])) <= bound(p)
+    srv = eik.Server(pool_bytes=64 << 20, max_cells=1 << 14, max_problems=3, cell=8,
+                     mode=eik.EIK_MODE_FP32)
+    queue = [(i, dict(F=torch.from_numpy(p.F).to(torch_dev), h=p.h, idx3=p.src, q=p.q))
+             for i, p in enumerate(ps)]
+    done, _ = run_server(eik, srv, queue, 4)
+    srv.close()
+    for i, p in enumerate(ps):
+        status, u = done[i]
+        assert status == 0
+        want = orc.fmm(p.F, p.h, p.src, p.q)
+        got = u.cpu().numpy()
+        fin = np.isfinite(want) & (want > 0)
+        assert float(np.max(np.abs(got[fin] - want[fin]) / want[fin])) <= bound(p)
