@@ -70,6 +70,15 @@ extern "C" {
  * least as many dependent rounds as the FP64 solve).  Single solves and batches only. */
 #define EIK_MODE_MIXED 2
 
+/* Cell values (eik_options.cell_value), the keys of the priority band:
+ *   EIK_CELL_VALUE_EQ5  eq. (5): the smallest newly decreased inflow value across the shared
+ *                       face; reset to +inf whenever the cell is taken (Section 4).
+ *   EIK_CELL_VALUE_EQ9  eq. (9), the authors' earlier heuristic: the largest such value plus
+ *                       (r h + h) / 2 over the speed at the middle of the tagged cell, combined
+ *                       by min with the cell's previous value, which is never reset. */
+#define EIK_CELL_VALUE_EQ5 0
+#define EIK_CELL_VALUE_EQ9 1
+
 /* In-cell solvers (eik_options.inner).  All solve the cell sub-problem of Section 4 exactly:
  *   EIK_INNER_SWEEP  locking sweeps (Algorithm 3) in the 8 directions, each sweep visiting the
  *                    diagonal planes x'+y'+z' = p of the cell in order (one plane per wave step);
@@ -112,6 +121,8 @@ typedef struct eik_options {
     int64_t round_log_len;
     int inner;            /* in-cell solver: 0 = default (EIK_INNER_SWEEP at cell 8,
                              EIK_INNER_LIST at cell 4), or one of EIK_INNER_*                */
+    int cell_value;       /* EIK_CELL_VALUE_EQ5 (default) or EIK_CELL_VALUE_EQ9; only the
+                             priority band (delta) reads cell values                        */
 } eik_options;
 
 /* Per-solve counters, filled by eik_stream_status(). */

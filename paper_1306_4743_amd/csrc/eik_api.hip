@@ -77,7 +77,7 @@ bool grid_size(const int64_t dims[3], int cell, int f_dtype, int mode, GridSize*
 // global per-cell arrays for `cells` cells.
 struct CommonLayout {
     size_t off_small = 0, off_slots = 0, off_slot_status = 0, off_counts = 0, off_key = 0,
-           off_flags = 0, off_list = 0, off_cell_slot = 0, total = 0;
+           off_flags = 0, off_list = 0, off_cell_slot = 0, off_keep = 0, total = 0;
 };
 
 CommonLayout common_layout(int64_t cells, int slots) {
@@ -92,6 +92,7 @@ CommonLayout common_layout(int64_t cells, int slots) {
     L.off_flags = o; o = align_up(o + 2 * n * 4);
     L.off_list = o; o = align_up(o + 2 * n * 4);
     L.off_cell_slot = o; o = align_up(o + n * 4);
+    L.off_keep = o; o = align_up(o + n * 8);
     L.total = o;
     return L;
 }
@@ -100,6 +101,7 @@ CommonLayout common_layout(int64_t cells, int slots) {
 void bind_common(SolveParams* P, unsigned char* base, const CommonLayout& L, int64_t cells) {
     P->slots = (const Slot*)(base + L.off_slots);
     P->cell_slot = (const int*)(base + L.off_cell_slot);
+    P->key_keep = (uint64_t*)(base + L.off_keep);
     P->key[0] = (uint64_t*)(base + L.off_key);
     P->key[1] = P->key[0] + cells;
     P->flags[0] = (uint32_t*)(base + L.off_flags);
@@ -123,6 +125,8 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
         return EIK_EINVAL;
     if (opt->round_log_len < 0 || (opt->round_log_len > 0 && !opt->round_log)) return EIK_EINVAL;
     if (opt->inner < 0 || opt->inner > EIK_INNER_DUAL) return EIK_EINVAL;
+    if (opt->cell_value != EIK_CELL_VALUE_EQ5 && opt->cell_value != EIK_CELL_VALUE_EQ9)
+        return EIK_EINVAL;
     std::memset(P, 0, sizeof(*P));
     P->max_rounds = opt->max_rounds > 0 ? opt->max_rounds : (int64_t(1) << 20);
     // default in-cell solver: sweeps at r = 8, the list relaxation at r = 4 (measured fastest)
@@ -134,6 +138,7 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
     P->inner = inner == EIK_INNER_SWEEP ? 0 : (inner == EIK_INNER_LIST ? 1 : 2);
     P->delta = opt->delta > 0.0 ? opt->delta : 0.0;
     P->fp32 = opt->mode == EIK_MODE_FP32 ? 1 : 0;
+    P->cell_value = opt->cell_value;
     P->shuffle = opt->shuffle;
     P->watchdog_polls = 1ull << 23;  // several seconds of polling
     P->round_log = opt->round_log;

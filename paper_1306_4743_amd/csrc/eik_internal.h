@@ -73,7 +73,7 @@ struct SolveParams {
     int max_sweeps;
     int inner;             // in-cell solver: 0 sweeps, 1 active-list relaxation, 2 dual sweeps
     int fp32;              // value type of every slot of the launch: 1 FP32, 0 FP64
-    int pad0;
+    int cell_value;        // 0: eq. (5) cell values; 1: eq. (9), kept across visits
     int64_t round_begin;   // first round of this launch
     int64_t round_end;     // the launch stops after round round_end - 1 (end of an epoch)
     int64_t max_rounds;    // absolute cap on rounds -> EIK_ENOCONV
@@ -83,6 +83,7 @@ struct SolveParams {
     const Slot* slots;     // slot table (device)
     const int* cell_slot;  // [global cells] slot of each cell
     uint64_t* key[2];      // cell values (FP64 bit patterns, all >= +0), global cell ids
+    uint64_t* key_keep;    // [global cells] eq. (9) cell values, never reset by a visit
     uint32_t* flags[2];
     int32_t* list[2];
     RoundCtl* ctl;         // [4] control blocks, slot = round & 3

@@ -388,9 +388,19 @@ __device__ __forceinline__ void mark_active(float* p, float v) {
 // Value = atomic min of the cell value and Add Cell = append to the next round's list unless
 // already queued).
 
+// With the eq. (9) cell values the value is first combined with the cell's kept value (which no
+// visit resets), and the kept value lowered to the result.
+__device__ __forceinline__ double kept_value(const SolveParams& P, int c, double value) {
+    if (!P.cell_value) return value;
+    const uint64_t old = atomicMin((unsigned long long*)&P.key_keep[c],
+                                   (unsigned long long)dbits(value));
+    return fmin(bitsd(old), value);
+}
+
 // Single-thread form, used while seeding.
 __device__ __forceinline__ void tag_cell(const SolveParams& P, RoundCtl* ctl_next, int nxt,
                                          int nb, uint32_t bits, double value) {
+    value = kept_value(P, nb, value);
     const uint64_t kb = dbits(value);
     atomicMin((unsigned long long*)&P.key[nxt][nb], (unsigned long long)kb);
     const uint32_t old = atomicOr(&P.flags[nxt][nb], bits | FL_QUEUED);
@@ -428,6 +438,7 @@ __device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCt
                                           int target, uint32_t bits, double value) {
     bool newq = false;
     if (do_tag) {
+        value = kept_value(P, target, value);
         atomicMin((unsigned long long*)&P.key[nxt][target], (unsigned long long)dbits(value));
         const uint32_t old = atomicOr(&P.flags[nxt][target], bits | FL_QUEUED);
         newq = !(old & FL_QUEUED);
@@ -867,7 +878,23 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
                 }
                 if (__any(ch) && lane < R2) fw[((size_t)lc * 6 + f) * R2 + lane] = v;
                 if (nb >= 0 && __any(inflow)) {
-                    const double kv = (double)wave_min(inflow ? v : INF);
+                    // eq. (5): the smallest newly decreased inflow value; eq. (9): the largest
+                    // one plus the time to reach the middle of the neighbour, (r h + h) / 2 at
+                    // the speed there (its middle node, or the nearest node inside the grid).
+                    double kv = (double)wave_min(inflow ? v : INF);
+                    if (P.cell_value) {
+                        kv = (double)wave_max(inflow ? v : -INF);
+                        if (lane == f) {
+                            const CellXYZ nc = cell_coords(S, nb);
+                            const int ex = min(R, S.nx - nc.x * R), ey = min(R, S.ny - nc.y * R),
+                                      ez = min(R, S.nz - nc.z * R);
+                            const int mx = min(R / 2, ex - 1), my = min(R / 2, ey - 1),
+                                      mz = min(R / 2, ez - 1);
+                            const double fv = (double)reinterpret_cast<const FT*>(S.f)[
+                                (size_t)nb * R3 + mx + R * (my + R * mz)];
+                            if (fv > 0.0) kv += 0.5 * (R * S.h + S.h) / fv;
+                        }
+                    }
                     if (lane == f) {
                         const int g = f ^ 1;
                         my_tag = true;
@@ -1120,6 +1147,7 @@ __global__ void k_init_cells(SolveParams P, Slot S, int slot) {
         P.key[1][c] = dbits(INF);
         P.flags[0][c] = 0;
         P.flags[1][c] = 0;
+        P.key_keep[c] = dbits(INF);
         const_cast<int*>(P.cell_slot)[c] = slot;
     }
     if (g0 == 0) *S.status = 0;

@@ -19,6 +19,7 @@ EIK_EBUSY = -6
 EIK_F64, EIK_F32 = 0, 1
 EIK_MODE_FP64, EIK_MODE_FP32, EIK_MODE_MIXED = 0, 1, 2
 EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL = 1, 2, 3
+EIK_CELL_VALUE_EQ5, EIK_CELL_VALUE_EQ9 = 0, 1
 
 
 class EikError(RuntimeError):
@@ -37,7 +38,7 @@ class Options(ctypes.Structure):
                 ("max_rounds", ctypes.c_int64), ("max_sweeps", ctypes.c_int),
                 ("workers", ctypes.c_int), ("shuffle", ctypes.c_uint64), ("timing", ctypes.c_int),
                 ("round_log", ctypes.c_void_p), ("round_log_len", ctypes.c_int64),
-                ("inner", ctypes.c_int)]
+                ("inner", ctypes.c_int), ("cell_value", ctypes.c_int)]
 
 
 class Problem(ctypes.Structure):
@@ -213,7 +214,7 @@ def _sources(F, idx3, q, stream):
 
 
 def _options(delta=0.0, max_rounds=0, max_sweeps=0, workers=0, shuffle=0, timing=False,
-             round_log=None, inner=0, mode=EIK_MODE_FP64):
+             round_log=None, inner=0, mode=EIK_MODE_FP64, cell_value=EIK_CELL_VALUE_EQ5):
     rl_ptr, rl_len = None, 0
     if round_log is not None:
         import torch
@@ -221,7 +222,8 @@ def _options(delta=0.0, max_rounds=0, max_sweeps=0, workers=0, shuffle=0, timing
             raise ValueError("round_log must be a contiguous int64 CUDA tensor")
         rl_ptr, rl_len = round_log.data_ptr(), round_log.numel() // 2
     return Options(int(mode), float(delta), int(max_rounds), int(max_sweeps), int(workers),
-                   int(shuffle), int(bool(timing)), rl_ptr, rl_len, int(inner))
+                   int(shuffle), int(bool(timing)), rl_ptr, rl_len, int(inner),
+                   int(cell_value))
 
 
 def _problem(F, h, idx3, q, tol, u_out, stream):
@@ -238,7 +240,8 @@ def _problem(F, h, idx3, q, tol, u_out, stream):
 def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, stream=None,
           delta: float = 0.0, max_rounds: int = 0, max_sweeps: int = 0, workers: int = 0,
           shuffle: int = 0, timing: bool = False, round_log=None, inner: int = 0,
-          mode: int = EIK_MODE_FP64, check: bool = True):
+          mode: int = EIK_MODE_FP64, cell_value: int = EIK_CELL_VALUE_EQ5,
+          check: bool = True):
     """Enqueue one solve of eq. (2) on ``stream`` (torch stream; default: current stream).
 
     F: torch CUDA tensor [nz, ny, nx] of float32 or float64 speeds (contiguous).
@@ -252,7 +255,7 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
     u_out = _out_tensor(F, u_out)
     src, keep = _sources(F, idx3, q, stream)
     opts = _options(delta, max_rounds, max_sweeps, workers, shuffle, timing, round_log, inner,
-                    mode)
+                    mode, cell_value)
     nz, ny, nx = F.shape
     dims = _dims_array((nx, ny, nz))
     rc = lib.eik_solve_ex(ctypes.cast(dims, ctypes.c_void_p), float(h),

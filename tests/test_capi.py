@@ -206,3 +206,11 @@ def test_mode_sizes_and_server_mode():
     opts = eik._options(mode=eik.EIK_MODE_MIXED)
     assert lib.eik_server_create(ctypes.byref(h), 1 << 20, 100, 4, 8, eik.EIK_F32, None,
                                  ctypes.byref(opts)) == eik.EIK_EINVAL
+
+
+def test_cell_value_option_checked():
+    lib = eik.load()
+    pb, keep = _problem()
+    arr = (eik.Problem * 1)(pb)
+    bad = eik._options(cell_value=2)
+    assert lib.eik_solve_batch(1, arr, eik.EIK_F32, 8, None, ctypes.byref(bad)) == eik.EIK_EINVAL

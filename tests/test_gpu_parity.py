@@ -393,3 +393,14 @@ def test_bumps_1025_precision_modes(orc, torch_dev):
               flush=True)
         assert err <= tol
         del got
+
+
+@pytest.mark.parametrize("inner", INNERS)
+@pytest.mark.parametrize("band", [0.0, 4.0, 32.0])
+def test_eq9_cell_values(orc, torch_dev, band, inner):
+    """The eq. (9) cell values (earlier heuristic, never reset) only change the order in which
+    the priority band takes cells: every band width gives the oracle's solution."""
+    from paper_1306_4743_amd import eik
+    for p in (W.shell_maze(65), W.maze(97, seed=3), W.oscillatory(65, periods=3)):
+        check(orc, torch_dev, p, tol=0.0, inner=inner, delta=band * p.cell * p.h,
+              cell_value=eik.EIK_CELL_VALUE_EQ9)
