@@ -147,7 +147,8 @@ typedef struct eik_stats {
 
 /*
  * eik_solve -- solve eq. (2) on one grid.
- *   dims     host array {nx, ny, nz}, each >= 2, product < 2^31.
+ *   dims     host array {nx, ny, nz}, each >= 2, product < 2^31, and the grid rounded up to
+ *            whole cells (ceil(n / cell) * cell per axis) also below 2^31 nodes.
  *   h        grid step, finite and > 0.
  *   F        device array of nx*ny*nz speeds of type f_dtype, each finite and > 0 (checked on
  *            the device; a violation yields EIK_EINVAL from eik_stream_status()).

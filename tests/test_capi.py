@@ -214,3 +214,17 @@ def test_cell_value_option_checked():
     arr = (eik.Problem * 1)(pb)
     bad = eik._options(cell_value=2)
     assert lib.eik_solve_batch(1, arr, eik.EIK_F32, 8, None, ctypes.byref(bad)) == eik.EIK_EINVAL
+
+
+def test_size_limits():
+    """Grids are limited to fewer than 2^31 nodes, also after rounding up to whole cells
+    (32-bit node and cell-node indices); the limit is checked before any allocation."""
+    assert eik.query_workspace((1280, 1280, 1280), 8, eik.EIK_F32) > 0       # 160^3 cells
+    with pytest.raises(eik.EikError):                                      # 2.1467e9 nodes, but
+        eik.query_workspace((1290, 1290, 1290), 8, eik.EIK_F32)            # 162^3 cells of 512
+    with pytest.raises(eik.EikError):
+        eik.query_workspace((1291, 1291, 1291), 8, eik.EIK_F32)            # >= 2^31 nodes
+    with pytest.raises(eik.EikError):
+        eik.query_workspace((1 << 16, 1 << 16, 2), 8, eik.EIK_F32)
+    # two nodes per side is the smallest grid
+    assert eik.query_workspace((2, 2, 2), 4, eik.EIK_F64) > 0
