@@ -75,6 +75,31 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def _oracle_request(i):
+    """One request of the serving stream recipe solved by the oracle (a worker process)."""
+    import oracle
+    from paper_1306_4743_amd import serve, workloads as W
+    n, ns = serve.request_shape(i)
+    p = W.maze(n, seed=5000 + i, n_sources=ns)
+    t0 = time.perf_counter()
+    oracle.fmm(p.F, p.h, p.src, p.q)
+    return p.nodes, time.perf_counter() - t0
+
+
+def cpu_serving_sample(count: int = 48):
+    """The oracle on the first `count` requests of the serving stream, one request per host
+    core at a time (the serial FMM cannot use more than one core per request)."""
+    import multiprocessing as mp
+    cores = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_request, range(count))
+    wall = time.perf_counter() - t0
+    nodes = sum(r[0] for r in res)
+    return {"requests": count, "cores": cores, "wall_s": wall, "requests_per_s": count / wall,
+            "solved_nodes_per_s": nodes / wall, "cpu_seconds": sum(r[1] for r in res)}
+
+
 def cpu_baseline(args, gpu_solve):
     """The serial oracle (FMM) on a bounded sample: the same maze recipe at 257^3 (seed 3),
     one full solve on one host core; the GPU solves the same sample for a parity spot check."""
@@ -90,7 +115,9 @@ def cpu_baseline(args, gpu_solve):
     fin = np.isfinite(want) & (want > 0)
     rel = float(np.max(np.abs(got[fin] - want[fin]) / want[fin]))
     same_inf = bool(np.array_equal(np.isinf(got), np.isinf(want)))
+    serving = cpu_serving_sample() if args.serving_requests > 0 else None
     return {"value": p.nodes / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+            "serving_sample": serving,
             "sample": f"serial FP64 FMM, one full solve of the barrier maze recipe at 257^3 "
                       f"({p.nodes} nodes, seed 3, 4 sources), {dt:.2f} s on one host core "
                       f"(FMM is serial)",

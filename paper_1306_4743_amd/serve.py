@@ -47,15 +47,27 @@ class Request:
         return self.n ** 3
 
 
+def request_shapes(count: int, seed: int = 1234, sizes=SIZES):
+    """(n, number of exits) of the first `count` requests of the stream."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(sizes[int(rng.integers(len(sizes)))])
+        out.append((n, int(rng.integers(1, 5))))
+    return out
+
+
+def request_shape(i: int, seed: int = 1234, sizes=SIZES):
+    """(n, number of exits) of request i of the stream."""
+    return request_shapes(i + 1, seed, sizes)[i]
+
+
 def make_requests(count: int, device, seed: int = 1234, sizes=SIZES):
     """The request stream: sizes and exit counts from ``seed``, maze i from seed 5000 + i."""
     import torch
     from . import workloads as W
-    rng = np.random.default_rng(seed)
     reqs = []
-    for i in range(count):
-        n = int(sizes[int(rng.integers(len(sizes)))])
-        ns = int(rng.integers(1, 5))
+    for i, (n, ns) in enumerate(request_shapes(count, seed, sizes)):
         F, h, src, q = W.maze_torch(n, 5000 + i, ns, device)
         u = torch.empty(F.shape, dtype=torch.float64, device=device)
         reqs.append(Request(i, n, 5000 + i, ns, F, h, src, q, u))
