@@ -438,8 +438,11 @@ __device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCt
                                           int target, uint32_t bits, double value) {
     bool newq = false;
     if (do_tag) {
-        value = kept_value(P, target, value);
-        atomicMin((unsigned long long*)&P.key[nxt][target], (unsigned long long)dbits(value));
+        // Cell values are only read by a priority band; without one they are not kept.
+        if (P.delta > 0.0) {
+            value = kept_value(P, target, value);
+            atomicMin((unsigned long long*)&P.key[nxt][target], (unsigned long long)dbits(value));
+        }
         const uint32_t old = atomicOr(&P.flags[nxt][target], bits | FL_QUEUED);
         newq = !(old & FL_QUEUED);
         wq.minkey = fmin(wq.minkey, value);
@@ -1023,8 +1026,10 @@ k_solve(SolveParams P) {
                 }
                 my_c = P.list[cur][idx];
                 my_fl = atomicExch(&P.flags[cur][my_c], 0u);
-                my_kb = atomicExch((unsigned long long*)&P.key[cur][my_c],
-                                   (unsigned long long)dbits(__builtin_inf()));
+                my_kb = P.delta > 0.0
+                            ? atomicExch((unsigned long long*)&P.key[cur][my_c],
+                                         (unsigned long long)dbits(__builtin_inf()))
+                            : 0ull;
             }
             // Cells outside the lowest band go straight back to the next round's list.
             const bool defer = (uint32_t)lane < cnt_here && !(bitsd(my_kb) < thr);
