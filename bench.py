@@ -317,6 +317,13 @@ def serving_leg(args):
         "saturated_requests_per_s": sat["requests_per_s"],
         "saturated_solved_nodes_per_s": sat["solved_nodes_per_s"],
         "saturated_fp32_mode_requests_per_s": r["saturated_fp32_mode"]["requests_per_s"],
+        "mixed_fp32_polish": {
+            "saturated_requests_per_s": r["mixed_fp32_polish_saturated"]["requests_per_s"],
+            "max_rel_diff_served_vs_alone":
+                r["mixed_fp32_polish_saturated"]["max_rel_diff_served_vs_alone"],
+            "poisson": {f: {k: v[k] for k in pick}
+                        for f, v in r["mixed_fp32_polish_poisson"].items()},
+        },
         "poisson": {f: {k: v[k] for k in pick} for f, v in r["poisson"].items()},
         "one_at_a_time_requests_per_s": one["requests_per_s"],
         "one_at_a_time_solved_nodes_per_s": one["solved_nodes_per_s"],

@@ -105,7 +105,9 @@ typedef struct eik_options {
     int mode;             /* EIK_MODE_*; default EIK_MODE_FP64                               */
     double delta;         /* width of the cell-value band swept per round (the lowest bucket
                              of the priority worklist): cells with value < min + delta are
-                             swept, the rest wait.  0 = default (+inf: every queued cell)    */
+                             swept, the rest wait.  0 = default (+inf: every queued cell).
+                             In a batch of several grids and in a server, min is taken per
+                             grid (the smallest value queued in that grid).                 */
     int64_t max_rounds;   /* cap on worklist rounds; 0 = default (1 << 20)                    */
     int max_sweeps;       /* cap on sweeps (list passes) per cell visit: a visit that reaches
                              it publishes its changes, keeps its active nodes and re-queues
@@ -222,7 +224,24 @@ int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
                  const eik_sources* sources, double* u_out, double tol, hipStream_t stream,
                  int reps, eik_tune_entry* table, int cap, int* n_out, eik_tune_entry* best);
 
-/* One problem of a batch or of a server: the arguments of eik_solve for one grid. */
+/*
+ * One problem of a batch or of a server: the arguments of eik_solve for one grid, and
+ * optionally an approximation to polish.
+ *
+ * u_approx (device, nx*ny*nz doubles in the layout of u_out, or NULL): a solution of eq. (2)
+ * that is accurate to about single precision, e.g. the u_out of an EIK_MODE_FP32 solve of the
+ * same problem.  The solver then starts from |u_approx| * (1 + 2^-12) instead of +inf (NaN and
+ * +inf entries start at +inf), sets the exits to their exact values, queues every cell with all
+ * of its nodes active, and sweeps in the order of the cells' values, as the second phase of
+ * EIK_MODE_MIXED does.  Values only decrease from their start, so the result is the FP64
+ * solution (to the usual 1e-10 relative accuracy) wherever the scaled start is not below it:
+ * that holds when u_approx is an upper bound or at most 2^-12 relative below the solution.
+ * With no band given (delta = 0), eik_solve_batch takes a band of 8 cell crossings (8 r h,
+ * smallest h of the batch); a server uses its own delta, so give a server that receives
+ * approximations a band.  u_approx is read when the problem starts (in the batch call or at
+ * the server step that admits it) and may be the same buffer as u_out.  Ignored for problems
+ * without exits (their solution is +inf).  Not allowed with EIK_MODE_MIXED (EIK_EINVAL).
+ */
 typedef struct eik_problem {
     int64_t dims[3];      /* as in eik_solve                                                  */
     double h;
@@ -230,6 +249,7 @@ typedef struct eik_problem {
     eik_sources sources;
     double* u_out;        /* device, nx*ny*nz doubles                                          */
     double tol;
+    const double* u_approx;  /* device approximation to polish, or NULL (solve from scratch)   */
 } eik_problem;
 
 /*

@@ -77,7 +77,9 @@ bool grid_size(const int64_t dims[3], int cell, int f_dtype, int mode, GridSize*
 // global per-cell arrays for `cells` cells.
 struct CommonLayout {
     size_t off_small = 0, off_slots = 0, off_slot_status = 0, off_counts = 0, off_key = 0,
-           off_flags = 0, off_list = 0, off_cell_slot = 0, off_keep = 0, total = 0;
+           off_flags = 0, off_list = 0, off_cell_slot = 0, off_keep = 0, off_slot_minkey = 0,
+           total = 0;
+    int nslots = 1;
 };
 
 CommonLayout common_layout(int64_t cells, int slots) {
@@ -93,6 +95,8 @@ CommonLayout common_layout(int64_t cells, int slots) {
     L.off_list = o; o = align_up(o + 2 * n * 4);
     L.off_cell_slot = o; o = align_up(o + n * 4);
     L.off_keep = o; o = align_up(o + n * 8);
+    L.off_slot_minkey = o; o = align_up(o + 4 * ns * 8);
+    L.nslots = (int)ns;
     L.total = o;
     return L;
 }
@@ -113,6 +117,8 @@ void bind_common(SolveParams* P, unsigned char* base, const CommonLayout& L, int
     P->status = (int*)(base + L.off_small + kSmallStatus);
     P->stats = (unsigned long long*)(base + L.off_small + kSmallStats);
     P->next_round = (int64_t*)(base + L.off_small + kSmallNextRound);
+    P->slot_minkey = (uint64_t*)(base + L.off_slot_minkey);
+    P->nslots = L.nslots;
 }
 
 // Options common to single solves, batches and servers.
@@ -144,6 +150,12 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
     P->round_log = opt->round_log;
     P->round_log_len = opt->round_log ? opt->round_log_len : 0;
     return EIK_OK;
+}
+
+// The approximation a problem starts from, or nullptr: none given, or no exits (the solution is
+// +inf everywhere, which no polish from finite values reaches).
+const double* start_values(const eik_problem& pb) {
+    return pb.sources.n > 0 ? pb.u_approx : nullptr;
 }
 
 // Synchronous validation of one problem (host-side sources are checked here).
@@ -414,6 +426,9 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
     }
     if (cells >= (int64_t(1) << 31)) return EIK_EINVAL;
     const bool mixed = opt.mode == EIK_MODE_MIXED;
+    bool polish = false;  // some problem starts from a given approximation
+    for (int i = 0; i < n; ++i) polish = polish || start_values(pbs[i]) != nullptr;
+    if (polish && mixed) return EIK_EINVAL;
     const int ntab = mixed ? 2 * n : n;  // slot table entries (FP64 slots, then FP32 twins)
     const CommonLayout L = common_layout(cells, ntab);
 
@@ -424,6 +439,7 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
     if (rc != EIK_OK) return rc;
     unsigned char* base = (unsigned char*)w->base;
     bind_common(&P, base, L, cells);
+    P.slot_band = n > 1;  // a band per grid: the grids of a batch advance side by side
     int* slot_status = (int*)(base + L.off_slot_status);
 
     // Slot table, built on the host and copied with the sources through one pinned buffer.
@@ -457,21 +473,34 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
     }
     // Mixed precision runs the method twice: in FP32 on the twins, then lifted and polished in
     // FP64 (every cell queued with all nodes active, exits re-seeded with their exact values).
+    // A given approximation is polished the same way; both polishes take the cells in the order
+    // of their values, a band of polish_band cell crossings (r h, smallest h of the batch) at a
+    // time, unless a band was given.
+    if ((mixed || polish) && !(opt.delta > 0.0)) {
+        double hmin = pbs[0].h;
+        for (int i = 1; i < n; ++i) hmin = std::min(hmin, pbs[i].h);
+        P.delta = kPolishBand * cell * hmin;
+    }
     SolveParams P1 = P;
     const Slot* first = slots.data();
     if (mixed) {
         P1.fp32 = 1;
+        P1.delta = opt.delta;  // the FP32 phase uses the band asked for (none by default)
         P1.slots = P.slots + n;
         first = slots.data() + n;
     }
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return hip_fail(e);
     if ((e = eik::launch_init_global(P, stream)) != hipSuccess) return hip_fail(e);
     for (int i = 0; i < n; ++i) {
-        e = eik::launch_init_slot(P1, first[i], i, cell, f_dtype, pbs[i].F, stream);
+        const double* u0 = start_values(pbs[i]);
+        e = eik::launch_init_slot(P1, first[i], i, cell, f_dtype, pbs[i].F, u0, kLiftFactor,
+                                  stream);
         if (e != hipSuccess) return hip_fail(e);
         e = eik::launch_seed(P1, first[i], cell, f_dtype, 0, pbs[i].sources.n, refs[i].idx3,
                              refs[i].q, stream);
         if (e != hipSuccess) return hip_fail(e);
+        if (u0 && (e = eik::launch_queue_all(P1, first[i], cell, 0, stream)) != hipSuccess)
+            return hip_fail(e);
     }
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return hip_fail(e);
     if (nsrc_total > 0) {
@@ -488,13 +517,6 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
                                           refs[i].idx3, refs[i].q, stream)) != hipSuccess ||
                     (e = eik::launch_queue_all(P, slots[i], cell, 0, stream)) != hipSuccess)
                     return hip_fail(e);
-            }
-            // The polish takes the cells in the order of their values, a band of polish_band
-            // cell crossings (r h, smallest h of the batch) at a time, unless a band was given.
-            if (!(opt.delta > 0.0)) {
-                double hmin = pbs[0].h;
-                for (int i = 1; i < n; ++i) hmin = std::min(hmin, pbs[i].h);
-                P.delta = kPolishBand * cell * hmin;
             }
             P.round_begin = 0;
             P.round_end = P.max_rounds;
@@ -871,6 +893,9 @@ int eik_server_create(eik_server** out, size_t pool_bytes, int64_t max_cells, in
         return hip_fail(e);
     }
     bind_common(&s->P, (unsigned char*)s->base, s->layout, max_cells);
+    // A band per problem, so that problems admitted later (values near their exits) do not
+    // hold back the ones whose fronts are further on.
+    s->P.slot_band = max_problems > 1;
     s->problems.resize((size_t)max_problems);
     s->free_pool.push_back({0, pool_bytes});
     s->free_cells.push_back({0, max_cells});
@@ -937,11 +962,16 @@ int eik_server_step(eik_server* s, int64_t rounds, int* finished) {
         if (e != hipSuccess) return hip_fail(e);
         for (size_t k = 0; k < s->fresh.size(); ++k) {
             eik_server::Problem& p = s->problems[s->fresh[k]];
-            e = eik::launch_init_slot(s->P, p.slot, s->fresh[k], s->cell, s->f_dtype, p.pb.F, st);
+            const double* u0 = start_values(p.pb);
+            e = eik::launch_init_slot(s->P, p.slot, s->fresh[k], s->cell, s->f_dtype, p.pb.F, u0,
+                                      kLiftFactor, st);
             if (e != hipSuccess) return hip_fail(e);
             e = eik::launch_seed(s->P, p.slot, s->cell, s->f_dtype, s->next_round,
                                  p.pb.sources.n, refs[k].idx3, refs[k].q, st);
             if (e != hipSuccess) return hip_fail(e);
+            if (u0 && (e = eik::launch_queue_all(s->P, p.slot, s->cell, s->next_round, st)) !=
+                          hipSuccess)
+                return hip_fail(e);
             p.started = true;
         }
         s->fresh.clear();

@@ -74,6 +74,8 @@ struct SolveParams {
     int inner;             // in-cell solver: 0 sweeps, 1 active-list relaxation, 2 dual sweeps
     int fp32;              // value type of every slot of the launch: 1 FP32, 0 FP64
     int cell_value;        // 0: eq. (5) cell values; 1: eq. (9), kept across visits
+    int slot_band;         // 1: with a band, each slot's band starts at that slot's own minimum
+    int nslots;            // entries of the slot table (row length of slot_minkey)
     int64_t round_begin;   // first round of this launch
     int64_t round_end;     // the launch stops after round round_end - 1 (end of an epoch)
     int64_t max_rounds;    // absolute cap on rounds -> EIK_ENOCONV
@@ -87,6 +89,7 @@ struct SolveParams {
     uint32_t* flags[2];
     int32_t* list[2];
     RoundCtl* ctl;         // [4] control blocks, slot = round & 3
+    uint64_t* slot_minkey; // [4][nslots] smallest cell value queued per slot, row = round & 3
     uint32_t* bar;         // grid barrier: bar[0] arrivals, bar[kBarGen] generation
     int* status;           // device status word of the launch (watchdog, round cap)
     unsigned long long* stats;  // [ST_TOTAL]
@@ -97,8 +100,10 @@ struct SolveParams {
 
 // Launchers (eik_kernels.hip).  All enqueue on `s` and return the first launch error.
 hipError_t launch_init_global(const SolveParams& P, hipStream_t s);
+// Cells of slot S cleared, speeds staged, values <- +inf or, if u_approx (row-major, device) is
+// given, <- |u_approx| * lift with face copies to match.
 hipError_t launch_init_slot(const SolveParams& P, const Slot& S, int slot, int cell, int f_dtype,
-                            const void* F, hipStream_t s);
+                            const void* F, const double* u_approx, double lift, hipStream_t s);
 hipError_t launch_seed(const SolveParams& P, const Slot& S, int cell, int f_dtype, int64_t round,
                        int64_t nsrc, const int64_t* idx3, const double* q, hipStream_t s);
 hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipStream_t s,

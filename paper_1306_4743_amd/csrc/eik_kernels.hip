@@ -397,9 +397,16 @@ __device__ __forceinline__ double kept_value(const SolveParams& P, int c, double
     return fmin(bitsd(old), value);
 }
 
-// Single-thread form, used while seeding.
-__device__ __forceinline__ void tag_cell(const SolveParams& P, RoundCtl* ctl_next, int nxt,
-                                         int nb, uint32_t bits, double value) {
+// Slot minima of the cell values queued for round `round`.
+__device__ __forceinline__ uint64_t* slot_minkeys(const SolveParams& P, int64_t round) {
+    return P.slot_minkey + (size_t)(round & 3) * (size_t)P.nslots;
+}
+
+// Single-thread form, used while seeding: queue cell nb for round `round`.
+__device__ __forceinline__ void tag_cell(const SolveParams& P, int64_t round, int nb,
+                                         uint32_t bits, double value) {
+    RoundCtl* ctl_next = &P.ctl[round & 3];
+    const int nxt = (int)(round & 1);
     value = kept_value(P, nb, value);
     const uint64_t kb = dbits(value);
     atomicMin((unsigned long long*)&P.key[nxt][nb], (unsigned long long)kb);
@@ -409,6 +416,9 @@ __device__ __forceinline__ void tag_cell(const SolveParams& P, RoundCtl* ctl_nex
         P.list[nxt][i] = nb;
     }
     atomicMin((unsigned long long*)&ctl_next->minkey, (unsigned long long)kb);
+    if (P.slot_band)
+        atomicMin((unsigned long long*)&slot_minkeys(P, round)[P.cell_slot[nb]],
+                  (unsigned long long)kb);
 }
 
 // Wave-level publishing of newly queued cells: they collect in the wave's LDS buffer and are
@@ -417,6 +427,12 @@ struct WaveQueue {
     int n;          // entries in the LDS buffer (wave-uniform)
     double minkey;  // per-lane smallest value tagged this round (used with a priority band)
 };
+
+// Slot minima of the round whose control block is ctl_next.
+__device__ __forceinline__ uint64_t* slot_minkeys_of(const SolveParams& P,
+                                                     const RoundCtl* ctl_next) {
+    return P.slot_minkey + (size_t)(ctl_next - P.ctl) * (size_t)P.nslots;
+}
 
 template <int R, int INNER, typename UT>
 __device__ __forceinline__ void queue_flush(const SolveParams& P, int nxt, RoundCtl* ctl_next,
@@ -432,10 +448,11 @@ __device__ __forceinline__ void queue_flush(const SolveParams& P, int nxt, Round
 
 // Every lane with do_tag set tags one cell (any lanes, in parallel): cell value <- min(value),
 // flags |= bits | QUEUED, and the cell joins the next round's list unless already queued.
+// band_slot: the slot of every tagged cell when they share one (a visit's neighbours), or -1.
 template <int R, int INNER, typename UT>
 __device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCtl* ctl_next,
                                           WaveLds<R, INNER, UT>& L, int lane, WaveQueue& wq, bool do_tag,
-                                          int target, uint32_t bits, double value) {
+                                          int target, uint32_t bits, double value, int band_slot) {
     bool newq = false;
     if (do_tag) {
         // Cell values are only read by a priority band; without one they are not kept.
@@ -446,6 +463,16 @@ __device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCt
         const uint32_t old = atomicOr(&P.flags[nxt][target], bits | FL_QUEUED);
         newq = !(old & FL_QUEUED);
         wq.minkey = fmin(wq.minkey, value);
+        if (P.slot_band && P.delta > 0.0 && band_slot < 0)
+            atomicMin((unsigned long long*)&slot_minkeys_of(P, ctl_next)[P.cell_slot[target]],
+                      (unsigned long long)dbits(value));
+    }
+    if (P.slot_band && P.delta > 0.0 && band_slot >= 0) {
+        // One atomic for the visit: the smallest value it queued in its slot.
+        const double m = wave_min(do_tag ? value : __builtin_inf());
+        if (lane == 0 && m < __builtin_inf())
+            atomicMin((unsigned long long*)&slot_minkeys_of(P, ctl_next)[band_slot],
+                      (unsigned long long)dbits(m));
     }
     const uint64_t mask = __ballot(newq);
     const int k = __popcll(mask);
@@ -490,7 +517,8 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     const unsigned long long t0 = cycles();
     // The cell's grid (slot) and its local index there; c itself is a global cell id.
     c = __builtin_amdgcn_readfirstlane(c);
-    const Slot S = P.slots[P.cell_slot[c]];
+    const int slot = P.cell_slot[c];
+    const Slot S = P.slots[slot];
     const int lc = c - S.cell_base;
     const CellXYZ cc = cell_coords(S, lc);
     const UT* __restrict__ ug = reinterpret_cast<const UT*>(S.u) + (size_t)lc * R3;
@@ -918,7 +946,8 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
         }
         cnt.requeued += 1;
     }
-    tag_lanes<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits, my_value);
+    tag_lanes<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits, my_value,
+                            slot);
     const unsigned long long t3 = cycles();
     cnt.cyc_stage += t1 - t0;
     cnt.cyc_sweep += t2 - t1;
@@ -994,9 +1023,18 @@ k_solve(SolveParams P) {
             r2->cursor = 0;
             r2->minkey = dbits(__builtin_inf());
         }
+        // Per-slot bands: the row of round t + 2 is neither read nor written in round t.
+        const bool slot_band = P.slot_band && P.delta > 0.0;
+        if (slot_band) {
+            uint64_t* r2 = slot_minkeys(P, t + 2);
+            for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P.nslots;
+                 i += gridDim.x * blockDim.x)
+                r2[i] = dbits(__builtin_inf());
+        }
         const uint32_t n = __hip_atomic_load(&ctl_cur->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double thr = P.delta > 0.0 ? bitsd(ld_relaxed_u64(&ctl_cur->minkey)) + P.delta
                                          : __builtin_inf();
+        const uint64_t* smk_cur = slot_band ? slot_minkeys(P, t) : nullptr;
         // Cells per pop: one when the list is short (balance), more when it is long (fewer
         // atomics on the shared cursor).
         const uint32_t chunk = n >= (uint32_t)nwaves_total * 32u ? 8u
@@ -1031,17 +1069,22 @@ k_solve(SolveParams P) {
                                          (unsigned long long)dbits(__builtin_inf()))
                             : 0ull;
             }
-            // Cells outside the lowest band go straight back to the next round's list.
-            const bool defer = (uint32_t)lane < cnt_here && !(bitsd(my_kb) < thr);
-            deferred += __popcll(__ballot(defer));
+            // Cells outside the lowest band (of the whole launch, or of their own slot) go
+            // straight back to the next round's list.
+            double my_thr = thr;
+            if (slot_band && (uint32_t)lane < cnt_here)
+                my_thr = bitsd(ld_relaxed_u64(&smk_cur[P.cell_slot[my_c]])) + P.delta;
+            const bool defer = (uint32_t)lane < cnt_here && !(bitsd(my_kb) < my_thr);
+            const uint64_t defer_mask = __ballot(defer);
+            deferred += __popcll(defer_mask);
             tag_lanes<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq, defer, my_c, my_fl & ~FL_QUEUED,
-                         bitsd(my_kb));
+                         bitsd(my_kb), -1);
             cyc_pop += cycles() - tp0;
             for (uint32_t j = 0; j < cnt_here; ++j) {
                 const int c = __shfl(my_c, (int)j, 64);
                 const uint32_t fl = __shfl(my_fl, (int)j, 64);
                 const double key = bitsd(__shfl(my_kb, (int)j, 64));
-                if (!(key < thr)) continue;
+                if ((defer_mask >> j) & 1ull) continue;
                 ++visits;
                 const unsigned long long sw0 = cnt.sweeps, tv0 = cycles();
                 visit_cell<R, FT, INNER, UT>(P, c, fl, key, L, pr, lane, ctl_next, nxt, cnt, wq);
@@ -1055,7 +1098,7 @@ k_solve(SolveParams P) {
         }
         const unsigned long long tw0 = cycles();
         queue_flush<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq);
-        if (P.delta > 0.0) {
+        if (P.delta > 0.0 && !slot_band) {
             const double mk = wave_min(wq.minkey);
             if (lane == 0 && mk < __builtin_inf())
                 atomicMin((unsigned long long*)&ctl_next->minkey, (unsigned long long)dbits(mk));
@@ -1104,11 +1147,12 @@ k_solve(SolveParams P) {
 
 // ------------------------------------------------------------------------------------------
 // Stage inputs (a1): row-major F -> cell-blocked F of one slot with padding marked 0, u <- +inf
-// (NaN on padding).  Speeds that are not finite and positive set the slot's status to
-// EIK_EINVAL.
+// (NaN on padding), or, to polish a given approximation, u <- |u_approx| * lift.  Speeds that
+// are not finite and positive set the slot's status to EIK_EINVAL.
 
 template <int R, typename FT, typename UT>
-__global__ void k_init_nodes(Slot S, const FT* __restrict__ F) {
+__global__ void k_init_nodes(Slot S, const FT* __restrict__ F, const double* __restrict__ u_approx,
+                             double lift) {
     constexpr int R3 = R * R * R;
     const size_t total = (size_t)S.ncell * R3;
     const UT INF = (UT)__builtin_inf();
@@ -1132,7 +1176,30 @@ __global__ void k_init_nodes(Slot S, const FT* __restrict__ F) {
         fb[g] = fv;
         // Padding nodes hold NaN: the minimum ignores them (like +inf beyond the grid) and
         // every comparison with them is false, so they are never activated or used as inflow.
-        ub[g] = fv == FT(0) ? (UT)__builtin_nan("") : INF;
+        UT v = INF;
+        if (u_approx && fv != FT(0)) {
+            const double a = fabs(u_approx[(size_t)i + (size_t)S.nx * ((size_t)j + (size_t)S.ny * k)]);
+            if (a <= 1.7976931348623157e308) v = (UT)(a * lift);  // +inf and NaN stay +inf
+        }
+        ub[g] = fv == FT(0) ? (UT)__builtin_nan("") : v;
+    }
+}
+
+// Face copies <- the border layers of the (initialised) values, +inf for padding nodes.
+template <int R, typename UT>
+__global__ void k_faces_from_u(Slot S) {
+    constexpr int R2 = R * R, R3 = R * R * R;
+    const size_t nf = (size_t)S.ncell * 6 * R2;
+    const UT* ub = reinterpret_cast<const UT*>(S.u);
+    UT* fb = reinterpret_cast<UT*>(S.faces);
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < nf;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const size_t lc = g / (6 * R2);
+        const int f = (int)((g / R2) % 6), e = (int)(g % R2);
+        int x, y, z;
+        face_node<R>(f, e % R, e / R, x, y, z);
+        const UT v = ub[lc * R3 + x + R * (y + R * z)];
+        fb[g] = v == v ? v : (UT)__builtin_inf();
     }
 }
 
@@ -1160,7 +1227,7 @@ __global__ void k_init_cells(SolveParams P, Slot S, int slot) {
 
 // Round control, barrier, launch status and counters (once per solve or server).
 __global__ void k_init_global(SolveParams P) {
-    const int g0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     const double INF = __builtin_inf();
     if (g0 < 4) {
         P.ctl[g0].count = 0;
@@ -1172,7 +1239,8 @@ __global__ void k_init_global(SolveParams P) {
         *P.status = 0;
         *P.next_round = 0;
     }
-    for (int g = g0; g < ST_TOTAL; g += 64) P.stats[g] = 0;
+    for (int g = g0; g < ST_TOTAL; g += stride) P.stats[g] = 0;
+    for (int g = g0; g < 4 * P.nslots; g += stride) P.slot_minkey[g] = dbits(INF);
 }
 
 // Seed (a2): exit nodes fixed at q (min over duplicates), marked as exits in the blocked speed
@@ -1215,16 +1283,14 @@ __global__ void k_seed(SolveParams P, Slot S, int64_t round, int64_t nsrc,
         const int b = (f >> 1) == 2 ? y : z;
         atomic_min_val(reinterpret_cast<UT*>(S.faces) + ((size_t)lc * 6 + f) * R2 + a + R * b, qu);
     }
-    RoundCtl* ctl = &P.ctl[round & 3];
-    const int par = (int)(round & 1);
-    tag_cell(P, ctl, par, S.cell_base + lc, FL_ALL, (double)qu);
+    tag_cell(P, round, S.cell_base + lc, FL_ALL, (double)qu);
     const int64_t nbr[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
                                {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
     for (int t = 0; t < 6; ++t) {
         const int64_t a = nbr[t][0], b = nbr[t][1], e = nbr[t][2];
         if (a < 0 || a >= S.nx || b < 0 || b >= S.ny || e < 0 || e >= S.nz) continue;
         const int nc = (int)(a / R) + S.ncx * ((int)(b / R) + S.ncy * (int)(e / R));
-        if (nc != lc) tag_cell(P, ctl, par, S.cell_base + nc, FL_ALL, (double)qu);
+        if (nc != lc) tag_cell(P, round, S.cell_base + nc, FL_ALL, (double)qu);
     }
 }
 
@@ -1271,28 +1337,29 @@ __global__ void k_lift(Slot S32, Slot S64, double factor) {
 template <int R>
 __global__ void k_queue_all(SolveParams P, Slot S, int64_t round) {
     constexpr int R3 = R * R * R;
-    RoundCtl* ctl = &P.ctl[round & 3];
-    const int par = (int)(round & 1);
     const int lane = threadIdx.x & 63;
     const int waves = (int)(gridDim.x * blockDim.x) >> 6;
     const double* u = reinterpret_cast<const double*>(S.u);
+    const float* u32 = reinterpret_cast<const float*>(S.u);
     for (int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); c < S.ncell; c += waves) {
         double m = __builtin_inf();
-        for (int l = lane; l < R3; l += 64) m = fmin(m, fabs(u[(size_t)c * R3 + l]));  // NaN pads
+        for (int l = lane; l < R3; l += 64)  // fmin ignores the NaN of padding nodes
+            m = fmin(m, S.fp32 ? fabs((double)u32[(size_t)c * R3 + l]) : fabs(u[(size_t)c * R3 + l]));
         m = wave_min(m);
-        if (lane == 0) tag_cell(P, ctl, par, S.cell_base + c, FL_ALL, m);
+        if (lane == 0) tag_cell(P, round, S.cell_base + c, FL_ALL, m);
     }
 }
 
 // Empty round lists and round counter 0 for a following launch (status and counters kept).
 __global__ void k_reset_rounds(SolveParams P) {
-    const int g0 = threadIdx.x;
+    const int g0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     if (g0 < 4) {
         P.ctl[g0].count = 0;
         P.ctl[g0].cursor = 0;
         P.ctl[g0].minkey = dbits(__builtin_inf());
     }
     if (g0 == 0) *P.next_round = 0;
+    for (int g = g0; g < 4 * P.nslots; g += stride) P.slot_minkey[g] = dbits(__builtin_inf());
 }
 
 // Cells of each slot in the list of the next launch's first round (the host's test for
@@ -1392,31 +1459,39 @@ static int blocks_for(size_t n, int threads) {
 }
 
 hipError_t launch_init_global(const SolveParams& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_global, dim3(1), dim3(64), 0, s, P);
+    hipLaunchKernelGGL(k_init_global, dim3(blocks_for((size_t)4 * P.nslots + 64, 256)), dim3(256),
+                       0, s, P);
     return hipGetLastError();
 }
 
 template <int R, typename UT>
 static void init_slot_t(const SolveParams& P, const Slot& S, int slot, int f_dtype,
-                        const void* F, int blocks, int threads, hipStream_t s) {
+                        const void* F, const double* u_approx, double lift, int blocks,
+                        int threads, hipStream_t s) {
     hipLaunchKernelGGL((k_init_cells<R, UT>), dim3(blocks), dim3(threads), 0, s, P, S, slot);
     if (f_dtype == EIK_F32)
         hipLaunchKernelGGL((k_init_nodes<R, float, UT>), dim3(blocks), dim3(threads), 0, s, S,
-                           reinterpret_cast<const float*>(F));
+                           reinterpret_cast<const float*>(F), u_approx, lift);
     else
         hipLaunchKernelGGL((k_init_nodes<R, double, UT>), dim3(blocks), dim3(threads), 0, s, S,
-                           reinterpret_cast<const double*>(F));
+                           reinterpret_cast<const double*>(F), u_approx, lift);
+    if (u_approx)
+        hipLaunchKernelGGL((k_faces_from_u<R, UT>), dim3(blocks), dim3(threads), 0, s, S);
 }
 
 hipError_t launch_init_slot(const SolveParams& P, const Slot& S, int slot, int cell, int f_dtype,
-                            const void* F, hipStream_t s) {
+                            const void* F, const double* u_approx, double lift, hipStream_t s) {
     const int threads = 256;
     const size_t nodes = (size_t)S.ncell * cell * cell * cell;
     const int blocks = blocks_for(nodes, threads);
-    if (cell == 8 && S.fp32) init_slot_t<8, float>(P, S, slot, f_dtype, F, blocks, threads, s);
-    else if (cell == 8) init_slot_t<8, double>(P, S, slot, f_dtype, F, blocks, threads, s);
-    else if (cell == 4 && S.fp32) init_slot_t<4, float>(P, S, slot, f_dtype, F, blocks, threads, s);
-    else if (cell == 4) init_slot_t<4, double>(P, S, slot, f_dtype, F, blocks, threads, s);
+    if (cell == 8 && S.fp32)
+        init_slot_t<8, float>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+    else if (cell == 8)
+        init_slot_t<8, double>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+    else if (cell == 4 && S.fp32)
+        init_slot_t<4, float>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+    else if (cell == 4)
+        init_slot_t<4, double>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -1490,7 +1565,8 @@ hipError_t launch_queue_all(const SolveParams& P, const Slot& S, int cell, int64
 }
 
 hipError_t launch_reset_rounds(const SolveParams& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset_rounds, dim3(1), dim3(64), 0, s, P);
+    hipLaunchKernelGGL(k_reset_rounds, dim3(blocks_for((size_t)4 * P.nslots + 64, 256)),
+                       dim3(256), 0, s, P);
     return hipGetLastError();
 }
 

@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
 
 class Problem(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int64 * 3), ("h", ctypes.c_double), ("F", ctypes.c_void_p),
-                ("sources", Sources), ("u_out", ctypes.c_void_p), ("tol", ctypes.c_double)]
+                ("sources", Sources), ("u_out", ctypes.c_void_p), ("tol", ctypes.c_double),
+                ("u_approx", ctypes.c_void_p)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -226,30 +227,50 @@ def _options(delta=0.0, max_rounds=0, max_sweeps=0, workers=0, shuffle=0, timing
                    int(cell_value))
 
 
-def _problem(F, h, idx3, q, tol, u_out, stream):
+def _approx(F, u_approx):
+    """Device address of an approximation to polish (0 for none), checked against F."""
+    import torch
+    if u_approx is None:
+        return 0
+    if not (u_approx.is_cuda and u_approx.dtype == torch.float64 and u_approx.shape == F.shape
+            and u_approx.is_contiguous()):
+        raise ValueError("u_approx must be a contiguous float64 CUDA tensor shaped like F")
+    return u_approx.data_ptr()
+
+
+def _problem(F, h, idx3, q, tol, u_out, stream, u_approx=None):
     """(ctypes Problem, u_out tensor, keep-alive objects) of one grid."""
     _f_dtype(F)
     u_out = _out_tensor(F, u_out)
     src, keep = _sources(F, idx3, q, stream)
     nz, ny, nx = F.shape
     pb = Problem((ctypes.c_int64 * 3)(nx, ny, nz), float(h), F.data_ptr(), src,
-                 u_out.data_ptr(), float(tol))
-    return pb, u_out, keep
+                 u_out.data_ptr(), float(tol), _approx(F, u_approx))
+    return pb, u_out, (keep, u_approx)
 
 
 def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, stream=None,
           delta: float = 0.0, max_rounds: int = 0, max_sweeps: int = 0, workers: int = 0,
           shuffle: int = 0, timing: bool = False, round_log=None, inner: int = 0,
           mode: int = EIK_MODE_FP64, cell_value: int = EIK_CELL_VALUE_EQ5,
-          check: bool = True):
+          check: bool = True, u_approx=None):
     """Enqueue one solve of eq. (2) on ``stream`` (torch stream; default: current stream).
 
     F: torch CUDA tensor [nz, ny, nx] of float32 or float64 speeds (contiguous).
     idx3, q: host arrays of exit nodes (i, j, k) and their values, or torch CUDA tensors
     (int64 [n, 3] and float64 [n]).  Returns u_out (allocated if None), a float64 CUDA tensor
     of F's shape.  The call returns after enqueueing; use ``status()`` to wait and read the
-    device-side status and counters.
+    device-side status and counters.  u_approx (float64 CUDA tensor shaped like F, may be
+    u_out): a single-precision-accurate solution to polish to the FP64 one (a one-problem
+    ``eik_solve_batch`` with the problem's ``u_approx`` set).
     """
+    if u_approx is not None:
+        outs = solve_batch([dict(F=F, h=h, src=idx3, q=q, tol=tol, u_out=u_out,
+                                 u_approx=u_approx)], cell=cell, stream=stream, check=check,
+                           delta=delta, max_rounds=max_rounds, max_sweeps=max_sweeps,
+                           workers=workers, shuffle=shuffle, timing=timing, round_log=round_log,
+                           inner=inner, mode=mode, cell_value=cell_value)
+        return outs[0]
     lib = load()
     f_dtype = _f_dtype(F)
     u_out = _out_tensor(F, u_out)
@@ -303,8 +324,8 @@ def problem_bytes(dims, cell: int = 8, f_dtype: int = EIK_F32, mode: int = EIK_M
 def solve_batch(problems, cell: int = 8, stream=None, check: bool = True, **opt):
     """Enqueue one batched solve of independent grids on ``stream``.
 
-    problems: sequence of dicts with keys F, h, src (idx3), q and optional tol, u_out; every F
-    of one dtype.  Returns the list of u_out tensors; ``batch_status(len(problems))`` waits and
+    problems: sequence of dicts with keys F, h, src (idx3), q and optional tol, u_out,
+    u_approx (an approximation to polish); every F of one dtype.  Returns the list of u_out tensors; ``batch_status(len(problems))`` waits and
     returns the per-problem status.
     """
     lib = load()
@@ -317,7 +338,7 @@ def solve_batch(problems, cell: int = 8, stream=None, check: bool = True, **opt)
         if _f_dtype(p["F"]) != f_dtype:
             raise ValueError("every F of a batch has the same dtype")
         pb, u, k = _problem(p["F"], p["h"], p["src"], p["q"], p.get("tol", 0.0),
-                            p.get("u_out"), stream)
+                            p.get("u_out"), stream, p.get("u_approx"))
         arr[i] = pb
         outs.append(u)
         keep.append(k)
@@ -361,8 +382,8 @@ class Server:
         self._pending = {}   # ticket -> (u_out, keep-alive)
         self._staged = []    # keep-alive of problems whose inputs the next step reads
 
-    def submit(self, F, h, idx3, q, tol=0.0, u_out=None):
-        pb, u, keep = _problem(F, h, idx3, q, tol, u_out, None)
+    def submit(self, F, h, idx3, q, tol=0.0, u_out=None, u_approx=None):
+        pb, u, keep = _problem(F, h, idx3, q, tol, u_out, None, u_approx)
         t = ctypes.c_int64(-1)
         rc = self._lib.eik_server_submit(self._h, ctypes.byref(pb), ctypes.byref(t))
         if rc == EIK_EBUSY:

@@ -13,6 +13,9 @@ Runs:
   * saturated: every request arrives at time 0; gives the server's throughput (requests/s).
   * Poisson arrivals at fractions (0.5, 0.8, 1.0) of that throughput: p50 / p99 latency.
   * saturated in FP32 mode (for context: values about 1e-5 relative, not the FP64 bar).
+  * mixed precision, saturated and at Poisson arrivals: an FP32 server solves each request, a
+    second (FP64) server polishes that result (``eik_problem.u_approx``) to the FP64 solution;
+    a request moves from the first server to the second when it retires there.
   * one-at-a-time: the same stream, FIFO, each request solved alone with ``eik_solve``.
 
 Usage: python -m paper_1306_4743_amd.serve [--requests N] [--rounds R] [--json]
@@ -149,6 +152,77 @@ def run_server(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int =
     return res
 
 
+def polish_band(reqs, cell: int) -> float:
+    """Priority band of the polishing server: 32 cell crossings at the finest grid step (on the
+    mixed-size maze stream the fastest of 8, 32, 128 and 512 crossings or no band)."""
+    return 32.0 * cell * min(r.h for r in reqs)
+
+
+def run_server_mixed(reqs, arrivals, cell: int = 8, rounds: int = 8,
+                     pool_bytes: int = 16 << 30, max_problems: int = 512, band=None):
+    """Feed ``reqs`` through an FP32 server and then an FP64 polishing server (u_approx = the
+    FP32 result, in the request's own output buffer); both step in turn on one stream.  A
+    request finishes when the polishing server retires it."""
+    import torch
+    from . import eik
+    p32, c32 = pool_config(reqs, cell, pool_bytes, eik.EIK_MODE_FP32)
+    p64, c64 = pool_config(reqs, cell, pool_bytes, eik.EIK_MODE_FP64)
+    s32 = eik.Server(p32, c32, max_problems, cell=cell, f_dtype=eik.EIK_F32,
+                     mode=eik.EIK_MODE_FP32)
+    s64 = eik.Server(p64, c64, max_problems, cell=cell, f_dtype=eik.EIK_F32,
+                     delta=polish_band(reqs, cell) if band is None else band)
+    count = len(reqs)
+    finish = np.full(count, np.nan)
+    own32, own64 = {}, {}
+    polish_queue = []  # requests whose FP32 result waits for the polishing server
+    nxt, done, on32, on64, steps = 0, 0, 0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while done < count:
+        now = time.perf_counter() - t0
+        while nxt < count and arrivals[nxt] <= now:
+            r = reqs[nxt]
+            t = s32.submit(r.F, r.h, r.src, r.q, 0.0, r.u)
+            if t is None:
+                break
+            own32[t] = nxt
+            nxt += 1
+            on32 += 1
+        while polish_queue:
+            r = reqs[polish_queue[0]]
+            t = s64.submit(r.F, r.h, r.src, r.q, 0.0, r.u, u_approx=r.u)
+            if t is None:
+                break
+            own64[t] = polish_queue.pop(0)
+            on64 += 1
+        if on32 == 0 and on64 == 0:
+            while time.perf_counter() - t0 < arrivals[nxt]:
+                pass
+            continue
+        if on32:
+            for t, (status, _) in s32.step(rounds).items():
+                if status != 0:
+                    raise RuntimeError(f"FP32 server: request {own32[t]}: {eik.strerror(status)}")
+                polish_queue.append(own32.pop(t))
+                on32 -= 1
+            steps += 1
+        if on64:
+            out = s64.step(rounds)
+            tnow = time.perf_counter() - t0
+            for t, (status, _) in out.items():
+                if status != 0:
+                    raise RuntimeError(f"polish server: request {own64[t]}: {eik.strerror(status)}")
+                finish[own64.pop(t)] = tnow
+                done += 1
+                on64 -= 1
+            steps += 1
+    s32.close()
+    s64.close()
+    res = _summary(reqs, arrivals, finish, 0.0, float(np.nanmax(finish)))
+    res["steps"] = steps
+    return res
+
+
 def run_sequential(reqs, arrivals, cell: int = 8, **opt):
     """The same stream, FIFO, one ``eik_solve`` at a time (each waits for the previous)."""
     import torch
@@ -209,6 +283,7 @@ def serve_benchmark(count: int = 2000, rounds: int = 8, cell: int = 8,
     # warm-up: a few requests through a server and alone
     run_server(reqs[:8], np.zeros(8), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
     run_sequential(reqs[:4], np.zeros(4), cell=cell)
+    run_server_mixed(reqs[:8], np.zeros(8), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
     sat = run_server(reqs, np.zeros(count), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
     say(f"serve: saturated {sat['requests_per_s']:.1f} req/s, {sat['steps']} steps")
     alone_diff = check_against_alone(reqs, cell=cell)
@@ -227,6 +302,21 @@ def serve_benchmark(count: int = 2000, rounds: int = 8, cell: int = 8,
                        mode=eik.EIK_MODE_FP32)
     out["saturated_fp32_mode"] = sat32
     say(f"serve: saturated, FP32 mode {sat32['requests_per_s']:.1f} req/s")
+    # FP32 bulk + FP64 polish: the FP64 bar at FP32's cost plus the polish.
+    for r in reqs:
+        r.u.fill_(float("nan"))  # the check below must see the mixed results, not old ones
+    mixed = run_server_mixed(reqs, np.zeros(count), cell=cell, rounds=rounds,
+                             pool_bytes=pool_bytes)
+    mixed["max_rel_diff_served_vs_alone"] = check_against_alone(reqs, cell=cell)
+    out["mixed_fp32_polish_saturated"] = mixed
+    say(f"serve: saturated, FP32 + FP64 polish {mixed['requests_per_s']:.1f} req/s, "
+        f"max rel diff {mixed['max_rel_diff_served_vs_alone']:.1e}")
+    rate = seq_fraction * mixed["requests_per_s"]
+    mp = run_server_mixed(reqs, poisson_arrivals(count, rate), cell=cell, rounds=rounds,
+                          pool_bytes=pool_bytes)
+    mp["arrival_rate_per_s"] = rate
+    out["mixed_fp32_polish_poisson"] = {str(seq_fraction): mp}
+    say(f"serve: FP32 + polish at {seq_fraction}x: p50 {mp['p50_ms']:.1f} p99 {mp['p99_ms']:.1f}")
     seq_sat = run_sequential(reqs, np.zeros(count), cell=cell)
     out["one_at_a_time_saturated"] = seq_sat
     say(f"serve: one-at-a-time {seq_sat['requests_per_s']:.1f} req/s")

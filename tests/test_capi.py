@@ -126,6 +126,22 @@ def test_batch_with_one_invalid_problem_rejected(bad):
     assert lib.eik_solve_batch(3, arr, eik.EIK_F32, 8, None, ctypes.byref(opts)) == eik.EIK_EINVAL
 
 
+def test_problem_struct_layout():
+    """The binding's eik_problem matches the C layout: u_approx follows tol at offset 88."""
+    assert eik.Problem.u_approx.offset == 88 and ctypes.sizeof(eik.Problem) == 96
+
+
+def test_polish_not_allowed_with_mixed_mode():
+    """A problem carrying an approximation cannot use EIK_MODE_MIXED (refused before any
+    device work)."""
+    lib = eik.load()
+    pb, keep = _problem()
+    pb.u_approx = 0x1000
+    arr = (eik.Problem * 1)(pb)
+    opts = eik._options(mode=eik.EIK_MODE_MIXED)
+    assert lib.eik_solve_batch(1, arr, eik.EIK_F32, 8, None, ctypes.byref(opts)) == eik.EIK_EINVAL
+
+
 def test_batch_argument_checks():
     lib = eik.load()
     good, keep = _problem()

@@ -280,3 +280,65 @@ def test_fp32_mode_batch_and_server(orc, torch_dev):
         got = u.cpu().numpy()
         fin = np.isfinite(want) & (want > 0)
         assert float(np.max(np.abs(got[fin] - want[fin]) / want[fin])) <= bound(p)
+
+
+@pytest.mark.parametrize("delta", [0.02, 0.3])
+def test_batch_with_band_per_grid(orc, torch_dev, delta):
+    """With a band, each grid of a batch takes its band from its own smallest queued value
+    (grids of different sizes and value ranges side by side); results are the oracle's."""
+    import torch
+    from paper_1306_4743_amd import eik
+    ps = mixed_problems()
+    outs = eik.solve_batch(as_dicts(ps, torch_dev), cell=8, delta=delta)
+    assert list(eik.batch_status(len(ps))) == [0] * len(ps)
+    for p, u in zip(ps, outs):
+        compare(u.cpu().numpy(), orc.fmm(p.F, p.h, p.src, p.q), p)
+
+
+def test_batch_polish_and_scratch_together(orc, torch_dev):
+    """A batch where some grids start from an FP32 result (u_approx) and the others from
+    scratch: every result is the oracle's."""
+    import torch
+    from paper_1306_4743_amd import eik
+    ps = mixed_problems()
+    ds = as_dicts(ps, torch_dev)
+    approx = eik.solve_batch(ds, cell=8, mode=eik.EIK_MODE_FP32)
+    assert list(eik.batch_status(len(ps))) == [0] * len(ps)
+    for i, d in enumerate(ds):
+        if i % 2 == 0:
+            d["u_approx"] = approx[i]
+    outs = eik.solve_batch(ds, cell=8)
+    assert list(eik.batch_status(len(ps))) == [0] * len(ps)
+    for p, u in zip(ps, outs):
+        compare(u.cpu().numpy(), orc.fmm(p.F, p.h, p.src, p.q), p)
+
+
+@pytest.mark.parametrize("rounds", [2, 50])
+def test_server_chain_fp32_then_polish(orc, torch_dev, rounds):
+    """Mixed-precision serving: an FP32 server's results go to an FP64 server as u_approx (the
+    same buffer); the polished results are the oracle's to 1e-10 and equal the grid solved
+    alone.  Few problem slots, so admissions happen while others are mid-polish."""
+    import torch
+    from paper_1306_4743_amd import eik
+    ps = mixed_problems()
+    dev_F = [torch.from_numpy(p.F).to(torch_dev) for p in ps]
+    s32 = eik.Server(pool_bytes=64 << 20, max_cells=1 << 14, max_problems=3, cell=8,
+                     mode=eik.EIK_MODE_FP32)
+    done32, _ = run_server(eik, s32, [(i, dict(F=dev_F[i], h=p.h, idx3=p.src, q=p.q))
+                                      for i, p in enumerate(ps)], rounds)
+    s32.close()
+    assert all(done32[i][0] == 0 for i in range(len(ps)))
+    band = 8.0 * 8 * min(p.h for p in ps)
+    s64 = eik.Server(pool_bytes=64 << 20, max_cells=1 << 14, max_problems=3, cell=8, delta=band)
+    queue = [(i, dict(F=dev_F[i], h=p.h, idx3=p.src, q=p.q, u_out=done32[i][1],
+                      u_approx=done32[i][1])) for i, p in enumerate(ps)]
+    done, steps = run_server(eik, s64, queue, rounds)
+    s64.close()
+    for i, p in enumerate(ps):
+        status, u = done[i]
+        assert status == 0
+        got = u.cpu().numpy()
+        compare(got, orc.fmm(p.F, p.h, p.src, p.q), p)
+        alone = eik.solve(dev_F[i], p.h, p.src, p.q, cell=8, tol=0.0).cpu().numpy()
+        compare(got, alone, p)
+    print(f"polish server, rounds/step {rounds}: {steps} steps", flush=True)

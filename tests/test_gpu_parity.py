@@ -404,3 +404,50 @@ def test_eq9_cell_values(orc, torch_dev, band, inner):
     for p in (W.shell_maze(65), W.maze(97, seed=3), W.oscillatory(65, periods=3)):
         check(orc, torch_dev, p, tol=0.0, inner=inner, delta=band * p.cell * p.h,
               cell_value=eik.EIK_CELL_VALUE_EQ9)
+
+
+@pytest.mark.parametrize("inner", INNERS)
+@pytest.mark.parametrize("cell", [8, 4])
+def test_polish_of_fp32_result(orc, torch_dev, cell, inner):
+    """An EIK_MODE_FP32 result given back as u_approx (in the output buffer itself) is
+    polished to the FP64 solution: the oracle's values to 1e-10, exits exact."""
+    from paper_1306_4743_amd import eik
+    import torch
+    for p in (W.maze(97, seed=3), W.oscillatory(65, periods=3)):
+        F = torch.from_numpy(np.ascontiguousarray(p.F)).to(torch_dev)
+        u = eik.solve(F, p.h, p.src, p.q, cell=cell, inner=inner, mode=eik.EIK_MODE_FP32)
+        assert eik.status()[0] == 0
+        u = eik.solve(F, p.h, p.src, p.q, cell=cell, inner=inner, u_out=u, u_approx=u)
+        rc, stats = eik.status()
+        assert rc == 0
+        err = compare(u.cpu().numpy(), orc.fmm(p.F, p.h, p.src, p.q), p)
+        print(f"polish {p.name} cell {cell} inner {inner}: max rel err {err:.2e} {stats}",
+              flush=True)
+
+
+def test_polish_from_upper_bound_with_gaps(orc, torch_dev):
+    """Any upper bound polishes to the solution: 1.5 U + 0.01 with a block of NaN and a block
+    of +inf (both start at +inf), and an explicit band."""
+    from paper_1306_4743_amd import eik
+    import torch
+    p = W.maze(65, seed=8, n_sources=2)
+    want = orc.fmm(p.F, p.h, p.src, p.q)
+    start = np.where(np.isfinite(want), 1.5 * want + 0.01, np.inf)
+    start[10:20, 30:40, 5:25] = np.nan
+    start[40:50, 0:10, 40:64] = np.inf
+    F = torch.from_numpy(np.ascontiguousarray(p.F)).to(torch_dev)
+    ua = torch.from_numpy(start).to(torch_dev)
+    for delta in (0.0, 0.05):
+        u = eik.solve(F, p.h, p.src, p.q, cell=8, delta=delta, u_approx=ua)
+        assert eik.status()[0] == 0
+        compare(u.cpu().numpy(), want, p)
+
+
+def test_polish_ignored_without_exits(torch_dev):
+    from paper_1306_4743_amd import eik
+    import torch
+    F = torch.ones((9, 10, 11), dtype=torch.float32, device=torch_dev)
+    ua = torch.ones((9, 10, 11), dtype=torch.float64, device=torch_dev)
+    u = eik.solve(F, 0.1, np.zeros((0, 3), np.int64), np.zeros(0), cell=8, u_approx=ua)
+    assert eik.status()[0] == 0
+    assert np.all(np.isposinf(u.cpu().numpy()))

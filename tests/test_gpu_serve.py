@@ -40,3 +40,22 @@ def test_served_stream_matches_oracle(orc, cell, rounds):
     assert seq["requests"] == len(reqs)
     print(f"cell {cell}: served p50 {res['p50_ms']:.2f} ms p99 {res['p99_ms']:.2f} ms, "
           f"one-at-a-time p50 {seq['p50_ms']:.2f} p99 {seq['p99_ms']:.2f}", flush=True)
+
+
+def test_mixed_precision_stream_matches_oracle(orc):
+    """The serving harness's FP32 + FP64-polish chain on a small Poisson stream: every result
+    equals the oracle's FMM to 1e-10 with exact exits."""
+    import torch
+    from paper_1306_4743_amd import serve
+    dev = torch.device("cuda:0")
+    reqs = serve.make_requests(16, dev, seed=11, sizes=(17, 33, 49))
+    arrivals = serve.poisson_arrivals(len(reqs), rate=3000.0, seed=4)
+    res = serve.run_server_mixed(reqs, arrivals, cell=8, rounds=4, pool_bytes=24 << 20,
+                                 max_problems=5)
+    assert res["requests"] == len(reqs) and res["p99_ms"] >= res["p50_ms"] > 0
+    for r in reqs:
+        got = r.u.cpu().numpy()
+        want = orc.fmm(r.F.cpu().numpy(), r.h, r.src, r.q)
+        s = r.src
+        assert np.array_equal(got[s[:, 2], s[:, 1], s[:, 0]], r.q)
+        assert _rel(got, want) <= REL_TOL, r
