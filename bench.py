@@ -25,8 +25,10 @@ if ROOT not in sys.path:
 METRIC = "grid-node updates/s and solved nodes/s at 1e-10 rel err; serving p50/p99"
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 FP64_VECTOR_PEAK_TF = 78.6   # MI355X FP64 vector, published
-# LDS: 256 CUs x 128 bytes per clock x 2.4 GHz
-LDS_PEAK_GBS = 256 * 128 * 2.4
+# LDS: 256 CUs x 256 bytes per clock x 2.4 GHz.  128 B per clock per CU is the older CDNA
+# figure; on this chip a plain 16-byte read stream (libeik_probe.so) already exceeds it (about
+# 160 B per clock per CU), consistent with the doubled LDS read path of CDNA4.
+LDS_PEAK_GBS = 256 * 256 * 2.4
 
 
 def lds_bytes_per_update(s_u: int = 8) -> int:
@@ -60,6 +62,58 @@ def measured_traffic(workload_name: str, cell: int):
             return (float(kv["fetch_kib"]) * float(kv["fetch_scale"])
                     + float(kv["write_kib"]) * float(kv["write_scale"])) * 1024.0
     return None
+
+
+def cell_hop_chain(u, src, cell: int) -> int:
+    """Longest chain of cell crossings along the characteristics of the solution u (torch
+    float64 [nz, ny, nx] on the device): each node's parent is its smallest axis neighbour (the
+    first term of its local solve, always upwind), an edge costs 1 where it crosses a cell face,
+    and the chain of a node is the sum along its parents up to an exit (pointer doubling).  A
+    cell can only be final after every cell on such a chain before it, and one round moves
+    information one cell, so the round-synchronous solve needs more rounds than this."""
+    import torch
+    nz, ny, nx = u.shape
+    inf = float("inf")
+    idx = torch.arange(u.numel(), device=u.device, dtype=torch.int64).view(nz, ny, nx)
+    best = torch.full_like(u, inf)
+    parent = idx.clone()
+    cross = torch.zeros(u.shape, dtype=torch.int32, device=u.device)
+    coord = {2: torch.arange(nx, device=u.device).view(1, 1, nx),
+             1: torch.arange(ny, device=u.device).view(1, ny, 1),
+             0: torch.arange(nz, device=u.device).view(nz, 1, 1)}
+    stride = {2: 1, 1: nx, 0: nx * ny}
+    for ax in (0, 1, 2):
+        n = u.shape[ax]
+        for step in (-1, 1):
+            nb = torch.full_like(u, inf)
+            dst = [slice(None)] * 3
+            srcs = [slice(None)] * 3
+            if step < 0:
+                dst[ax], srcs[ax] = slice(1, n), slice(0, n - 1)
+            else:
+                dst[ax], srcs[ax] = slice(0, n - 1), slice(1, n)
+            nb[tuple(dst)] = u[tuple(srcs)]
+            better = nb < best
+            best = torch.where(better, nb, best)
+            parent = torch.where(better, idx + step * stride[ax], parent)
+            c = coord[ax]
+            crosses = (c % cell == 0) if step < 0 else ((c + 1) % cell == 0)
+            cross = torch.where(better, crosses.to(torch.int32).expand_as(cross), cross)
+            del nb, better
+    root = ~(best < u) | ~torch.isfinite(u)  # exits (no smaller neighbour), unreachable nodes
+    if len(src):
+        s = torch.as_tensor(src, device=u.device)
+        root[s[:, 2], s[:, 1], s[:, 0]] = True
+    parent = torch.where(root, idx, parent).view(-1)
+    cross = torch.where(root, torch.zeros_like(cross), cross).view(-1)
+    del best, root, idx
+    for _ in range(40):
+        cross = cross + cross[parent]
+        nxt = parent[parent]
+        if torch.equal(nxt, parent):
+            break
+        parent = nxt
+    return int(cross.max())
 
 
 def workload(name: str):
@@ -243,6 +297,21 @@ def main():
                          "frac": st["updates"] * lds_bytes_per_update() / (kern_ms / 1000.0) / 1e9
                          / LDS_PEAK_GBS, "bytes_per_update": lds_bytes_per_update()},
     }
+    # Latency floor: rounds cannot be fewer than the longest chain of cell crossings, and each
+    # round lasts at least one visit.
+    chain = cell_hop_chain(u, p.src, args.cell)
+    busy = sum(st[k] for k in ("cycles_stage", "cycles_sweep", "cycles_write"))
+    visit_us = kern_ms * 1000.0 * st["workers"] * (busy / max(tot_cyc, 1)) / max(visits, 1)
+    line["latency_floor"] = {
+        "cell_hop_chain": chain, "rounds": st["rounds"], "mean_visit_us": visit_us,
+        "floor_ms": (chain + 1) * visit_us / 1000.0,
+        "frac": (chain + 1) * visit_us / 1000.0 / kern_ms,
+        "visits_per_round_per_worker": visits / max(st["rounds"], 1) / max(st["workers"], 1)}
+    from paper_1306_4743_amd import probes
+    line["device_probes"] = probes.measure(dev)
+    line["roofline"]["frac_of_probe_copy"] = achieved / line["device_probes"]["hbm_copy_gbs"]
+    line["lds_roofline"]["frac_of_probe_read"] = (line["lds_roofline"]["achieved"]
+                                                  / line["device_probes"]["lds_read_gbs"])
     if not args.no_cpu_baseline:
         def gpu_solve(q):
             Fq = torch.from_numpy(q.F).to(dev)
@@ -304,32 +373,39 @@ def precision_leg(args, dev):
 
 def serving_leg(args):
     """The mixed-size request stream (33..257 nodes per side, barrier mazes, 1-4 exits) through
-    the continuous-batching server, against one-at-a-time solves of the same stream."""
+    the continuous-batching servers, against one-at-a-time solves of the same stream."""
     from paper_1306_4743_amd import serve
     r = serve.serve_benchmark(args.serving_requests, rounds=args.serving_rounds, cell=args.cell,
                               log=sys.stderr)
     sat, one = r["saturated"], r["one_at_a_time_saturated"]
+    mix = r["mode_mix"]
     pick = ("p50_ms", "p99_ms", "requests_per_s", "arrival_rate_per_s")
     return {
         "workload": f"{r['requests']} requests, n uniform over {r['sizes']}, barrier mazes seed "
                     f"5000+i, 1-4 exits, FP32 speeds, FP64 values, tol 0, inputs resident",
         "rounds_per_step": r["rounds_per_step"], "pool_bytes": r["pool_bytes"],
-        "saturated_requests_per_s": sat["requests_per_s"],
-        "saturated_solved_nodes_per_s": sat["solved_nodes_per_s"],
-        "saturated_fp32_mode_requests_per_s": r["saturated_fp32_mode"]["requests_per_s"],
-        "mixed_fp32_polish": {
-            "saturated_requests_per_s": r["mixed_fp32_polish_saturated"]["requests_per_s"],
-            "max_rel_diff_served_vs_alone":
-                r["mixed_fp32_polish_saturated"]["max_rel_diff_served_vs_alone"],
-            "poisson": {f: {k: v[k] for k in pick}
-                        for f, v in r["mixed_fp32_polish_poisson"].items()},
+        "mode_mix": {
+            "modes": f"fair coin per request: FP64 or FP32 + FP64 polish "
+                     f"({mix['saturated']['polish_requests']} of {r['requests']} polish)",
+            "saturated_requests_per_s": mix["saturated"]["requests_per_s"],
+            "saturated_solved_nodes_per_s": mix["saturated"]["solved_nodes_per_s"],
+            "max_rel_diff_served_vs_alone": mix["saturated"]["max_rel_diff_served_vs_alone"],
+            "poisson": {f: {k: v[k] for k in pick} for f, v in mix["poisson"].items()},
+            "one_at_a_time_requests_per_s": mix["one_at_a_time_saturated"]["requests_per_s"],
         },
-        "poisson": {f: {k: v[k] for k in pick} for f, v in r["poisson"].items()},
-        "one_at_a_time_requests_per_s": one["requests_per_s"],
-        "one_at_a_time_solved_nodes_per_s": one["solved_nodes_per_s"],
-        "one_at_a_time_poisson": {f: {k: v[k] for k in pick}
-                                  for f, v in r["one_at_a_time_poisson"].items()},
-        "max_rel_diff_served_vs_alone": r["max_rel_diff_served_vs_alone"],
+        "fp64": {
+            "saturated_requests_per_s": sat["requests_per_s"],
+            "saturated_solved_nodes_per_s": sat["solved_nodes_per_s"],
+            "max_rel_diff_served_vs_alone": r["max_rel_diff_served_vs_alone"],
+            "poisson": {f: {k: v[k] for k in pick} for f, v in r["poisson"].items()},
+            "one_at_a_time_requests_per_s": one["requests_per_s"],
+            "one_at_a_time_solved_nodes_per_s": one["solved_nodes_per_s"],
+            "one_at_a_time_poisson": {f: {k: v[k] for k in pick}
+                                      for f, v in r["one_at_a_time_poisson"].items()},
+        },
+        "all_fp32_polish_saturated_requests_per_s":
+            r["mixed_fp32_polish_saturated"]["requests_per_s"],
+        "fp32_mode_saturated_requests_per_s": r["saturated_fp32_mode"]["requests_per_s"],
     }
 
 

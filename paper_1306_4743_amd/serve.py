@@ -13,10 +13,13 @@ Runs:
   * saturated: every request arrives at time 0; gives the server's throughput (requests/s).
   * Poisson arrivals at fractions (0.5, 0.8, 1.0) of that throughput: p50 / p99 latency.
   * saturated in FP32 mode (for context: values about 1e-5 relative, not the FP64 bar).
-  * mixed precision, saturated and at Poisson arrivals: an FP32 server solves each request, a
-    second (FP64) server polishes that result (``eik_problem.u_approx``) to the FP64 solution;
-    a request moves from the first server to the second when it retires there.
-  * one-at-a-time: the same stream, FIFO, each request solved alone with ``eik_solve``.
+  * the mode mix, saturated and at Poisson arrivals: a fair coin (``request_modes``) gives each
+    request FP64 or FP32 + FP64 polish; FP64 requests go to an FP64 server, the others to an
+    FP32 server and then to a second FP64 server that polishes the FP32 result
+    (``eik_problem.u_approx``) to the FP64 solution (``run_stream``); every request at 1e-10.
+  * every request in FP32 + polish, saturated.
+  * one-at-a-time: the same stream, FIFO, each request solved alone with ``eik_solve`` (in FP64,
+    and in its own mode: FP32 + polish = one EIK_MODE_MIXED solve).
 
 Usage: python -m paper_1306_4743_amd.serve [--requests N] [--rounds R] [--json]
 """
@@ -44,6 +47,7 @@ class Request:
     src: np.ndarray
     q: np.ndarray
     u: object       # torch float64 [n, n, n] on the device (the result buffer)
+    polish: bool = False  # mode: FP32 solve + FP64 polish (True) or FP64 (False)
 
     @property
     def nodes(self) -> int:
@@ -65,15 +69,22 @@ def request_shape(i: int, seed: int = 1234, sizes=SIZES):
     return request_shapes(i + 1, seed, sizes)[i]
 
 
+def request_modes(count: int, seed: int = 4321) -> np.ndarray:
+    """Mode of each request of the stream: a fair coin, True = FP32 solve + FP64 polish."""
+    return np.random.default_rng(seed).integers(0, 2, size=count).astype(bool)
+
+
 def make_requests(count: int, device, seed: int = 1234, sizes=SIZES):
-    """The request stream: sizes and exit counts from ``seed``, maze i from seed 5000 + i."""
+    """The request stream: sizes and exit counts from ``seed``, maze i from seed 5000 + i, modes
+    from ``request_modes``."""
     import torch
     from . import workloads as W
     reqs = []
+    modes = request_modes(count)
     for i, (n, ns) in enumerate(request_shapes(count, seed, sizes)):
         F, h, src, q = W.maze_torch(n, 5000 + i, ns, device)
         u = torch.empty(F.shape, dtype=torch.float64, device=device)
-        reqs.append(Request(i, n, 5000 + i, ns, F, h, src, q, u))
+        reqs.append(Request(i, n, 5000 + i, ns, F, h, src, q, u, bool(modes[i])))
     torch.cuda.synchronize(device)
     return reqs
 
@@ -158,73 +169,93 @@ def polish_band(reqs, cell: int) -> float:
     return 32.0 * cell * min(r.h for r in reqs)
 
 
-def run_server_mixed(reqs, arrivals, cell: int = 8, rounds: int = 8,
-                     pool_bytes: int = 16 << 30, max_problems: int = 512, band=None):
-    """Feed ``reqs`` through an FP32 server and then an FP64 polishing server (u_approx = the
-    FP32 result, in the request's own output buffer); both step in turn on one stream.  A
-    request finishes when the polishing server retires it."""
+def run_stream(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int = 16 << 30,
+               max_problems: int = 512, polish=None, band=None):
+    """Feed ``reqs`` to servers by mode: an FP64 request goes to an FP64 server; an FP32 +
+    polish request goes to an FP32 server and, when it retires there, to an FP64 polishing
+    server (``u_approx`` = its FP32 result, in the request's own output buffer; priority band
+    ``band``, default ``polish_band``).  polish: None = each request's own mode, True / False =
+    every request in that mode.  Arrivals are admitted in order; the servers step in turn on
+    one stream.  A request finishes when its last server retires it."""
     import torch
     from . import eik
-    p32, c32 = pool_config(reqs, cell, pool_bytes, eik.EIK_MODE_FP32)
-    p64, c64 = pool_config(reqs, cell, pool_bytes, eik.EIK_MODE_FP64)
-    s32 = eik.Server(p32, c32, max_problems, cell=cell, f_dtype=eik.EIK_F32,
-                     mode=eik.EIK_MODE_FP32)
-    s64 = eik.Server(p64, c64, max_problems, cell=cell, f_dtype=eik.EIK_F32,
-                     delta=polish_band(reqs, cell) if band is None else band)
+    want = [r.polish if polish is None else bool(polish) for r in reqs]
     count = len(reqs)
+
+    def server(subset, mode, delta=0.0):
+        if not subset:
+            return None
+        pb, mc = pool_config(subset, cell, pool_bytes, mode)
+        return eik.Server(pb, mc, max_problems, cell=cell, f_dtype=eik.EIK_F32, mode=mode,
+                          delta=delta)
+
+    pol = [r for r, w in zip(reqs, want) if w]
+    s64 = server([r for r, w in zip(reqs, want) if not w], eik.EIK_MODE_FP64)
+    s32 = server(pol, eik.EIK_MODE_FP32)
+    sp = server(pol, eik.EIK_MODE_FP64, polish_band(reqs, cell) if band is None else band)
+    owner = {id(x): {} for x in (s64, s32, sp) if x is not None}
+    on = {id(x): 0 for x in (s64, s32, sp) if x is not None}
     finish = np.full(count, np.nan)
-    own32, own64 = {}, {}
-    polish_queue = []  # requests whose FP32 result waits for the polishing server
-    nxt, done, on32, on64, steps = 0, 0, 0, 0, 0
+    polish_queue = []
+    nxt, done, steps = 0, 0, 0
+
+    def submit(srv, k, **kw):
+        r = reqs[k]
+        t = srv.submit(r.F, r.h, r.src, r.q, 0.0, r.u, **kw)
+        if t is None:
+            return False
+        owner[id(srv)][t] = k
+        on[id(srv)] += 1
+        return True
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while done < count:
         now = time.perf_counter() - t0
         while nxt < count and arrivals[nxt] <= now:
-            r = reqs[nxt]
-            t = s32.submit(r.F, r.h, r.src, r.q, 0.0, r.u)
-            if t is None:
-                break
-            own32[t] = nxt
+            if not submit(s32 if want[nxt] else s64, nxt):
+                break  # no room now: the head of the queue waits for a retirement
             nxt += 1
-            on32 += 1
-        while polish_queue:
-            r = reqs[polish_queue[0]]
-            t = s64.submit(r.F, r.h, r.src, r.q, 0.0, r.u, u_approx=r.u)
-            if t is None:
-                break
-            own64[t] = polish_queue.pop(0)
-            on64 += 1
-        if on32 == 0 and on64 == 0:
+        while polish_queue and submit(sp, polish_queue[0], u_approx=reqs[polish_queue[0]].u):
+            polish_queue.pop(0)
+        if sum(on.values()) == 0:
             while time.perf_counter() - t0 < arrivals[nxt]:
                 pass
             continue
-        if on32:
-            for t, (status, _) in s32.step(rounds).items():
-                if status != 0:
-                    raise RuntimeError(f"FP32 server: request {own32[t]}: {eik.strerror(status)}")
-                polish_queue.append(own32.pop(t))
-                on32 -= 1
+        for srv in (s32, s64, sp):
+            if srv is None or on[id(srv)] == 0:
+                continue
+            out = srv.step(rounds)
             steps += 1
-        if on64:
-            out = s64.step(rounds)
             tnow = time.perf_counter() - t0
             for t, (status, _) in out.items():
+                k = owner[id(srv)].pop(t)
+                on[id(srv)] -= 1
                 if status != 0:
-                    raise RuntimeError(f"polish server: request {own64[t]}: {eik.strerror(status)}")
-                finish[own64.pop(t)] = tnow
-                done += 1
-                on64 -= 1
-            steps += 1
-    s32.close()
-    s64.close()
+                    raise RuntimeError(f"request {k}: {eik.strerror(status)}")
+                if srv is s32:
+                    polish_queue.append(k)
+                else:
+                    finish[k] = tnow
+                    done += 1
+    for srv in (s64, s32, sp):
+        if srv is not None:
+            srv.close()
     res = _summary(reqs, arrivals, finish, 0.0, float(np.nanmax(finish)))
     res["steps"] = steps
+    res["polish_requests"] = int(sum(want))
     return res
 
 
-def run_sequential(reqs, arrivals, cell: int = 8, **opt):
-    """The same stream, FIFO, one ``eik_solve`` at a time (each waits for the previous)."""
+def run_server_mixed(reqs, arrivals, cell: int = 8, rounds: int = 8,
+                     pool_bytes: int = 16 << 30, max_problems: int = 512, band=None):
+    """Every request in FP32 + polish mode (``run_stream`` with polish=True)."""
+    return run_stream(reqs, arrivals, cell, rounds, pool_bytes, max_problems, True, band)
+
+
+def run_sequential(reqs, arrivals, cell: int = 8, by_mode: bool = False, **opt):
+    """The same stream, FIFO, one ``eik_solve`` at a time (each waits for the previous); with
+    by_mode, each request in its own mode (FP32 + polish = one EIK_MODE_MIXED solve)."""
     import torch
     from . import eik
     count = len(reqs)
@@ -234,7 +265,10 @@ def run_sequential(reqs, arrivals, cell: int = 8, **opt):
     for k, r in enumerate(reqs):
         while time.perf_counter() - t0 < arrivals[k]:
             pass
-        eik.solve(r.F, r.h, r.src, r.q, cell=cell, tol=0.0, u_out=r.u, **opt)
+        kw = dict(opt)
+        if by_mode and r.polish:
+            kw["mode"] = eik.EIK_MODE_MIXED
+        eik.solve(r.F, r.h, r.src, r.q, cell=cell, tol=0.0, u_out=r.u, **kw)
         rc, _ = eik.status()
         if rc != 0:
             raise RuntimeError(f"request {r.i}: {eik.strerror(rc)}")
@@ -277,54 +311,69 @@ def serve_benchmark(count: int = 2000, rounds: int = 8, cell: int = 8,
         if log:
             print(msg, file=log, flush=True)
 
+    def poisson_runs(runner, sat_rate):
+        out = {}
+        for f in fractions:
+            rate = f * sat_rate
+            res = runner(poisson_arrivals(count, rate))
+            res["arrival_rate_per_s"] = rate
+            out[str(f)] = res
+            say(f"serve: {f:.1f}x rate: p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms")
+        return out
+
     t = time.perf_counter()
     reqs = make_requests(count, dev)
     say(f"serve: {count} requests generated in {time.perf_counter() - t:.1f} s")
-    # warm-up: a few requests through a server and alone
+    # warm-up: a few requests through each kind of server and alone
     run_server(reqs[:8], np.zeros(8), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
-    run_sequential(reqs[:4], np.zeros(4), cell=cell)
-    run_server_mixed(reqs[:8], np.zeros(8), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
-    sat = run_server(reqs, np.zeros(count), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
-    say(f"serve: saturated {sat['requests_per_s']:.1f} req/s, {sat['steps']} steps")
-    alone_diff = check_against_alone(reqs, cell=cell)
+    run_stream(reqs[:8], np.zeros(8), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
+    run_sequential(reqs[:4], np.zeros(4), cell=cell, by_mode=True)
     out = {"requests": count, "sizes": list(SIZES), "cell": cell, "rounds_per_step": rounds,
-           "pool_bytes": pool_bytes, "saturated": sat, "max_rel_diff_served_vs_alone": alone_diff,
-           "poisson": {}}
-    for f in fractions:
-        rate = f * sat["requests_per_s"]
-        res = run_server(reqs, poisson_arrivals(count, rate), cell=cell, rounds=rounds,
-                         pool_bytes=pool_bytes)
-        res["arrival_rate_per_s"] = rate
-        out["poisson"][str(f)] = res
-        say(f"serve: {f:.1f}x rate: p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms")
-    # The same stream served in single precision (values ~1e-5 relative, not the FP64 bar).
+           "pool_bytes": pool_bytes}
+    # Every request in FP64.
+    sat = run_server(reqs, np.zeros(count), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
+    say(f"serve: FP64 saturated {sat['requests_per_s']:.1f} req/s, {sat['steps']} steps")
+    out["saturated"] = sat
+    out["max_rel_diff_served_vs_alone"] = check_against_alone(reqs, cell=cell)
+    out["poisson"] = poisson_runs(
+        lambda arr: run_server(reqs, arr, cell=cell, rounds=rounds, pool_bytes=pool_bytes),
+        sat["requests_per_s"])
+    # The same stream in single precision (values ~1e-5 relative, not the FP64 bar).
     sat32 = run_server(reqs, np.zeros(count), cell=cell, rounds=rounds, pool_bytes=pool_bytes,
                        mode=eik.EIK_MODE_FP32)
     out["saturated_fp32_mode"] = sat32
     say(f"serve: saturated, FP32 mode {sat32['requests_per_s']:.1f} req/s")
-    # FP32 bulk + FP64 polish: the FP64 bar at FP32's cost plus the polish.
+    # The mode mix: a fair coin picks FP64 or FP32 + FP64 polish per request (both at 1e-10).
     for r in reqs:
-        r.u.fill_(float("nan"))  # the check below must see the mixed results, not old ones
+        r.u.fill_(float("nan"))  # the checks below must see these results, not earlier ones
+    coin = run_stream(reqs, np.zeros(count), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
+    coin["max_rel_diff_served_vs_alone"] = check_against_alone(reqs, cell=cell)
+    say(f"serve: coin-mix saturated {coin['requests_per_s']:.1f} req/s "
+        f"({coin['polish_requests']} FP32 + polish), max rel diff "
+        f"{coin['max_rel_diff_served_vs_alone']:.1e}")
+    out["mode_mix"] = {"saturated": coin, "poisson": poisson_runs(
+        lambda arr: run_stream(reqs, arr, cell=cell, rounds=rounds, pool_bytes=pool_bytes),
+        coin["requests_per_s"])}
+    # Every request in FP32 + polish.
+    for r in reqs:
+        r.u.fill_(float("nan"))
     mixed = run_server_mixed(reqs, np.zeros(count), cell=cell, rounds=rounds,
                              pool_bytes=pool_bytes)
     mixed["max_rel_diff_served_vs_alone"] = check_against_alone(reqs, cell=cell)
     out["mixed_fp32_polish_saturated"] = mixed
-    say(f"serve: saturated, FP32 + FP64 polish {mixed['requests_per_s']:.1f} req/s, "
-        f"max rel diff {mixed['max_rel_diff_served_vs_alone']:.1e}")
-    rate = seq_fraction * mixed["requests_per_s"]
-    mp = run_server_mixed(reqs, poisson_arrivals(count, rate), cell=cell, rounds=rounds,
-                          pool_bytes=pool_bytes)
-    mp["arrival_rate_per_s"] = rate
-    out["mixed_fp32_polish_poisson"] = {str(seq_fraction): mp}
-    say(f"serve: FP32 + polish at {seq_fraction}x: p50 {mp['p50_ms']:.1f} p99 {mp['p99_ms']:.1f}")
+    say(f"serve: saturated, all FP32 + FP64 polish {mixed['requests_per_s']:.1f} req/s")
+    # One at a time.
     seq_sat = run_sequential(reqs, np.zeros(count), cell=cell)
     out["one_at_a_time_saturated"] = seq_sat
-    say(f"serve: one-at-a-time {seq_sat['requests_per_s']:.1f} req/s")
+    say(f"serve: one-at-a-time FP64 {seq_sat['requests_per_s']:.1f} req/s")
     rate = seq_fraction * sat["requests_per_s"]
     seq = run_sequential(reqs, poisson_arrivals(count, rate), cell=cell)
     seq["arrival_rate_per_s"] = rate
     out["one_at_a_time_poisson"] = {str(seq_fraction): seq}
     say(f"serve: one-at-a-time at {seq_fraction}x: p50 {seq['p50_ms']:.1f} p99 {seq['p99_ms']:.1f}")
+    seq_mix = run_sequential(reqs, np.zeros(count), cell=cell, by_mode=True)
+    out["mode_mix"]["one_at_a_time_saturated"] = seq_mix
+    say(f"serve: one-at-a-time, coin mix {seq_mix['requests_per_s']:.1f} req/s")
     del reqs
     torch.cuda.empty_cache()
     return out

@@ -244,3 +244,23 @@ def test_size_limits():
         eik.query_workspace((1 << 16, 1 << 16, 2), 8, eik.EIK_F32)
     # two nodes per side is the smallest grid
     assert eik.query_workspace((2, 2, 2), 4, eik.EIK_F64) > 0
+
+
+def test_probe_library_exports():
+    """libeik_probe.so (bandwidth probes) exports what include/eik_probe.h declares and rejects
+    invalid arguments before touching a device."""
+    from paper_1306_4743_amd import probes
+    lib = probes.load()
+    hdr = open(os.path.join(ROOT, "include", "eik_probe.h")).read()
+    declared = set(re.findall(r"^int (eikp_\w+)\(", hdr, re.M))
+    assert declared == set(probes.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name)
+    ms, nb = ctypes.c_float(0), ctypes.c_double(0)
+    assert lib.eikp_copy(None, None, 16, 1, None, ctypes.byref(ms)) == -1
+    assert lib.eikp_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1008), 16, 1, None,
+                         ctypes.byref(ms)) == -1  # overlap / misaligned
+    assert lib.eikp_lds(0, 8, 0, 1, ctypes.c_void_p(0x1000), None, ctypes.byref(ms),
+                        ctypes.byref(nb)) == -1
+    assert lib.eikp_lds(1, 8, 2, 1, ctypes.c_void_p(0x1000), None, ctypes.byref(ms),
+                        ctypes.byref(nb)) == -1

@@ -59,3 +59,26 @@ def test_mixed_precision_stream_matches_oracle(orc):
         s = r.src
         assert np.array_equal(got[s[:, 2], s[:, 1], s[:, 0]], r.q)
         assert _rel(got, want) <= REL_TOL, r
+
+
+def test_mode_mix_stream_matches_oracle(orc):
+    """The coin-mixed stream (FP64 requests to an FP64 server, FP32 + polish requests through an
+    FP32 server into a polishing server): every result is the oracle's to 1e-10."""
+    import torch
+    from paper_1306_4743_amd import serve
+    dev = torch.device("cuda:0")
+    reqs = serve.make_requests(20, dev, seed=13, sizes=(17, 33, 49))
+    assert 0 < sum(r.polish for r in reqs) < len(reqs)
+    arrivals = serve.poisson_arrivals(len(reqs), rate=2000.0, seed=5)
+    res = serve.run_stream(reqs, arrivals, cell=8, rounds=3, pool_bytes=24 << 20, max_problems=4)
+    assert res["requests"] == len(reqs) and res["polish_requests"] == sum(r.polish for r in reqs)
+    for r in reqs:
+        got = r.u.cpu().numpy()
+        want = orc.fmm(r.F.cpu().numpy(), r.h, r.src, r.q)
+        s = r.src
+        assert np.array_equal(got[s[:, 2], s[:, 1], s[:, 0]], r.q)
+        assert _rel(got, want) <= REL_TOL, r
+    seq = serve.run_sequential(reqs, arrivals, cell=8, by_mode=True)
+    assert seq["requests"] == len(reqs)
+    for r in reqs:
+        assert _rel(r.u.cpu().numpy(), orc.fmm(r.F.cpu().numpy(), r.h, r.src, r.q)) <= REL_TOL
