@@ -13,7 +13,7 @@
 #ifndef EIK_PROBE_H
 #define EIK_PROBE_H
 
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 #include <stddef.h>
 
 #ifdef __cplusplus

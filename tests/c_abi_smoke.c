@@ -1,0 +1,37 @@
+/* A plain C99 caller of the C ABI: compiled with gcc against include/eik.h and
+ * include/eik_probe.h, linked with libeik.so and libeik_probe.so, and run without a GPU (only
+ * the host-side entry points are called: sizes, argument checks, names). */
+#include <stdio.h>
+#include <string.h>
+
+#include "eik.h"
+#include "eik_probe.h"
+
+static int fails = 0;
+#define CHECK(c) do { if (!(c)) { printf("FAIL %s:%d %s\n", __FILE__, __LINE__, #c); ++fails; } } while (0)
+
+int main(void) {
+    int64_t dims[3] = {65, 65, 65};
+    size_t grid = 0, ws = 0;
+    CHECK(eik_problem_bytes(dims, 8, EIK_F32, EIK_MODE_FP64, &grid) == EIK_OK);
+    CHECK(grid > (size_t)65 * 65 * 65 * (8 + 4));
+    CHECK(eik_query_workspace(dims, 8, EIK_F32, EIK_MODE_FP64, &ws) == EIK_OK && ws > grid);
+    CHECK(eik_problem_bytes(dims, 6, EIK_F32, EIK_MODE_FP64, &grid) == EIK_EINVAL);
+    int64_t bad[3] = {1, 65, 65};
+    CHECK(eik_problem_bytes(bad, 8, EIK_F32, EIK_MODE_FP64, &grid) == EIK_EINVAL);
+    /* invalid arguments are refused before any device work */
+    eik_sources src;
+    memset(&src, 0, sizeof src);
+    CHECK(eik_solve(dims, 0.1, NULL, EIK_F32, &src, NULL, 8, 0.0, NULL) == EIK_EINVAL);
+    eik_problem pb;
+    memset(&pb, 0, sizeof pb);
+    CHECK(eik_solve_batch(0, &pb, EIK_F32, 8, NULL, NULL) == EIK_EINVAL);
+    CHECK(eik_server_create(NULL, 1, 1, 1, 8, EIK_F32, NULL, NULL) == EIK_EINVAL);
+    float ms = 0.0f;
+    CHECK(eikp_copy(NULL, NULL, 16, 1, NULL, &ms) == -1);
+    CHECK(strcmp(eik_strerror(EIK_OK), "EIK_OK") == 0);
+    CHECK(strncmp(eik_version(), "eik-mi355x", 10) == 0);
+    CHECK(sizeof(eik_problem) == 96);
+    printf("%s: %d failures\n", eik_version(), fails);
+    return fails != 0;
+}

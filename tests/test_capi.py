@@ -264,3 +264,25 @@ def test_probe_library_exports():
                         ctypes.byref(nb)) == -1
     assert lib.eikp_lds(1, 8, 2, 1, ctypes.c_void_p(0x1000), None, ctypes.byref(ms),
                         ctypes.byref(nb)) == -1
+
+
+def test_headers_are_a_c_abi(tmp_path):
+    """include/eik.h and include/eik_probe.h compile as C99 (gcc, not a C++ compiler) and a C
+    program links against both libraries and calls their host-side entry points."""
+    import shutil
+    import subprocess
+    from paper_1306_4743_amd import probes
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc is not installed")
+    libdir = os.path.dirname(eik.LIB_PATH)
+    assert os.path.exists(eik.LIB_PATH) and os.path.exists(probes.LIB_PATH)
+    exe = tmp_path / "c_abi_smoke"
+    cmd = [gcc, "-std=c99", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           f"-I{os.path.join(ROOT, 'include')}", "-I/opt/rocm/include",
+           os.path.join(ROOT, "tests", "c_abi_smoke.c"), f"-L{libdir}", "-leik", "-leik_probe",
+           f"-Wl,-rpath,{libdir}", "-o", str(exe)]
+    subprocess.run(cmd, check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "0 failures" in out.stdout
