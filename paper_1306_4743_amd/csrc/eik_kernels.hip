@@ -174,17 +174,16 @@ __device__ __forceinline__ uint64_t ld_relaxed_u64(const uint64_t* p) {
 
 // ------------------------------------------------------------------------------------------
 // Square root of d >= 0 for the local solve: hardware reciprocal square root refined by one
-// Goldschmidt step and two Newton corrections (the standard refinement, without the rescaling
-// for subnormal or huge arguments that the discriminants here never need).  Within one ulp.
+// Goldschmidt step (which squares its relative error to ~2^-50) and one Newton correction
+// (without the rescaling for subnormal or huge arguments that the discriminants here never
+// need).  Within about one ulp.
 __device__ __forceinline__ double disc_sqrt(double d) {
     const double r = __builtin_amdgcn_rsq(d);
     double g = d * r, hh = 0.5 * r;
     const double e = fma(-hh, g, 0.5);
     g = fma(g, e, g);
     hh = fma(hh, e, hh);
-    double res = fma(-g, g, d);
-    g = fma(res, hh, g);
-    res = fma(-g, g, d);
+    const double res = fma(-g, g, d);
     g = fma(res, hh, g);
     return d > 0.0 ? g : 0.0;
 }
@@ -239,9 +238,10 @@ __device__ __forceinline__ double local_solve(double m0, double m1, double m2, d
     const double ss = s * s;
     const double u1 = a + s;
     const double dab = b - a, dca = c - a, dcb = c - b;
-    const bool two = fma(dca, dca, dcb * dcb) >= ss;
+    const double qc = fma(dca, dca, dcb * dcb);  // the terms c adds to the three-term sum
+    const bool two = qc >= ss;
     const double d2 = fma(-dab, dab, 2.0 * ss);
-    const double d3 = fma(-dca, dca, fma(-dcb, dcb, fma(-dab, dab, 3.0 * ss)));
+    const double d3 = (d2 + ss) - qc;
     const double sum = two ? a + b : (a + b) + c;
     const double u = (sum + disc_sqrt(two ? d2 : d3)) * (two ? 0.5 : (1.0 / 3.0));
     return u1 <= b ? u1 : u;
@@ -376,11 +376,13 @@ __device__ __forceinline__ bool is_active(float v) { return __float_as_int(v) < 
 
 // Marks the LDS node p active given its (non-negative) value v: only the word that holds the
 // sign bit is written.  Lanes that mark the same node in one step write the same word.
-__device__ __forceinline__ void mark_active(double* p, double v) {
-    reinterpret_cast<uint32_t*>(p)[1] = (uint32_t)(__double_as_longlong(v) >> 32) | 0x80000000u;
+__device__ __forceinline__ void mark_active(double* p, double) {
+    __hip_atomic_fetch_or(reinterpret_cast<uint32_t*>(p) + 1, 0x80000000u, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void mark_active(float* p, float v) {
-    *reinterpret_cast<uint32_t*>(p) = __float_as_uint(v) | 0x80000000u;
+__device__ __forceinline__ void mark_active(float* p, float) {
+    __hip_atomic_fetch_or(reinterpret_cast<uint32_t*>(p), 0x80000000u, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // ------------------------------------------------------------------------------------------
