@@ -201,7 +201,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
-              "(independent solves shard across GPUs with no exchange; see DESIGN.md)",
+              "(independent solves shard across GPUs, one process and one server per GPU, with no exchange)",
               file=sys.stderr)
         sys.exit(2)
 
