@@ -1343,12 +1343,43 @@ __global__ void k_queue_all(SolveParams P, Slot S, int64_t round) {
     const int waves = (int)(gridDim.x * blockDim.x) >> 6;
     const double* u = reinterpret_cast<const double*>(S.u);
     const float* u32 = reinterpret_cast<const float*>(S.u);
-    for (int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); c < S.ncell; c += waves) {
-        double m = __builtin_inf();
-        for (int l = lane; l < R3; l += 64)  // fmin ignores the NaN of padding nodes
-            m = fmin(m, S.fp32 ? fabs((double)u32[(size_t)c * R3 + l]) : fabs(u[(size_t)c * R3 + l]));
-        m = wave_min(m);
-        if (lane == 0) tag_cell(P, round, S.cell_base + c, FL_ALL, m);
+    RoundCtl* ctl = &P.ctl[round & 3];
+    const int par = (int)(round & 1);
+    // A wave takes 64 cells at a time: lane j ends up holding the smallest value of cell j, and
+    // the 64 cells join the list with one counter atomic.
+    for (int c0 = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; c0 < S.ncell;
+         c0 += waves * 64) {
+        const int cnt = min(64, S.ncell - c0);
+        double mine = __builtin_inf();
+        for (int j = 0; j < cnt; ++j) {
+            const size_t o = (size_t)(c0 + j) * R3;
+            double m = __builtin_inf();
+            for (int l = lane; l < R3; l += 64)  // fmin ignores the NaN of padding nodes
+                m = fmin(m, S.fp32 ? fabs((double)u32[o + l]) : fabs(u[o + l]));
+            m = wave_min(m);
+            if (lane == j) mine = m;
+        }
+        const bool valid = lane < cnt;
+        const int nb = S.cell_base + c0 + lane;
+        bool newq = false;
+        if (valid) {
+            mine = kept_value(P, nb, mine);
+            atomicMin((unsigned long long*)&P.key[par][nb], (unsigned long long)dbits(mine));
+            const uint32_t old = atomicOr(&P.flags[par][nb], FL_ALL | FL_QUEUED);
+            newq = !(old & FL_QUEUED);
+        }
+        const uint64_t mask = __ballot(newq);
+        uint32_t base = 0;
+        if (lane == 0 && mask) base = atomicAdd(&ctl->count, (uint32_t)__popcll(mask));
+        base = __shfl(base, 0, 64);
+        if (newq) P.list[par][base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = nb;
+        const double wm = wave_min(valid ? mine : __builtin_inf());
+        if (lane == 0 && wm < __builtin_inf()) {
+            atomicMin((unsigned long long*)&ctl->minkey, (unsigned long long)dbits(wm));
+            if (P.slot_band)
+                atomicMin((unsigned long long*)&slot_minkeys(P, round)[P.cell_slot[S.cell_base + c0]],
+                          (unsigned long long)dbits(wm));
+        }
     }
 }
 
@@ -1558,7 +1589,7 @@ hipError_t launch_lift(const Slot& S32, const Slot& S64, int cell, double factor
 
 hipError_t launch_queue_all(const SolveParams& P, const Slot& S, int cell, int64_t round,
                             hipStream_t s) {
-    const int blocks = blocks_for((size_t)S.ncell * 64, 256);
+    const int blocks = blocks_for(((size_t)S.ncell + 63) / 64 * 64, 256);
     if (cell == 8)
         hipLaunchKernelGGL((k_queue_all<8>), dim3(blocks), dim3(256), 0, s, P, S, round);
     else

@@ -1,6 +1,6 @@
 """Summarise a rocprofv3 results database (rocpd SQLite) as short text.
 
-Usage: python -m paper_1306_4743_amd.rocpd_summary <results.db> [--pmc]
+Usage: python -m paper_1306_4743_amd.rocpd_summary <results.db> [--pmc] [--match TEXT ...]
 
 Prints per-kernel call counts and durations (total, average, min, max) and, with --pmc, the
 average of every collected counter per dispatch of each kernel.  Only the standard library is
@@ -13,10 +13,12 @@ import sqlite3
 import statistics
 
 
-def kernel_table(con):
+def kernel_table(con, match=None):
     rows = con.execute("select name, duration from kernels").fetchall()
     by = {}
     for name, dur in rows:
+        if match and not any(m in name for m in match):
+            continue
         by.setdefault(name, []).append(float(dur))
     out = []
     for name, ds in sorted(by.items(), key=lambda kv: -sum(kv[1])):
@@ -49,11 +51,13 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db")
     ap.add_argument("--pmc", action="store_true")
+    ap.add_argument("--match", action="append",
+                    help="only kernels whose name contains this text (repeatable)")
     a = ap.parse_args()
     con = sqlite3.connect(a.db)
     print("| kernel | calls | total ms | avg ms | min ms | max ms |")
     print("|---|---|---|---|---|---|")
-    for name, n, tot, avg, mn, mx in kernel_table(con):
+    for name, n, tot, avg, mn, mx in kernel_table(con, a.match):
         print(f"| `{name}` | {n} | {tot:.3f} | {avg:.3f} | {mn:.3f} | {mx:.3f} |")
     if a.pmc:
         print()
