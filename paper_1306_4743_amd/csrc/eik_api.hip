@@ -984,7 +984,8 @@ int eik_server_step(eik_server* s, int64_t rounds, int* finished) {
     P.round_log_len = 0;
     rc = ordered_solve(s->device, P, s->cell, s->f_dtype, st, s->opt.workers);
     if (rc != EIK_OK) return rc;
-    // 3. Per problem: cells still queued, status; the round where the launch stopped.
+    // 3. Per problem: whether a cell is still queued, status; the round where the launch
+    //    stopped.
     int* counts_dev = (int*)(base + s->layout.off_counts);
     e = eik::launch_slot_counts(P, counts_dev, ns, st);
     if (e != hipSuccess) return hip_fail(e);

@@ -117,7 +117,8 @@ hipError_t launch_queue_all(const SolveParams& P, const Slot& S, int cell, int64
                             hipStream_t s);
 // Round lists emptied and the round counter reset (launch status and counters kept).
 hipError_t launch_reset_rounds(const SolveParams& P, hipStream_t s);
-// Cells of each slot queued for the first round of the next launch (P.next_round).
+// counts[slot] <- 1 if the slot has a cell queued for the first round of the next launch
+// (P.next_round), else 0.
 hipError_t launch_slot_counts(const SolveParams& P, int* counts, int nslots, hipStream_t s);
 
 }  // namespace eik

@@ -1395,8 +1395,8 @@ __global__ void k_reset_rounds(SolveParams P) {
     for (int g = g0; g < 4 * P.nslots; g += stride) P.slot_minkey[g] = dbits(__builtin_inf());
 }
 
-// Cells of each slot in the list of the next launch's first round (the host's test for
-// finished grids).
+// Whether each slot has a cell in the list of the next launch's first round (the host's test
+// for finished grids): 1 if so, else 0.  Every writer stores the same 1, so plain stores do.
 __global__ void k_slot_counts_zero(int* counts, int nslots) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g < nslots) counts[g] = 0;
@@ -1406,7 +1406,7 @@ __global__ void k_slot_counts(SolveParams P, int* counts) {
     const uint32_t n = P.ctl[round & 3].count;
     const int32_t* lst = P.list[round & 1];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        atomicAdd(&counts[P.cell_slot[lst[i]]], 1);
+        counts[P.cell_slot[lst[i]]] = 1;
 }
 
 // ------------------------------------------------------------------------------------------
