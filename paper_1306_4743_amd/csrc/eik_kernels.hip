@@ -528,22 +528,40 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     const UT hh = (UT)S.h;
     const FT* __restrict__ fg = reinterpret_cast<const FT*>(S.f) + (size_t)lc * R3;
 
-    // Stage in: cell values and s = h/F.
-    for (int l = lane; l < R3; l += 64) {
-        const int x = l % R, y = (l / R) % R, z = l / R2;
-        L.U[box_index<R>(x, y, z)] = ug[l];
-        const FT fv = fg[l];
-        L.S[l] = fv > FT(0) ? hh / (UT)fv : (fv < FT(0) ? UT(-1) : UT(0));
+    // Stage in: cell values, s = h/F and the halo (the neighbours' opposite face copies, +inf
+    // beyond the grid).  Every load is issued before any is used, so the visit waits for one
+    // memory round trip instead of one per load.
+    static_assert(R3 % 64 == 0, "whole 64-lane passes over the cell");
+    constexpr int PER = R3 / 64;
+    UT uv[PER];
+    FT fv[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        uv[k] = ug[lane + 64 * k];
+        fv[k] = fg[lane + 64 * k];
     }
-    // Halo: the neighbour's opposite face copy, +inf beyond the grid.
+    UT hv[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int nb = cell_neighbour(S, lc, cc, f);
+        // Beyond the grid the cell's own face is read (an address inside the array) and ignored.
+        const size_t src = ((size_t)(nb >= 0 ? nb : lc) * 6 + (f ^ 1)) * R2 + lane;
+        hv[f] = lane < R2 ? faces[src] : INF;
+        if (nb < 0) hv[f] = INF;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int l = lane + 64 * k;
+        const int x = l % R, y = (l / R) % R, z = l / R2;
+        L.U[box_index<R>(x, y, z)] = uv[k];
+        L.S[l] = fv[k] > FT(0) ? hh / (UT)fv[k] : (fv[k] < FT(0) ? UT(-1) : UT(0));
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
         if (lane < R2) {
             int x, y, z;
             face_node<R>(f, lane % R, lane / R, x, y, z);
-            const UT v = nb >= 0 ? faces[((size_t)nb * 6 + (f ^ 1)) * R2 + lane] : INF;
-            L.U[box_index<R>(x, y, z) + face_step<R>(f)] = v;
+            L.U[box_index<R>(x, y, z) + face_step<R>(f)] = hv[f];
         }
     }
     wave_sync();
