@@ -508,7 +508,7 @@ __device__ __forceinline__ int face_step(int f) {
 }
 
 template <int R, typename FT, int INNER, typename UT>
-__device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t fl,
+__device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot, uint32_t fl,
                                            double popped_key, WaveLds<R, INNER, UT>& L,
                                            const PlaneRegs<R>& pr, int lane,
                                            RoundCtl* ctl_next, int nxt, VisitCounters& cnt,
@@ -517,9 +517,10 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, uint32_t
     constexpr int BOFF = 1 + B + B * B;
     const UT INF = (UT)__builtin_inf();
     const unsigned long long t0 = cycles();
-    // The cell's grid (slot) and its local index there; c itself is a global cell id.
+    // The cell's grid (slot, looked up by the pop) and its local index there; c itself is a
+    // global cell id.
     c = __builtin_amdgcn_readfirstlane(c);
-    const int slot = P.cell_slot[c];
+    slot = __builtin_amdgcn_readfirstlane(slot);
     const Slot S = P.slots[slot];
     const int lc = c - S.cell_base;
     const CellXYZ cc = cell_coords(S, lc);
@@ -1073,7 +1074,7 @@ k_solve(SolveParams P) {
             if (n - base < (uint32_t)nwaves_total * 2u) chunk_now = 1u;
             // Lanes j < cnt_here take cell j of the chunk: its flags and value are exchanged
             // for empty ones (the removal of Algorithm 2 with V^c <- +inf).
-            int my_c = 0;
+            int my_c = 0, my_slot = 0;
             uint32_t my_fl = 0;
             unsigned long long my_kb = 0;
             if ((uint32_t)lane < cnt_here) {
@@ -1083,6 +1084,7 @@ k_solve(SolveParams P) {
                     idx = (uint32_t)(((uint64_t)idx * 2654435761ull + (mix >> 17)) % n);
                 }
                 my_c = P.list[cur][idx];
+                my_slot = P.cell_slot[my_c];  // issued beside the exchanges, read by the visit
                 my_fl = atomicExch(&P.flags[cur][my_c], 0u);
                 my_kb = P.delta > 0.0
                             ? atomicExch((unsigned long long*)&P.key[cur][my_c],
@@ -1093,7 +1095,7 @@ k_solve(SolveParams P) {
             // straight back to the next round's list.
             double my_thr = thr;
             if (slot_band && (uint32_t)lane < cnt_here)
-                my_thr = bitsd(ld_relaxed_u64(&smk_cur[P.cell_slot[my_c]])) + P.delta;
+                my_thr = bitsd(ld_relaxed_u64(&smk_cur[my_slot])) + P.delta;
             const bool defer = (uint32_t)lane < cnt_here && !(bitsd(my_kb) < my_thr);
             const uint64_t defer_mask = __ballot(defer);
             deferred += __popcll(defer_mask);
@@ -1102,12 +1104,14 @@ k_solve(SolveParams P) {
             cyc_pop += cycles() - tp0;
             for (uint32_t j = 0; j < cnt_here; ++j) {
                 const int c = __shfl(my_c, (int)j, 64);
+                const int cs = __shfl(my_slot, (int)j, 64);
                 const uint32_t fl = __shfl(my_fl, (int)j, 64);
                 const double key = bitsd(__shfl(my_kb, (int)j, 64));
                 if ((defer_mask >> j) & 1ull) continue;
                 ++visits;
                 const unsigned long long sw0 = cnt.sweeps, tv0 = cycles();
-                visit_cell<R, FT, INNER, UT>(P, c, fl, key, L, pr, lane, ctl_next, nxt, cnt, wq);
+                visit_cell<R, FT, INNER, UT>(P, c, cs, fl, key, L, pr, lane, ctl_next, nxt, cnt,
+                                             wq);
                 if (lane == 0) {
                     const unsigned long long dsw = cnt.sweeps - sw0, dt = cycles() - tv0;
                     atomicAdd(&s_hist[dsw < 31 ? dsw : 31], 1u);
