@@ -69,8 +69,9 @@ def cell_hop_chain(u, src, cell: int) -> int:
     float64 [nz, ny, nx] on the device): each node's parent is its smallest axis neighbour (the
     first term of its local solve, always upwind), an edge costs 1 where it crosses a cell face,
     and the chain of a node is the sum along its parents up to an exit (pointer doubling).  A
-    cell can only be final after every cell on such a chain before it, and one round moves
-    information one cell, so the round-synchronous solve needs more rounds than this."""
+    cell can only be final after every cell on such a chain before it, and a round moves
+    information about one cell (a face published early in a round can be read later in the same
+    round, so sometimes further), so the solve needs about this many rounds."""
     import torch
     nz, ny, nx = u.shape
     inf = float("inf")
