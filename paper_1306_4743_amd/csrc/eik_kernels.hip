@@ -1358,6 +1358,8 @@ __global__ void k_lift(Slot S32, Slot S64, double factor) {
 // Every cell of a slot joins the list of round `round` with all nodes active and, as its cell
 // value, the smallest of its (lifted) values, so that a priority band polishes the cells in the
 // order of their values.  One wave per cell.
+constexpr int kQueueGroup = 16;  // cells per wave and per list-counter atomic
+
 template <int R>
 __global__ void k_queue_all(SolveParams P, Slot S, int64_t round) {
     constexpr int R3 = R * R * R;
@@ -1367,11 +1369,11 @@ __global__ void k_queue_all(SolveParams P, Slot S, int64_t round) {
     const float* u32 = reinterpret_cast<const float*>(S.u);
     RoundCtl* ctl = &P.ctl[round & 3];
     const int par = (int)(round & 1);
-    // A wave takes 64 cells at a time: lane j ends up holding the smallest value of cell j, and
-    // the 64 cells join the list with one counter atomic.
-    for (int c0 = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; c0 < S.ncell;
-         c0 += waves * 64) {
-        const int cnt = min(64, S.ncell - c0);
+    // A wave takes kQueueGroup cells at a time: lane j ends up holding the smallest value of
+    // cell j, and the group joins the list with one counter atomic.
+    for (int c0 = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * kQueueGroup;
+         c0 < S.ncell; c0 += waves * kQueueGroup) {
+        const int cnt = min(kQueueGroup, S.ncell - c0);
         double mine = __builtin_inf();
         for (int j = 0; j < cnt; ++j) {
             const size_t o = (size_t)(c0 + j) * R3;
@@ -1611,7 +1613,7 @@ hipError_t launch_lift(const Slot& S32, const Slot& S64, int cell, double factor
 
 hipError_t launch_queue_all(const SolveParams& P, const Slot& S, int cell, int64_t round,
                             hipStream_t s) {
-    const int blocks = blocks_for(((size_t)S.ncell + 63) / 64 * 64, 256);
+    const int blocks = blocks_for(((size_t)S.ncell + kQueueGroup - 1) / kQueueGroup * 64, 256);
     if (cell == 8)
         hipLaunchKernelGGL((k_queue_all<8>), dim3(blocks), dim3(256), 0, s, P, S, round);
     else
