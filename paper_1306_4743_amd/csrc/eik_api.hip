@@ -215,9 +215,6 @@ Slot fp32_twin(const Slot& S64, const GridSize& g) {
 // solution: 2^-12, about twenty times the largest relative FP32 error measured on the grids
 // here (1.3e-5).
 constexpr double kLiftFactor = 1.0 + 1.0 / 4096.0;
-// Band width of the polish in cell crossings (r h): measured best of {0.5, 2, 8, 32} over the
-// maze, oscillatory, shell-maze and bumps workloads.
-constexpr double kPolishBand = 8.0;
 
 // Pinned staging of host-side data (sources, slot tables); one buffer, reused after its last
 // copy finished.
@@ -471,21 +468,16 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
         ev = &w->ring[4 * (w->timed % Workspace::kRing)];
         w->timed++;
     }
-    // Mixed precision runs the method twice: in FP32 on the twins, then lifted and polished in
-    // FP64 (every cell queued with all nodes active, exits re-seeded with their exact values).
-    // A given approximation is polished the same way; both polishes take the cells in the order
-    // of their values, a band of polish_band cell crossings (r h, smallest h of the batch) at a
-    // time, unless a band was given.
-    if ((mixed || polish) && !(opt.delta > 0.0)) {
-        double hmin = pbs[0].h;
-        for (int i = 1; i < n; ++i) hmin = std::min(hmin, pbs[i].h);
-        P.delta = kPolishBand * cell * hmin;
-    }
+    // Mixed precision runs the method twice: in FP32 on the twins, then in FP64 from the FP32
+    // result lifted above the FP64 solution, with the exits re-seeded at their exact values.  A
+    // given approximation is polished the same way.  Nothing else is queued: the exact exit
+    // values decrease the cells around them, whose changed faces tag their downwind neighbours,
+    // so the polish reaches every cell whose boundary changes, in the order of a solve from
+    // +inf, and visits no other.
     SolveParams P1 = P;
     const Slot* first = slots.data();
     if (mixed) {
         P1.fp32 = 1;
-        P1.delta = opt.delta;  // the FP32 phase uses the band asked for (none by default)
         P1.slots = P.slots + n;
         first = slots.data() + n;
     }
@@ -499,8 +491,6 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
         e = eik::launch_seed(P1, first[i], cell, f_dtype, 0, pbs[i].sources.n, refs[i].idx3,
                              refs[i].q, stream);
         if (e != hipSuccess) return hip_fail(e);
-        if (u0 && (e = eik::launch_queue_all(P1, first[i], cell, 0, stream)) != hipSuccess)
-            return hip_fail(e);
     }
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return hip_fail(e);
     if (nsrc_total > 0) {
@@ -514,8 +504,7 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
                 if ((e = eik::launch_lift(first[i], slots[i], cell, kLiftFactor, stream)) !=
                         hipSuccess ||
                     (e = eik::launch_seed(P, slots[i], cell, f_dtype, 0, pbs[i].sources.n,
-                                          refs[i].idx3, refs[i].q, stream)) != hipSuccess ||
-                    (e = eik::launch_queue_all(P, slots[i], cell, 0, stream)) != hipSuccess)
+                                          refs[i].idx3, refs[i].q, stream)) != hipSuccess)
                     return hip_fail(e);
             }
             P.round_begin = 0;
@@ -969,9 +958,6 @@ int eik_server_step(eik_server* s, int64_t rounds, int* finished) {
             e = eik::launch_seed(s->P, p.slot, s->cell, s->f_dtype, s->next_round,
                                  p.pb.sources.n, refs[k].idx3, refs[k].q, st);
             if (e != hipSuccess) return hip_fail(e);
-            if (u0 && (e = eik::launch_queue_all(s->P, p.slot, s->cell, s->next_round, st)) !=
-                          hipSuccess)
-                return hip_fail(e);
             p.started = true;
         }
         s->fresh.clear();

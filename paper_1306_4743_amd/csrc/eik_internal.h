@@ -111,10 +111,6 @@ hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipS
 hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s);
 // Mixed precision: FP64 values (and faces) of S64 <- FP32 ones of S32 times factor.
 hipError_t launch_lift(const Slot& S32, const Slot& S64, int cell, double factor, hipStream_t s);
-// Every cell of slot S (FP64 values) queued for round `round` with all nodes active and the
-// smallest of its values as cell value.
-hipError_t launch_queue_all(const SolveParams& P, const Slot& S, int cell, int64_t round,
-                            hipStream_t s);
 // Round lists emptied and the round counter reset (launch status and counters kept).
 hipError_t launch_reset_rounds(const SolveParams& P, hipStream_t s);
 // counts[slot] <- 1 if the slot has a cell queued for the first round of the next launch

@@ -1355,58 +1355,6 @@ __global__ void k_lift(Slot S32, Slot S64, double factor) {
     for (size_t g = g0; g < nf; g += stride) f64[g] = (double)f32[g] * factor;
 }
 
-// Every cell of a slot joins the list of round `round` with all nodes active and, as its cell
-// value, the smallest of its (lifted) values, so that a priority band polishes the cells in the
-// order of their values.  One wave per cell.
-constexpr int kQueueGroup = 16;  // cells per wave and per list-counter atomic
-
-template <int R>
-__global__ void k_queue_all(SolveParams P, Slot S, int64_t round) {
-    constexpr int R3 = R * R * R;
-    const int lane = threadIdx.x & 63;
-    const int waves = (int)(gridDim.x * blockDim.x) >> 6;
-    const double* u = reinterpret_cast<const double*>(S.u);
-    const float* u32 = reinterpret_cast<const float*>(S.u);
-    RoundCtl* ctl = &P.ctl[round & 3];
-    const int par = (int)(round & 1);
-    // A wave takes kQueueGroup cells at a time: lane j ends up holding the smallest value of
-    // cell j, and the group joins the list with one counter atomic.
-    for (int c0 = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * kQueueGroup;
-         c0 < S.ncell; c0 += waves * kQueueGroup) {
-        const int cnt = min(kQueueGroup, S.ncell - c0);
-        double mine = __builtin_inf();
-        for (int j = 0; j < cnt; ++j) {
-            const size_t o = (size_t)(c0 + j) * R3;
-            double m = __builtin_inf();
-            for (int l = lane; l < R3; l += 64)  // fmin ignores the NaN of padding nodes
-                m = fmin(m, S.fp32 ? fabs((double)u32[o + l]) : fabs(u[o + l]));
-            m = wave_min(m);
-            if (lane == j) mine = m;
-        }
-        const bool valid = lane < cnt;
-        const int nb = S.cell_base + c0 + lane;
-        bool newq = false;
-        if (valid) {
-            mine = kept_value(P, nb, mine);
-            atomicMin((unsigned long long*)&P.key[par][nb], (unsigned long long)dbits(mine));
-            const uint32_t old = atomicOr(&P.flags[par][nb], FL_ALL | FL_QUEUED);
-            newq = !(old & FL_QUEUED);
-        }
-        const uint64_t mask = __ballot(newq);
-        uint32_t base = 0;
-        if (lane == 0 && mask) base = atomicAdd(&ctl->count, (uint32_t)__popcll(mask));
-        base = __shfl(base, 0, 64);
-        if (newq) P.list[par][base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = nb;
-        const double wm = wave_min(valid ? mine : __builtin_inf());
-        if (lane == 0 && wm < __builtin_inf()) {
-            atomicMin((unsigned long long*)&ctl->minkey, (unsigned long long)dbits(wm));
-            if (P.slot_band)
-                atomicMin((unsigned long long*)&slot_minkeys(P, round)[P.cell_slot[S.cell_base + c0]],
-                          (unsigned long long)dbits(wm));
-        }
-    }
-}
-
 // Empty round lists and round counter 0 for a following launch (status and counters kept).
 __global__ void k_reset_rounds(SolveParams P) {
     const int g0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
@@ -1611,15 +1559,6 @@ hipError_t launch_lift(const Slot& S32, const Slot& S64, int cell, double factor
     return hipGetLastError();
 }
 
-hipError_t launch_queue_all(const SolveParams& P, const Slot& S, int cell, int64_t round,
-                            hipStream_t s) {
-    const int blocks = blocks_for(((size_t)S.ncell + kQueueGroup - 1) / kQueueGroup * 64, 256);
-    if (cell == 8)
-        hipLaunchKernelGGL((k_queue_all<8>), dim3(blocks), dim3(256), 0, s, P, S, round);
-    else
-        hipLaunchKernelGGL((k_queue_all<4>), dim3(blocks), dim3(256), 0, s, P, S, round);
-    return hipGetLastError();
-}
 
 hipError_t launch_reset_rounds(const SolveParams& P, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_rounds, dim3(blocks_for((size_t)4 * P.nslots + 64, 256)),

@@ -163,38 +163,30 @@ def run_server(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int =
     return res
 
 
-def polish_band(reqs, cell: int) -> float:
-    """Priority band of the polishing server: 32 cell crossings at the finest grid step (on the
-    mixed-size maze stream the fastest of 8, 32, 128 and 512 crossings or no band)."""
-    return 32.0 * cell * min(r.h for r in reqs)
-
-
 def run_stream(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int = 16 << 30,
-               max_problems: int = 512, polish=None, band=None):
-    """Feed ``reqs`` to servers by mode: an FP64 request goes to an FP64 server; an FP32 +
-    polish request goes to an FP32 server and, when it retires there, to an FP64 polishing
-    server (``u_approx`` = its FP32 result, in the request's own output buffer; priority band
-    ``band``, default ``polish_band``).  polish: None = each request's own mode, True / False =
-    every request in that mode.  Arrivals are admitted in order; the servers step in turn on
-    one stream.  A request finishes when its last server retires it."""
+               max_problems: int = 512, polish=None):
+    """Feed ``reqs`` to servers by mode: an FP64 request goes to the FP64 server; an FP32 +
+    polish request goes to an FP32 server and, when it retires there, to the same FP64 server
+    with ``u_approx`` = its FP32 result (in the request's own output buffer), which polishes it.
+    polish: None = each request's own mode, True / False = every request in that mode.
+    Arrivals are admitted in order; the two servers step in turn on one stream.  A request
+    finishes when the FP64 server retires it."""
     import torch
     from . import eik
     want = [r.polish if polish is None else bool(polish) for r in reqs]
     count = len(reqs)
 
-    def server(subset, mode, delta=0.0):
+    def server(subset, mode):
         if not subset:
             return None
         pb, mc = pool_config(subset, cell, pool_bytes, mode)
-        return eik.Server(pb, mc, max_problems, cell=cell, f_dtype=eik.EIK_F32, mode=mode,
-                          delta=delta)
+        return eik.Server(pb, mc, max_problems, cell=cell, f_dtype=eik.EIK_F32, mode=mode)
 
     pol = [r for r, w in zip(reqs, want) if w]
-    s64 = server([r for r, w in zip(reqs, want) if not w], eik.EIK_MODE_FP64)
+    s64 = server(reqs, eik.EIK_MODE_FP64)  # FP64 requests and the polish of the others
     s32 = server(pol, eik.EIK_MODE_FP32)
-    sp = server(pol, eik.EIK_MODE_FP64, polish_band(reqs, cell) if band is None else band)
-    owner = {id(x): {} for x in (s64, s32, sp) if x is not None}
-    on = {id(x): 0 for x in (s64, s32, sp) if x is not None}
+    owner = {id(x): {} for x in (s64, s32) if x is not None}
+    on = {id(x): 0 for x in (s64, s32) if x is not None}
     finish = np.full(count, np.nan)
     polish_queue = []
     nxt, done, steps = 0, 0, 0
@@ -216,13 +208,13 @@ def run_stream(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int =
             if not submit(s32 if want[nxt] else s64, nxt):
                 break  # no room now: the head of the queue waits for a retirement
             nxt += 1
-        while polish_queue and submit(sp, polish_queue[0], u_approx=reqs[polish_queue[0]].u):
+        while polish_queue and submit(s64, polish_queue[0], u_approx=reqs[polish_queue[0]].u):
             polish_queue.pop(0)
         if sum(on.values()) == 0:
             while time.perf_counter() - t0 < arrivals[nxt]:
                 pass
             continue
-        for srv in (s32, s64, sp):
+        for srv in (s32, s64):
             if srv is None or on[id(srv)] == 0:
                 continue
             out = srv.step(rounds)
@@ -238,7 +230,7 @@ def run_stream(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int =
                 else:
                     finish[k] = tnow
                     done += 1
-    for srv in (s64, s32, sp):
+    for srv in (s64, s32):
         if srv is not None:
             srv.close()
     res = _summary(reqs, arrivals, finish, 0.0, float(np.nanmax(finish)))
@@ -248,9 +240,9 @@ def run_stream(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int =
 
 
 def run_server_mixed(reqs, arrivals, cell: int = 8, rounds: int = 8,
-                     pool_bytes: int = 16 << 30, max_problems: int = 512, band=None):
+                     pool_bytes: int = 16 << 30, max_problems: int = 512):
     """Every request in FP32 + polish mode (``run_stream`` with polish=True)."""
-    return run_stream(reqs, arrivals, cell, rounds, pool_bytes, max_problems, True, band)
+    return run_stream(reqs, arrivals, cell, rounds, pool_bytes, max_problems, True)
 
 
 def run_sequential(reqs, arrivals, cell: int = 8, by_mode: bool = False, **opt):

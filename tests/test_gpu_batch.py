@@ -313,8 +313,9 @@ def test_batch_polish_and_scratch_together(orc, torch_dev):
         compare(u.cpu().numpy(), orc.fmm(p.F, p.h, p.src, p.q), p)
 
 
+@pytest.mark.parametrize("banded", [False, True])
 @pytest.mark.parametrize("rounds", [2, 50])
-def test_server_chain_fp32_then_polish(orc, torch_dev, rounds):
+def test_server_chain_fp32_then_polish(orc, torch_dev, rounds, banded):
     """Mixed-precision serving: an FP32 server's results go to an FP64 server as u_approx (the
     same buffer); the polished results are the oracle's to 1e-10 and equal the grid solved
     alone.  Few problem slots, so admissions happen while others are mid-polish."""
@@ -328,7 +329,7 @@ def test_server_chain_fp32_then_polish(orc, torch_dev, rounds):
                                       for i, p in enumerate(ps)], rounds)
     s32.close()
     assert all(done32[i][0] == 0 for i in range(len(ps)))
-    band = 8.0 * 8 * min(p.h for p in ps)
+    band = 8.0 * 8 * min(p.h for p in ps) if banded else 0.0
     s64 = eik.Server(pool_bytes=64 << 20, max_cells=1 << 14, max_problems=3, cell=8, delta=band)
     queue = [(i, dict(F=dev_F[i], h=p.h, idx3=p.src, q=p.q, u_out=done32[i][1],
                       u_approx=done32[i][1])) for i, p in enumerate(ps)]
