@@ -119,7 +119,7 @@ def pool_config(reqs, cell: int, pool_bytes: int, mode: int = 0):
     return pool_bytes, pool_bytes // per_cell + 1
 
 
-def run_server(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int = 16 << 30,
+def run_server(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int = 32 << 30,
                max_problems: int = 512, **opt):
     """Feed ``reqs`` (arriving at ``arrivals`` seconds) to one server; returns the summary."""
     import torch
@@ -163,7 +163,7 @@ def run_server(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int =
     return res
 
 
-def run_stream(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int = 16 << 30,
+def run_stream(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int = 32 << 30,
                max_problems: int = 512, polish=None):
     """Feed ``reqs`` to servers by mode: an FP64 request goes to the FP64 server; an FP32 +
     polish request goes to an FP32 server and, when it retires there, to the same FP64 server
@@ -240,7 +240,7 @@ def run_stream(reqs, arrivals, cell: int = 8, rounds: int = 8, pool_bytes: int =
 
 
 def run_server_mixed(reqs, arrivals, cell: int = 8, rounds: int = 8,
-                     pool_bytes: int = 16 << 30, max_problems: int = 512):
+                     pool_bytes: int = 32 << 30, max_problems: int = 512):
     """Every request in FP32 + polish mode (``run_stream`` with polish=True)."""
     return run_stream(reqs, arrivals, cell, rounds, pool_bytes, max_problems, True)
 
@@ -292,7 +292,7 @@ def check_against_alone(reqs, sample: int = 10, cell: int = 8):
 
 def serve_benchmark(count: int = 2000, rounds: int = 8, cell: int = 8,
                     fractions=(0.5, 0.8, 1.0), seq_fraction: float = 0.8,
-                    pool_bytes: int = 16 << 30, log=None):
+                    pool_bytes: int = 32 << 30, log=None):
     """The whole serving measurement; returns a JSON-able dict."""
     import torch
     from . import eik
@@ -377,7 +377,7 @@ def main():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rounds", type=int, default=8, help="worklist rounds per server step")
     ap.add_argument("--cell", type=int, default=8)
-    ap.add_argument("--pool-gib", type=float, default=16.0)
+    ap.add_argument("--pool-gib", type=float, default=32.0)
     a = ap.parse_args()
     res = serve_benchmark(a.requests, a.rounds, a.cell, pool_bytes=int(a.pool_gib * (1 << 30)),
                           log=sys.stderr)
