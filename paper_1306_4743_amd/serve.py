@@ -14,8 +14,8 @@ Runs:
   * Poisson arrivals at fractions (0.5, 0.8, 1.0) of that throughput: p50 / p99 latency.
   * saturated in FP32 mode (for context: values about 1e-5 relative, not the FP64 bar).
   * the mode mix, saturated and at Poisson arrivals: a fair coin (``request_modes``) gives each
-    request FP64 or FP32 + FP64 polish; FP64 requests go to an FP64 server, the others to an
-    FP32 server and then to a second FP64 server that polishes the FP32 result
+    request FP64 or FP32 + FP64 polish; FP64 requests go to the FP64 server, the others to an
+    FP32 server and then to the same FP64 server, which polishes the FP32 result
     (``eik_problem.u_approx``) to the FP64 solution (``run_stream``); every request at 1e-10.
   * every request in FP32 + polish, saturated.
   * one-at-a-time: the same stream, FIFO, each request solved alone with ``eik_solve`` (in FP64,
