@@ -62,7 +62,8 @@ extern "C" {
  * 1e-7 on the grids here), not the FP64 bar; exit values are rounded to FP32. */
 #define EIK_MODE_FP32 1
 /* FP32 bulk, FP64 polish: the method runs in EIK_MODE_FP32, its result is lifted above the FP64
- * solution (times 1 + 2^-12), the exits are re-seeded at their exact values, and the FP64
+ * solution (times 1 + max(2^-12, n 2^-20), n the longest side), the exits are re-seeded at
+ * their exact values, and the FP64
  * method runs from there: the exits' cells decrease first and every changed face tags the cell
  * downwind of it, so only cells whose boundary changes are swept.  Values only decrease, so it
  * ends at the FP64 solution: same accuracy as EIK_MODE_FP64.  The polish costs about as much as
@@ -230,12 +231,13 @@ int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
  *
  * u_approx (device, nx*ny*nz doubles in the layout of u_out, or NULL): a solution of eq. (2)
  * that is accurate to about single precision, e.g. the u_out of an EIK_MODE_FP32 solve of the
- * same problem.  The solver then starts from |u_approx| * (1 + 2^-12) instead of +inf (NaN and
- * +inf entries start at +inf) and sets the exits to their exact values, as the second phase of
- * EIK_MODE_MIXED does; the corrections spread from the exits, and only cells whose boundary
- * changes are swept.  Values only decrease from their start, so the result is the FP64 solution
- * (to the usual 1e-10 relative accuracy) wherever the scaled start is not below it: that holds
- * when u_approx is an upper bound or at most 2^-12 relative below the solution.  u_approx is
+ * same problem.  The solver then starts from |u_approx| * (1 + m), m = max(2^-12, n 2^-20)
+ * with n the longest side, instead of +inf (NaN and +inf entries start at +inf) and sets the
+ * exits to their exact values, as the second phase of EIK_MODE_MIXED does; the corrections
+ * spread from the exits, and only cells whose boundary changes are swept.  Values only
+ * decrease from their start, so the result is the FP64 solution (to the usual 1e-10 relative
+ * accuracy) wherever the scaled start is not below it: that holds when u_approx is an upper
+ * bound or at most about m relative below the solution.  u_approx is
  * read when the problem starts (in the batch call or at the server step that admits it) and may
  * be the same buffer as u_out.  Ignored for problems without exits (their solution is +inf).
  * Not allowed with EIK_MODE_MIXED (EIK_EINVAL).

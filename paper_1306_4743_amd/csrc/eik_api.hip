@@ -211,10 +211,15 @@ Slot fp32_twin(const Slot& S64, const GridSize& g) {
     return S;
 }
 
-// Relative margin of the lift from the FP32 result to an FP64 starting point above the
-// solution: 2^-12, about twenty times the largest relative FP32 error measured on the grids
-// here (1.3e-5).
-constexpr double kLiftFactor = 1.0 + 1.0 / 4096.0;
+// Factor that lifts an FP32-accurate result of a problem above its FP64 solution: 1 + the larger
+// of 2^-12 (about twenty times the largest relative FP32 error measured on the grids here,
+// 1.3e-5) and n 2^-20 with n the longest side (four times the bound 4 n 2^-24 that the FP32
+// error is tested against: rounding at each local solve, accumulated along a characteristic of
+// at most a few n nodes).  Any larger factor polishes to the same solution.
+double lift_factor(const int64_t dims[3]) {
+    const double n = (double)std::max(dims[0], std::max(dims[1], dims[2]));
+    return 1.0 + std::max(1.0 / 4096.0, n / 1048576.0);
+}
 
 // Pinned staging of host-side data (sources, slot tables); one buffer, reused after its last
 // copy finished.
@@ -485,8 +490,8 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
     if ((e = eik::launch_init_global(P, stream)) != hipSuccess) return hip_fail(e);
     for (int i = 0; i < n; ++i) {
         const double* u0 = start_values(pbs[i]);
-        e = eik::launch_init_slot(P1, first[i], i, cell, f_dtype, pbs[i].F, u0, kLiftFactor,
-                                  stream);
+        e = eik::launch_init_slot(P1, first[i], i, cell, f_dtype, pbs[i].F, u0,
+                                  lift_factor(pbs[i].dims), stream);
         if (e != hipSuccess) return hip_fail(e);
         e = eik::launch_seed(P1, first[i], cell, f_dtype, 0, pbs[i].sources.n, refs[i].idx3,
                              refs[i].q, stream);
@@ -501,7 +506,8 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
         if (mixed) {
             if ((e = eik::launch_reset_rounds(P, stream)) != hipSuccess) return hip_fail(e);
             for (int i = 0; i < n; ++i) {
-                if ((e = eik::launch_lift(first[i], slots[i], cell, kLiftFactor, stream)) !=
+                if ((e = eik::launch_lift(first[i], slots[i], cell, lift_factor(pbs[i].dims),
+                                          stream)) !=
                         hipSuccess ||
                     (e = eik::launch_seed(P, slots[i], cell, f_dtype, 0, pbs[i].sources.n,
                                           refs[i].idx3, refs[i].q, stream)) != hipSuccess)
@@ -953,7 +959,7 @@ int eik_server_step(eik_server* s, int64_t rounds, int* finished) {
             eik_server::Problem& p = s->problems[s->fresh[k]];
             const double* u0 = start_values(p.pb);
             e = eik::launch_init_slot(s->P, p.slot, s->fresh[k], s->cell, s->f_dtype, p.pb.F, u0,
-                                      kLiftFactor, st);
+                                      lift_factor(p.pb.dims), st);
             if (e != hipSuccess) return hip_fail(e);
             e = eik::launch_seed(s->P, p.slot, s->cell, s->f_dtype, s->next_round,
                                  p.pb.sources.n, refs[k].idx3, refs[k].q, st);
