@@ -23,6 +23,10 @@
  *   streams All GPU work of a call is enqueued on `stream` (NULL = the default stream) and the
  *           call returns once it is enqueued.  Calls on different streams may run concurrently;
  *           each stream has its own workspace.  Calls on one stream are ordered by the stream.
+ *   process The solve kernel is a cooperative launch, which the HIP runtime grants to one
+ *           process per device at a time: while one process has launched it on a GPU, solves
+ *           from another process on that GPU fail with EIK_EHIP.  Serve many callers of one GPU
+ *           from one process (streams, batches, a server).
  *   errors  A negative return value is a synchronous error: nothing was enqueued and u_out is
  *           untouched.  Conditions found on the device (invalid speeds, a cap on rounds) are
  *           recorded in the stream's workspace and returned by eik_stream_status(); u_out then
@@ -87,7 +91,10 @@ extern "C" {
  *                    listed nodes in dense 64-lane chunks and a node that decreases lists its
  *                    larger neighbours (Algorithm 3 activation without an ordering of nodes);
  *   EIK_INNER_DUAL   the locking sweeps run as two streams on the cell at once, half a sweep
- *                    apart, with directions that never put one node in both streams' planes. */
+ *                    apart, with directions that never put one node in both streams' planes;
+ *                    cells of 4 and 8 only (EIK_EINVAL at 16).
+ * At r = 16 a plane holds up to 192 nodes and is swept in up to three 64-node steps; a worker's
+ * cell takes 78 KiB of LDS in FP64 (39 KiB in FP32), so a CU holds two (four) such workers. */
 #define EIK_INNER_SWEEP 1
 #define EIK_INNER_LIST 2
 #define EIK_INNER_DUAL 3
@@ -122,7 +129,7 @@ typedef struct eik_options {
                              < round_log_len, [2t] = cells in the round's list and [2t+1] =
                              shader-clock cycle count when the round ended (analysis)       */
     int64_t round_log_len;
-    int inner;            /* in-cell solver: 0 = default (EIK_INNER_SWEEP at cell 8,
+    int inner;            /* in-cell solver: 0 = default (EIK_INNER_SWEEP at cell 8 and 16,
                              EIK_INNER_LIST at cell 4), or one of EIK_INNER_*                */
     int cell_value;       /* EIK_CELL_VALUE_EQ5 (default) or EIK_CELL_VALUE_EQ9; only the
                              priority band (delta) reads cell values                        */
@@ -159,7 +166,7 @@ typedef struct eik_stats {
  *   sources  exit nodes and values (see eik_sources).
  *   u_out    device array of nx*ny*nz doubles; receives U (+inf where no exit node is reachable,
  *            q at exit nodes).  May not alias F.
- *   cell     cell side r in nodes: 4 or 8.  Cells are anchored at node 0; the last layer of
+ *   cell     cell side r in nodes: 4, 8 or 16.  Cells are anchored at node 0; the last layer of
  *            cells along an axis is partial when r does not divide the node count.
  *   tol      kappa >= 0, the early-termination threshold of the "early sweep termination"
  *            subsection: sweeping inside a cell stops after a sweep whose largest decrease is
@@ -199,7 +206,7 @@ int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_
 
 /* One configuration tried by eik_autotune and its time. */
 typedef struct eik_tune_entry {
-    int cell;             /* r: 4 or 8                                                        */
+    int cell;             /* r: 4, 8 or 16                                                    */
     int inner;            /* EIK_INNER_SWEEP, EIK_INNER_LIST or EIK_INNER_DUAL                 */
     int workers;          /* persistent workgroups (0 = one per CU)                            */
     double delta;         /* priority band width (0 = every queued cell each round)            */
@@ -212,8 +219,8 @@ typedef struct eik_tune_entry {
  * eik_autotune -- time the solver's configurations on one problem and return the fastest.
  * The best cell size, in-cell solver, worker count and priority band depend on the problem
  * (Section 6 finds the best cell size problem-dependent), so they are measured, not guessed:
- * every combination of r in {8, 4}, inner in {SWEEP, LIST, DUAL} and workers in {all, half the
- * CUs} with no band, then the best of those with bands of 4, 16 and 64 cell
+ * every combination of r in {8, 4, 16}, inner in {SWEEP, LIST, DUAL} (DUAL up to r = 8) and
+ * workers in {all, half the CUs} with no band, then the best of those with bands of 4, 16 and 64 cell
  * crossings (delta = 4 r h, 16 r h, 64 r h).  Each configuration is solved once to warm up and `reps` (1..100)
  * times timed; the problem's arguments are those of eik_solve_ex (u_out receives the result of
  * the last run; every configuration computes the same U up to rounding).  Blocks until done.

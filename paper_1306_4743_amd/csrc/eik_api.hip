@@ -33,6 +33,9 @@ int hip_fail(hipError_t e) {
     return EIK_EHIP;
 }
 
+// Cell sides with kernels: 4, 8 and 16.
+bool valid_cell(int cell) { return cell == 4 || cell == 8 || cell == 16; }
+
 bool valid_dims(const int64_t* dims) {
     if (!dims) return false;
     for (int a = 0; a < 3; ++a)
@@ -135,8 +138,10 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
         return EIK_EINVAL;
     std::memset(P, 0, sizeof(*P));
     P->max_rounds = opt->max_rounds > 0 ? opt->max_rounds : (int64_t(1) << 20);
-    // default in-cell solver: sweeps at r = 8, the list relaxation at r = 4 (measured fastest)
-    const int inner = opt->inner ? opt->inner : (cell == 8 ? EIK_INNER_SWEEP : EIK_INNER_LIST);
+    // default in-cell solver: sweeps at r = 8 and 16, the list relaxation at r = 4 (measured
+    // fastest); two sweep streams need both planes in one wave, which r = 16 does not allow
+    const int inner = opt->inner ? opt->inner : (cell == 4 ? EIK_INNER_LIST : EIK_INNER_SWEEP);
+    if (inner == EIK_INNER_DUAL && cell == 16) return EIK_EINVAL;
     // default sweep cap: 8 directional sweeps (one Gray cycle) per visit for the sweeps -- a
     // longer visit publishes what it has and resumes next round, which keeps rounds short --
     // and effectively none for the others (their passes are short)
@@ -410,7 +415,7 @@ int ensure_device(void** p, size_t* have, size_t need, hipStream_t stream) {
 int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipStream_t stream,
                      const eik_options* options) {
     if (n < 1 || n > (1 << 20) || !pbs) return EIK_EINVAL;
-    if (cell != 4 && cell != 8) return EIK_EINVAL;
+    if (!valid_cell(cell)) return EIK_EINVAL;
     eik_options opt;
     SolveParams P;
     int rc = parse_options(options, cell, &opt, &P);
@@ -620,7 +625,7 @@ const char* eik_strerror(int code) {
 const char* eik_version(void) { return "eik-mi355x 0.2 (gfx950)"; }
 
 int eik_problem_bytes(const int64_t dims[3], int cell, int f_dtype, int mode, size_t* bytes) {
-    if (!bytes || !valid_dims(dims) || (cell != 4 && cell != 8) ||
+    if (!bytes || !valid_dims(dims) || !valid_cell(cell) ||
         (f_dtype != EIK_F32 && f_dtype != EIK_F64) ||
         (mode != EIK_MODE_FP64 && mode != EIK_MODE_FP32 && mode != EIK_MODE_MIXED))
         return EIK_EINVAL;
@@ -671,7 +676,7 @@ int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
                  int reps, eik_tune_entry* table, int cap, int* n_out, eik_tune_entry* best) {
     if (!best || reps < 1 || reps > 100 || cap < 0 || (cap > 0 && !table)) return EIK_EINVAL;
     int rc = EIK_OK;
-    // Synchronous validation of the problem once (cell 8 and 4 accept the same problems).
+    // Synchronous validation of the problem once (every cell size accepts the same problems).
     {
         eik_problem pb;
         std::memset(&pb, 0, sizeof(pb));
@@ -692,11 +697,12 @@ int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
     for (auto& x : ev)
         if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(e);
     std::vector<eik_tune_entry> cand;
-    const int cells[2] = {8, 4};
+    const int cells[3] = {8, 4, 16};
     const int inners[3] = {EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL};
     for (int cell : cells)
         for (int inner : inners)
             for (int workers : {0, ncu / 2}) {
+                if (inner == EIK_INNER_DUAL && cell == 16) continue;
                 eik_tune_entry t;
                 std::memset(&t, 0, sizeof(t));
                 t.cell = cell;
@@ -864,7 +870,7 @@ void eik_release(void) {
 int eik_server_create(eik_server** out, size_t pool_bytes, int64_t max_cells, int max_problems,
                       int cell, int f_dtype, hipStream_t stream, const eik_options* options) {
     if (!out || pool_bytes == 0 || max_cells < 1 || max_cells >= (int64_t(1) << 31) ||
-        max_problems < 1 || max_problems > (1 << 16) || (cell != 4 && cell != 8) ||
+        max_problems < 1 || max_problems > (1 << 16) || !valid_cell(cell) ||
         (f_dtype != EIK_F32 && f_dtype != EIK_F64))
         return EIK_EINVAL;
     eik_server* s = new eik_server();

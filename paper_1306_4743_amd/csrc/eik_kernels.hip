@@ -44,31 +44,50 @@ namespace eik {
 // Constant tables.
 
 // Nodes of a cell of side R grouped by diagonal plane p = x + y + z (canonical direction +++),
-// packed as x | y << 5 | z << 10; 0xFFFF marks an unused (plane, lane) slot.  Planes with more
-// than 64 nodes (R > 8) are spread over several 64-lane passes: slot = (p * passes + pass) * 64.
+// packed as x | y << 5 | z << 10; 0xFFFF marks an unused (step, lane) slot.  A sweep takes the
+// planes in order, 64 nodes per wave step: one step per plane up to r = 8 (at most 48 nodes), and
+// a plane of more than 64 nodes (r = 16: up to 192) over consecutive steps.  Nodes of one plane
+// are not neighbours of each other, so splitting a plane over steps keeps the plane order.
+constexpr int plane_nodes(int R, int p) {
+    int n = 0;
+    for (int z = 0; z < R; ++z)
+        for (int y = 0; y < R; ++y)
+            if (p - y - z >= 0 && p - y - z < R) ++n;
+    return n;
+}
+constexpr int plane_steps(int R) {
+    int s = 0;
+    for (int p = 0; p < 3 * R - 2; ++p) s += (plane_nodes(R, p) + 63) / 64;
+    return s;
+}
+
 template <int R>
 struct PlaneTable {
     static constexpr int NP = 3 * R - 2;
-    static constexpr int MAXP = (R <= 4) ? 12 : (R <= 8 ? 48 : 192);
-    static constexpr int PASSES = (MAXP + 63) / 64;
-    uint16_t slot[NP * PASSES * 64];
+    static constexpr int NSTEP = plane_steps(R);
+    uint16_t slot[NSTEP * 64];
     constexpr PlaneTable() : slot() {
-        for (int i = 0; i < NP * PASSES * 64; ++i) slot[i] = 0xFFFF;
+        for (int i = 0; i < NSTEP * 64; ++i) slot[i] = 0xFFFF;
+        int step = 0;
         for (int p = 0; p < NP; ++p) {
             int n = 0;
             for (int z = 0; z < R; ++z)
                 for (int y = 0; y < R; ++y) {
                     int x = p - y - z;
                     if (x < 0 || x >= R) continue;
-                    slot[p * PASSES * 64 + n] = (uint16_t)(x | (y << 5) | (z << 10));
+                    slot[(step + n / 64) * 64 + n % 64] = (uint16_t)(x | (y << 5) | (z << 10));
                     ++n;
                 }
+            step += (n + 63) / 64;
         }
     }
 };
+static_assert(PlaneTable<4>::NSTEP == 10 && PlaneTable<8>::NSTEP == 22 &&
+                  PlaneTable<16>::NSTEP == 88, "one step per plane up to r = 8");
 
 __constant__ PlaneTable<4> kPlanes4 = PlaneTable<4>();
 __constant__ PlaneTable<8> kPlanes8 = PlaneTable<8>();
+__constant__ PlaneTable<16> kPlanes16 = PlaneTable<16>();
 
 // Two sweep streams on one cell, offset by half a sweep: at step t, lanes [0, n_t) take the
 // nodes of plane t of stream 0 and the next lanes take plane (t + H) mod NP of stream 1
@@ -112,6 +131,8 @@ template <>
 __device__ __forceinline__ const uint16_t* plane_slots<4>() { return kPlanes4.slot; }
 template <>
 __device__ __forceinline__ const uint16_t* plane_slots<8>() { return kPlanes8.slot; }
+template <>
+__device__ __forceinline__ const uint16_t* plane_slots<16>() { return kPlanes16.slot; }
 
 // Gray-code order of the 8 sweep directions; bit a of a direction set = descending along axis a.
 __constant__ int kGray[8] = {0, 1, 3, 2, 6, 7, 5, 4};
@@ -335,20 +356,24 @@ __device__ __forceinline__ int box_index(int x, int y, int z) {
     return (x + 1) + B * ((y + 1) + B * (z + 1));
 }
 
-// Per-lane node coordinates of every diagonal plane, packed two planes per register, plus a
-// bit mask of the planes in which the lane has a node.  Loaded once per kernel.
-template <int R>
+// Per-lane node coordinates of every sweep step (a diagonal plane, or 64 nodes of one), packed
+// two steps per register, plus a bit mask of the steps in which the lane has a node.  Loaded
+// once per kernel.
+template <int R, int INNER>
 struct PlaneRegs {
-    static constexpr int NP = 3 * R - 2;
-    uint32_t pk[(NP + 1) / 2];
-    uint32_t valid;
+    static constexpr int NS = INNER == INNER_DUAL ? 3 * R - 2 : PlaneTable<R>::NSTEP;
+    uint32_t pk[(NS + 1) / 2];
+    uint32_t valid[(NS + 31) / 32];
     int dummy;  // this lane's scratch slot: a box node on a halo edge, never read
+    __device__ __forceinline__ bool has(int p) const { return (valid[p >> 5] >> (p & 31)) & 1u; }
 };
 
 template <int R, int INNER>
-__device__ __forceinline__ void load_plane_regs(PlaneRegs<R>& pr, int lane) {
-    static_assert(PlaneTable<R>::PASSES == 1, "one 64-lane pass per plane");
-    const uint16_t* slots = INNER == INNER_DUAL ? dual_slots<R>() : plane_slots<R>();
+__device__ __forceinline__ void load_plane_regs(PlaneRegs<R, INNER>& pr, int lane) {
+    static_assert(INNER != INNER_DUAL || R <= 8, "two sweep streams fit one wave up to r = 8");
+    const uint16_t* slots;
+    if constexpr (INNER == INNER_DUAL) slots = dual_slots<R>();
+    else slots = plane_slots<R>();
     // Halo edges: lines where two coordinates are -1 or R (12 R nodes); lane -> one of them.
     {
         const int e = lane % (12 * R), edge = e / R, t = e % R;
@@ -359,12 +384,13 @@ __device__ __forceinline__ void load_plane_regs(PlaneRegs<R>& pr, int lane) {
         const int z = kind == 0 ? t : v;
         pr.dummy = box_index<R>(x, y, z);
     }
-    pr.valid = 0;
 #pragma unroll
-    for (int p = 0; p < PlaneRegs<R>::NP; ++p) {
+    for (int w = 0; w < (PlaneRegs<R, INNER>::NS + 31) / 32; ++w) pr.valid[w] = 0;
+#pragma unroll
+    for (int p = 0; p < PlaneRegs<R, INNER>::NS; ++p) {
         const uint32_t raw = slots[p * 64 + lane];
         const bool ok = raw != 0xFFFFu;
-        if (ok) pr.valid |= 1u << p;
+        if (ok) pr.valid[p >> 5] |= 1u << (p & 31);
         const uint32_t e = ok ? raw : 0u;
         if (p & 1) pr.pk[p >> 1] |= e << 16;
         else pr.pk[p >> 1] = e;
@@ -510,10 +536,13 @@ __device__ __forceinline__ int face_step(int f) {
 template <int R, typename FT, int INNER, typename UT>
 __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot, uint32_t fl,
                                            double popped_key, WaveLds<R, INNER, UT>& L,
-                                           const PlaneRegs<R>& pr, int lane,
+                                           const PlaneRegs<R, INNER>& pr, int lane,
                                            RoundCtl* ctl_next, int nxt, VisitCounters& cnt,
                                            WaveQueue& wq) {
     constexpr int R2 = R * R, R3 = R * R * R, B = R + 2, NP = 3 * R - 2;
+    constexpr int NS = PlaneRegs<R, INNER>::NS;
+    // face nodes per lane: one up to r = 8, four at r = 16
+    constexpr int FPL = (R2 + 63) / 64;
     constexpr int BOFF = 1 + B + B * B;
     const UT INF = (UT)__builtin_inf();
     const unsigned long long t0 = cycles();
@@ -531,38 +560,53 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
 
     // Stage in: cell values, s = h/F and the halo (the neighbours' opposite face copies, +inf
     // beyond the grid).  Every load is issued before any is used, so the visit waits for one
-    // memory round trip instead of one per load.
+    // memory round trip instead of one per load (up to r = 8; at r = 16, one per 16 nodes a
+    // lane, so that the values in flight fit the registers).
     static_assert(R3 % 64 == 0, "whole 64-lane passes over the cell");
     constexpr int PER = R3 / 64;
-    UT uv[PER];
-    FT fv[PER];
+    constexpr int CH = PER < 16 ? PER : 16;
+    UT hv[6][FPL];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        uv[k] = ug[lane + 64 * k];
-        fv[k] = fg[lane + 64 * k];
+    for (int k0 = 0; k0 < PER; k0 += CH) {
+        UT uv[CH];
+        FT fv[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            uv[k] = ug[lane + 64 * (k0 + k)];
+            fv[k] = fg[lane + 64 * (k0 + k)];
+        }
+        if (k0 == 0) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                const int nb = cell_neighbour(S, lc, cc, f);
+                // Beyond the grid the cell's own face is read (an address inside the array) and
+                // ignored.
+                const size_t src = ((size_t)(nb >= 0 ? nb : lc) * 6 + (f ^ 1)) * R2 + lane;
+#pragma unroll
+                for (int j = 0; j < FPL; ++j) {
+                    hv[f][j] = lane + 64 * j < R2 ? faces[src + 64 * j] : INF;
+                    if (nb < 0) hv[f][j] = INF;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int l = lane + 64 * (k0 + k);
+            const int x = l % R, y = (l / R) % R, z = l / R2;
+            L.U[box_index<R>(x, y, z)] = uv[k];
+            L.S[l] = fv[k] > FT(0) ? hh / (UT)fv[k] : (fv[k] < FT(0) ? UT(-1) : UT(0));
+        }
     }
-    UT hv[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        const int nb = cell_neighbour(S, lc, cc, f);
-        // Beyond the grid the cell's own face is read (an address inside the array) and ignored.
-        const size_t src = ((size_t)(nb >= 0 ? nb : lc) * 6 + (f ^ 1)) * R2 + lane;
-        hv[f] = lane < R2 ? faces[src] : INF;
-        if (nb < 0) hv[f] = INF;
-    }
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int l = lane + 64 * k;
-        const int x = l % R, y = (l / R) % R, z = l / R2;
-        L.U[box_index<R>(x, y, z)] = uv[k];
-        L.S[l] = fv[k] > FT(0) ? hh / (UT)fv[k] : (fv[k] < FT(0) ? UT(-1) : UT(0));
-    }
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        if (lane < R2) {
-            int x, y, z;
-            face_node<R>(f, lane % R, lane / R, x, y, z);
-            L.U[box_index<R>(x, y, z) + face_step<R>(f)] = hv[f];
+        for (int j = 0; j < FPL; ++j) {
+            const int e = lane + 64 * j;
+            if (e < R2) {
+                int x, y, z;
+                face_node<R>(f, e % R, e / R, x, y, z);
+                L.U[box_index<R>(x, y, z) + face_step<R>(f)] = hv[f][j];
+            }
         }
     }
     wave_sync();
@@ -570,14 +614,18 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
     // published face copies; a border node below them has decreased), then the initial active
     // set: every node on a first visit, otherwise the layer next to each face that received new
     // inflow (plus, after a capped visit, the active flags it stored).
-    UT before[6];
+    UT before[6][FPL];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        before[f] = INF;
-        if (lane < R2) {
-            int x, y, z;
-            face_node<R>(f, lane % R, lane / R, x, y, z);
-            before[f] = fabs(L.U[box_index<R>(x, y, z)]);
+#pragma unroll
+        for (int j = 0; j < FPL; ++j) {
+            const int e = lane + 64 * j;
+            before[f][j] = INF;
+            if (e < R2) {
+                int x, y, z;
+                face_node<R>(f, e % R, e / R, x, y, z);
+                before[f][j] = fabs(L.U[box_index<R>(x, y, z)]);
+            }
         }
     }
     wave_sync();
@@ -598,10 +646,14 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
     } else {
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            if ((fl & (1u << f)) && lane < R2) {
-                int x, y, z;
-                face_node<R>(f, lane % R, lane / R, x, y, z);
-                if (L.S[x + R * (y + R * z)] > UT(0)) activate(box_index<R>(x, y, z));
+#pragma unroll
+            for (int j = 0; j < FPL; ++j) {
+                const int e = lane + 64 * j;
+                if ((fl & (1u << f)) && e < R2) {
+                    int x, y, z;
+                    face_node<R>(f, e % R, e / R, x, y, z);
+                    if (L.S[x + R * (y + R * z)] > UT(0)) activate(box_index<R>(x, y, z));
+                }
             }
         }
     }
@@ -638,9 +690,9 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
             bool changed = false;
             UT maxdec = UT(0);
     #pragma unroll
-            for (int p = 0; p < NP; ++p) {
+            for (int p = 0; p < NS; ++p) {
                 uint32_t e = (pr.pk[p >> 1] >> ((p & 1) * 16)) & 0xFFFFu;
-                // Keep the decode inside the sweep loop: hoisting the 3 x NP decoded coordinates
+                // Keep the decode inside the sweep loop: hoisting the 3 x NS decoded coordinates
                 // out of it costs more registers than the few ALU operations it saves.
                 asm volatile("" : "+v"(e));
                 const int x = (int)(e & 31u) ^ mx, y = (int)((e >> 5) & 31u) ^ my,
@@ -655,7 +707,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                 // Issue every LDS read of the step before the activity test: one LDS round trip.
                 asm volatile("" : "+v"(raw), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
                              "+v"(zm), "+v"(zp));
-                const bool act = ((pr.valid >> p) & 1u) && is_active(raw);
+                const bool act = pr.has(p) && is_active(raw);
                 if (__any(act)) {
                     // An active lane stores its value back (|raw| clears the flag); a decrease
                     // activates every neighbour that is inactive (sign clear) and larger than
@@ -757,7 +809,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                 uint32_t af = L.A[b];
                 asm volatile("" : "+v"(old), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
                              "+v"(zm), "+v"(zp), "+v"(af));
-                const bool act = ((pr.valid >> t) & 1u) && af != 0u;
+                const bool act = pr.has(t) && af != 0u;
                 if (__any(act)) {
                     const UT g = local_solve(vmin(xm, xp), vmin(ym, yp), vmin(zm, zp), s);
                     const bool live = act && s > UT(0);
@@ -919,23 +971,36 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
             for (int f = 0; f < 6; ++f) {
                 const int nb = cell_neighbour(S, lc, cc, f);
                 bool ch = false, inflow = false;
-                UT v = INF;
-                if (lane < R2) {
-                    int x, y, z;
-                    face_node<R>(f, lane % R, lane / R, x, y, z);
-                    const int b = box_index<R>(x, y, z);
-                    v = fabs(L.U[b]);
-                    ch = v < before[f];
-                    inflow = ch && v < fabs(L.U[b + face_step<R>(f)]);
+                UT v[FPL], in_min = INF, in_max = -INF;
+#pragma unroll
+                for (int j = 0; j < FPL; ++j) {
+                    const int e = lane + 64 * j;
+                    v[j] = INF;
+                    if (e < R2) {
+                        int x, y, z;
+                        face_node<R>(f, e % R, e / R, x, y, z);
+                        const int b = box_index<R>(x, y, z);
+                        v[j] = fabs(L.U[b]);
+                        const bool chj = v[j] < before[f][j];
+                        const bool inj = chj && v[j] < fabs(L.U[b + face_step<R>(f)]);
+                        ch |= chj;
+                        inflow |= inj;
+                        in_min = inj ? vmin(in_min, v[j]) : in_min;
+                        in_max = inj ? vmax(in_max, v[j]) : in_max;
+                    }
                 }
-                if (__any(ch) && lane < R2) fw[((size_t)lc * 6 + f) * R2 + lane] = v;
+                if (__any(ch)) {
+#pragma unroll
+                    for (int j = 0; j < FPL; ++j)
+                        if (lane + 64 * j < R2) fw[((size_t)lc * 6 + f) * R2 + lane + 64 * j] = v[j];
+                }
                 if (nb >= 0 && __any(inflow)) {
                     // eq. (5): the smallest newly decreased inflow value; eq. (9): the largest
                     // one plus the time to reach the middle of the neighbour, (r h + h) / 2 at
                     // the speed there (its middle node, or the nearest node inside the grid).
-                    double kv = (double)wave_min(inflow ? v : INF);
+                    double kv = (double)wave_min(in_min);
                     if (P.cell_value) {
-                        kv = (double)wave_max(inflow ? v : -INF);
+                        kv = (double)wave_max(in_max);
                         if (lane == f) {
                             const CellXYZ nc = cell_coords(S, nb);
                             const int ex = min(R, S.nx - nc.x * R), ey = min(R, S.ny - nc.y * R),
@@ -1017,14 +1082,15 @@ __device__ bool grid_barrier(const SolveParams& P) {
 // launch runs every round (persistent, grid barrier between rounds).
 
 template <int R, typename FT, int W, int INNER, typename UT>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(sizeof(UT) == 4 ? 4 : 3)))
+__global__ void __launch_bounds__(64 * W)
+    __attribute__((amdgpu_waves_per_eu(R == 16 ? 1 : (sizeof(UT) == 4 ? 4 : 3))))
 k_solve(SolveParams P) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     WaveLds<R, INNER, UT>& L = reinterpret_cast<WaveLds<R, INNER, UT>*>(lds_raw)[wave];
     VisitCounters cnt{0, 0, 0, 0, 0, 0};
     unsigned long long cyc_pop = 0, cyc_wait = 0;
-    PlaneRegs<R> pr;
+    PlaneRegs<R, INNER> pr;
     load_plane_regs<R, INNER>(pr, lane);
     unsigned long long visits = 0, deferred = 0;
     int rounds_done = 0;
@@ -1425,17 +1491,24 @@ static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int worker
     }
     SolveParams Pc = P;
     void* args[] = {&Pc};
-    return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(64 * W), args, lds, s);
+    e = hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(64 * W), args, lds, s);
+    if (e != hipSuccess && std::getenv("EIK_DEBUG"))
+        std::fprintf(stderr, "[eik] cooperative launch of %d x %d threads failed: %s\n", grid,
+                     64 * W, hipGetErrorString(e));
+    return e;
 }
 
 // Workers (waves) per workgroup: one workgroup fills a CU -- as many waves as the register
-// budget allows (three per SIMD in FP64, four in FP32), bounded by the CU's LDS -- so a round
-// barrier has one arrival and one release/acquire pair per CU (each of those costs
-// microseconds per round at hundreds of workgroups).
+// budget allows (three per SIMD in FP64, four in FP32), bounded by the CU's 160 KiB of LDS
+// (150 KiB of it up to r = 8; at r = 16 all but 1 KiB for the static arrays, which makes room
+// for two FP64 or four FP32 cells per CU) -- so a round barrier has one arrival and one
+// release/acquire pair per CU (each of those costs microseconds per round at hundreds of
+// workgroups).
 template <int R, int INNER, typename UT>
 constexpr int waves_per_group() {
     constexpr int by_regs = sizeof(UT) == 4 ? 16 : 12;
-    constexpr int by_lds = (int)((150u * 1024u) / sizeof(WaveLds<R, INNER, UT>));
+    constexpr unsigned budget = (R == 16 ? 159u : 150u) * 1024u;
+    constexpr int by_lds = (int)(budget / sizeof(WaveLds<R, INNER, UT>));
     return by_regs < by_lds ? by_regs : by_lds;
 }
 
@@ -1447,8 +1520,10 @@ static hipError_t solve_rounds_ut(const SolveParams& P, hipStream_t s, int worke
     if (P.inner == INNER_LIST)
         return launch_solve_t<R, FT, waves_per_group<R, INNER_LIST, UT>(), INNER_LIST, UT>(
             P, s, workers, used);
-    return launch_solve_t<R, FT, waves_per_group<R, INNER_DUAL, UT>(), INNER_DUAL, UT>(
-        P, s, workers, used);
+    if constexpr (R <= 8)
+        return launch_solve_t<R, FT, waves_per_group<R, INNER_DUAL, UT>(), INNER_DUAL, UT>(
+            P, s, workers, used);
+    return hipErrorInvalidValue;  // the host refuses two sweep streams at r = 16
 }
 
 template <int R, typename FT>
@@ -1489,7 +1564,11 @@ hipError_t launch_init_slot(const SolveParams& P, const Slot& S, int slot, int c
     const int threads = 256;
     const size_t nodes = (size_t)S.ncell * cell * cell * cell;
     const int blocks = blocks_for(nodes, threads);
-    if (cell == 8 && S.fp32)
+    if (cell == 16 && S.fp32)
+        init_slot_t<16, float>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+    else if (cell == 16)
+        init_slot_t<16, double>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+    else if (cell == 8 && S.fp32)
         init_slot_t<8, float>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
     else if (cell == 8)
         init_slot_t<8, double>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
@@ -1516,7 +1595,9 @@ static void seed_t(const SolveParams& P, const Slot& S, int f_dtype, int64_t rou
 hipError_t launch_seed(const SolveParams& P, const Slot& S, int cell, int f_dtype, int64_t round,
                        int64_t nsrc, const int64_t* idx3, const double* q, hipStream_t s) {
     if (nsrc <= 0) return hipSuccess;
-    if (cell == 8 && S.fp32) seed_t<8, float>(P, S, f_dtype, round, nsrc, idx3, q, s);
+    if (cell == 16 && S.fp32) seed_t<16, float>(P, S, f_dtype, round, nsrc, idx3, q, s);
+    else if (cell == 16) seed_t<16, double>(P, S, f_dtype, round, nsrc, idx3, q, s);
+    else if (cell == 8 && S.fp32) seed_t<8, float>(P, S, f_dtype, round, nsrc, idx3, q, s);
     else if (cell == 8) seed_t<8, double>(P, S, f_dtype, round, nsrc, idx3, q, s);
     else if (cell == 4 && S.fp32) seed_t<4, float>(P, S, f_dtype, round, nsrc, idx3, q, s);
     else if (cell == 4) seed_t<4, double>(P, S, f_dtype, round, nsrc, idx3, q, s);
@@ -1526,6 +1607,9 @@ hipError_t launch_seed(const SolveParams& P, const Slot& S, int cell, int f_dtyp
 
 hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipStream_t s,
                                int workers, int* used) {
+    if (cell == 16)
+        return f_dtype == EIK_F32 ? solve_rounds_t<16, float>(P, s, workers, used)
+                                  : solve_rounds_t<16, double>(P, s, workers, used);
     if (cell == 8)
         return f_dtype == EIK_F32 ? solve_rounds_t<8, float>(P, s, workers, used)
                                   : solve_rounds_t<8, double>(P, s, workers, used);
@@ -1538,7 +1622,11 @@ hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipS
 hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s) {
     const int threads = 256;
     const int ob = blocks_for((size_t)S.nx * S.ny * S.nz, threads);
-    if (cell == 8 && S.fp32)
+    if (cell == 16 && S.fp32)
+        hipLaunchKernelGGL((k_output<16, float>), dim3(ob), dim3(threads), 0, s, S, u_out);
+    else if (cell == 16)
+        hipLaunchKernelGGL((k_output<16, double>), dim3(ob), dim3(threads), 0, s, S, u_out);
+    else if (cell == 8 && S.fp32)
         hipLaunchKernelGGL((k_output<8, float>), dim3(ob), dim3(threads), 0, s, S, u_out);
     else if (cell == 8)
         hipLaunchKernelGGL((k_output<8, double>), dim3(ob), dim3(threads), 0, s, S, u_out);
@@ -1552,7 +1640,9 @@ hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s) 
 hipError_t launch_lift(const Slot& S32, const Slot& S64, int cell, double factor, hipStream_t s) {
     const int threads = 256;
     const int blocks = blocks_for((size_t)S64.ncell * cell * cell * cell, threads);
-    if (cell == 8)
+    if (cell == 16)
+        hipLaunchKernelGGL((k_lift<16>), dim3(blocks), dim3(threads), 0, s, S32, S64, factor);
+    else if (cell == 8)
         hipLaunchKernelGGL((k_lift<8>), dim3(blocks), dim3(threads), 0, s, S32, S64, factor);
     else
         hipLaunchKernelGGL((k_lift<4>), dim3(blocks), dim3(threads), 0, s, S32, S64, factor);

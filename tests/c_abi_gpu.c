@@ -128,7 +128,9 @@ int main(void) {
     /* eik_solve: FP32 speeds, default options. */
     eik_stats st;
     memset(&st, 0, sizeof st);
-    CHECK(eik_solve(dims, H, d_f32, EIK_F32, &src[0], d_u[0], 8, 0.0, stream) == EIK_OK);
+    int rc = eik_solve(dims, H, d_f32, EIK_F32, &src[0], d_u[0], 8, 0.0, stream);
+    if (rc != EIK_OK) printf("eik_solve returned %s\n", eik_strerror(rc));
+    CHECK(rc == EIK_OK);
     CHECK(eik_stream_status(stream, &st) == EIK_OK);
     CHECK(st.cells == 9 * 9 * 9 && st.visits >= st.cells && st.rounds > 0);
     printf("eik_solve: rounds %lld, visits %lld, updates %lld\n", (long long)st.rounds,

@@ -104,6 +104,39 @@ def test_problem_bytes():
         eik.problem_bytes((65, 65, 65), 8, 3)
 
 
+def test_problem_bytes_cell_16():
+    """Cells of 16: 65 nodes per axis -> 5 cells (the last holds one node layer), 4096 nodes and
+    six faces of 256 per cell."""
+    ncell = 5 ** 3
+    want = sum(-(-b // 256) * 256 for b in (ncell * 4096 * 8, ncell * 4096 * 4, ncell * 1536 * 8))
+    assert eik.problem_bytes((65, 65, 65), 16, eik.EIK_F32) == want
+    # the node limit applies to the grid rounded up to whole cells: 1280 = 80 * 16 fits, 1290
+    # rounds up to 1296^3 > 2^31
+    assert eik.query_workspace((1280, 1280, 1280), 16, eik.EIK_F32) > 0
+    with pytest.raises(eik.EikError):
+        eik.query_workspace((1290, 1290, 1290), 16, eik.EIK_F32)
+
+
+def test_two_sweep_streams_refused_at_cell_16():
+    """EIK_INNER_DUAL needs both streams' planes in one wave, which holds up to r = 8 only: a
+    solve, a batch and a server asking for it at r = 16 are refused before any device work."""
+    lib = eik.load()
+    d = (ctypes.c_int64 * 3)(17, 17, 17)
+    idx = np.zeros((1, 3), dtype=np.int64)
+    q = np.zeros(1)
+    src = eik.Sources(1, idx.ctypes.data, q.ctypes.data, 0)
+    opts = eik._options(inner=eik.EIK_INNER_DUAL)
+    assert lib.eik_solve_ex(ctypes.cast(d, ctypes.c_void_p), 0.1, ctypes.c_void_p(1), 0,
+                            ctypes.byref(src), ctypes.c_void_p(1), 16, 0.0, None,
+                            ctypes.byref(opts)) == eik.EIK_EINVAL
+    good, keep = _problem()
+    arr = (eik.Problem * 1)(good)
+    assert lib.eik_solve_batch(1, arr, eik.EIK_F32, 16, None, ctypes.byref(opts)) == eik.EIK_EINVAL
+    srv = ctypes.c_void_p()
+    assert lib.eik_server_create(ctypes.byref(srv), 1 << 20, 1000, 4, 16, eik.EIK_F32, None,
+                                 ctypes.byref(opts)) == eik.EIK_EINVAL
+
+
 def _problem(dims=(8, 8, 8), h=0.1, F=1, u=1, n=1, idx=None, q=None, tol=0.0):
     idx = np.array([[0, 0, 0]] * max(n, 1), dtype=np.int64) if idx is None else idx
     q = np.zeros(max(n, 1)) if q is None else q

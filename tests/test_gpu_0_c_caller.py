@@ -1,7 +1,12 @@
 """A C99 program (tests/c_abi_gpu.c) drives GPU solves through the C ABI with no Python and no
 torch in its process: eik_solve, eik_solve_ex in the mixed mode, eik_solve_batch and a server.
 It checks what eq. (2) fixes for a constant-speed point source (axis values q + d h bit for bit,
-the two- and three-term roots next to the exit, a vanishing residual everywhere)."""
+the two- and three-term roots next to the exit, a vanishing residual everywhere).
+
+The HIP runtime grants cooperative launches to one process per device at a time: once a
+process has launched the solver, another process's launches fail (EIK_EHIP) until it exits.
+The program therefore runs before any other GPU test of the session (this file sorts first
+among them), while the test process itself has launched nothing."""
 import os
 import shutil
 import subprocess
