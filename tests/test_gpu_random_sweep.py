@@ -40,12 +40,29 @@ def draw(case: int):
     return p, cfg
 
 
+def draw16(case: int):
+    """A case of the same recipe with cells of 16 (sweeps or the list relaxation)."""
+    p, cfg = draw(90_000 + case)
+    cfg["cell"] = 16
+    cfg["inner"] = 1 + case % 2
+    p.cell = 16
+    return p, cfg
+
+
 @pytest.mark.parametrize("case", range(CASES))
 def test_random_configuration_matches_oracle(orc, case):
+    run_case(orc, *draw(case))
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_random_configuration_cell16_matches_oracle(orc, case):
+    run_case(orc, *draw16(case))
+
+
+def run_case(orc, p, cfg):
     import torch
     from paper_1306_4743_amd import eik
     dev = torch.device("cuda:0")
-    p, cfg = draw(case)
     F = torch.from_numpy(np.ascontiguousarray(p.F)).to(dev)
     kw = dict(cell=cfg["cell"], inner=cfg["inner"], delta=cfg["delta"], shuffle=cfg["shuffle"],
               max_sweeps=cfg["max_sweeps"])
