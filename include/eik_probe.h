@@ -2,10 +2,12 @@
  * eik_probe.h -- bandwidth probes of the device the solver runs on (libeik_probe.so).
  *
  * The solver's kernels are judged against two rooflines: HBM bandwidth for the cells' global
- * traffic and LDS bandwidth for the in-cell sweeps.  The published peaks (8 TB/s HBM3E;
- * 256 CUs x 128 B per clock x 2.4 GHz = 78.6 TB/s LDS) are what the bench reports fractions of;
- * these probes measure what plain kernels reach on the same device, so that the fractions can be
- * read against an achievable figure too.  They are measurement tools, not part of the solve.
+ * traffic and LDS bandwidth for the in-cell sweeps.  The peaks (8 TB/s HBM3E; 256 CUs x 256 B
+ * per clock x 2.4 GHz = 157 TB/s LDS, a figure the LDS read probe's 161 B per clock per CU
+ * already shows the older 128 B per clock to understate) are what the bench reports fractions
+ * of; these probes measure what plain kernels reach on the same device, so that the fractions
+ * can be read against an achievable figure too.  They are measurement tools, not part of the
+ * solve.
  *
  * All pointers are device pointers; the caller owns every buffer.  Every call enqueues on
  * `stream`, waits for it, and returns 0 or -3 (a HIP error) / -1 (invalid argument).
