@@ -319,3 +319,17 @@ def test_headers_are_a_c_abi(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "0 failures" in out.stdout
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without libeik.so the binding raises on load and on every solve: there is no CPU
+    fallback that could stand in for the HIP path."""
+    import numpy as np
+    monkeypatch.setattr(eik, "LIB_PATH", str(tmp_path / "libeik.so"))
+    monkeypatch.setattr(eik, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        eik.load()
+    import torch
+    F = torch.ones((4, 4, 4), dtype=torch.float64)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        eik.solve(F, 0.25, np.zeros((1, 3), np.int64), np.zeros(1), cell=8)
