@@ -1,6 +1,7 @@
 /* A plain C99 caller of the C ABI: compiled with gcc against include/eik.h and
  * include/eik_probe.h, linked with libeik.so and libeik_probe.so, and run without a GPU (only
- * the host-side entry points are called: sizes, argument checks, names). */
+ * the host-side entry points are called: sizes, argument checks, names; the fake device
+ * pointers are refused before any use). */
 #include <stdio.h>
 #include <string.h>
 
@@ -27,6 +28,26 @@ int main(void) {
     memset(&pb, 0, sizeof pb);
     CHECK(eik_solve_batch(0, &pb, EIK_F32, 8, NULL, NULL) == EIK_EINVAL);
     CHECK(eik_server_create(NULL, 1, 1, 1, 8, EIK_F32, NULL, NULL) == EIK_EINVAL);
+    /* cells of 16: 65 nodes -> 5 cells per axis; two sweep streams are refused there */
+    size_t g16 = 0;
+    CHECK(eik_problem_bytes(dims, 16, EIK_F32, EIK_MODE_FP64, &g16) == EIK_OK);
+    CHECK(g16 >= (size_t)125 * 4096 * (8 + 4) + (size_t)125 * 1536 * 8);
+    CHECK(eik_problem_bytes(dims, 32, EIK_F32, EIK_MODE_FP64, &g16) == EIK_EINVAL);
+    eik_options dual;
+    memset(&dual, 0, sizeof dual);
+    dual.inner = EIK_INNER_DUAL;
+    int64_t idx[3] = {0, 0, 0};
+    double q0 = 0.0;
+    eik_sources one;
+    memset(&one, 0, sizeof one);
+    one.n = 1;
+    one.idx3 = idx;
+    one.q = &q0;
+    CHECK(eik_solve_ex(dims, 0.1, (const void*)16, EIK_F32, &one, (double*)16, 16, 0.0, NULL,
+                       &dual) == EIK_EINVAL);
+    eik_server* srv = NULL;
+    CHECK(eik_server_create(&srv, 1 << 20, 100, 2, 16, EIK_F32, NULL, &dual) == EIK_EINVAL);
+    CHECK(srv == NULL);
     float ms = 0.0f;
     CHECK(eikp_copy(NULL, NULL, 16, 1, NULL, &ms) == -1);
     CHECK(strcmp(eik_strerror(EIK_OK), "EIK_OK") == 0);
