@@ -10,6 +10,7 @@ def test_bytes_per_visit_and_update():
     # s_u (2 r^3 + 6 r^2) + s_F r^3 at r = 8, FP64 values, FP32 speeds
     assert bench.bytes_per_visit(8, 8, 4) == 8 * (2 * 512 + 6 * 64) + 4 * 512 == 13312
     assert bench.bytes_per_visit(4, 8, 8) == 8 * (2 * 64 + 6 * 16) + 8 * 64
+    assert bench.bytes_per_visit(16, 8, 8) == 8 * (2 * 4096 + 6 * 256) + 8 * 4096 == 110592
     assert bench.lds_bytes_per_update() == 72
 
 
@@ -21,12 +22,14 @@ def _chain(u, src, cell):
 
 def test_cell_hop_chain_corner_source(orc):
     """Corner exit of a 17^3 unit-speed grid: the farthest node (16, 16, 16) is reached through
-    two cell faces per axis at r = 8 (16 -> 15 and 8 -> 7), six in all; at r = 4 four per axis."""
+    two cell faces per axis at r = 8 (16 -> 15 and 8 -> 7), six in all; at r = 4 four per axis,
+    at r = 16 one."""
     F = np.ones((17, 17, 17))
     src = np.array([[0, 0, 0]])
     u = orc.fmm(F, 1 / 16, src, np.zeros(1))
     assert _chain(u, src, 8) == 6
     assert _chain(u, src, 4) == 12
+    assert _chain(u, src, 16) == 3  # one face per axis (16 -> 15)
 
 
 def test_cell_hop_chain_line_and_unreachable(orc):
@@ -37,5 +40,6 @@ def test_cell_hop_chain_line_and_unreachable(orc):
     u = orc.fmm(F, 1 / 32, src, np.zeros(1))
     assert _chain(u, src, 8) == 4
     assert _chain(u, src, 4) == 8
+    assert _chain(u, src, 16) == 2
     none = np.full((5, 5, 5), np.inf)
     assert _chain(none, np.zeros((0, 3), np.int64), 4) == 0
