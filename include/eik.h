@@ -7,9 +7,9 @@
  *     sum over axes of max(D^-U, -D^+U, 0)^2 = 1 / F^2,
  * with U = q on the exit nodes and U = +inf beyond the grid (the exit set Q of eq. (1); the rest
  * of the boundary is non-inflow).  The solver follows the Heap-Cell Method (Section 4,
- * Algorithms 1 and 3) and its parallel form (Section 5, Algorithm 2): the grid is split into
+ * Algorithms 1 and 2) and its parallel form (Section 5, Algorithm 3): the grid is split into
  * cubic cells of `cell` nodes per side, cells are swept with Gauss-Seidel / locking-sweeping
- * updates, and a cell-priority worklist (cell values, eq. (5)) decides which cells are swept.
+ * updates, and a cell-priority worklist (cell values, eq. (3)) decides which cells are swept.
  * The discrete solution is unique, so the result does not depend on cell size, schedule or
  * processing order (Section 4, "Assigning Cell Values") beyond rounding.
  *
@@ -24,9 +24,10 @@
  *           call returns once it is enqueued.  Calls on different streams may run concurrently;
  *           each stream has its own workspace.  Calls on one stream are ordered by the stream.
  *   process The solve kernel is a cooperative launch, which the HIP runtime grants to one
- *           process per device at a time: while one process has launched it on a GPU, solves
- *           from another process on that GPU fail with EIK_EHIP.  Serve many callers of one GPU
- *           from one process (streams, batches, a server).
+ *           process per device at a time.  While another process holds it, a solve falls back
+ *           to one ordinary launch per round, driven by the calling thread (EIK_SCHED_AUTO,
+ *           see eik_options.schedule), which blocks the call until the solve ends.  Serve many
+ *           callers of one GPU from one process (streams, batches, a server).
  *   errors  A negative return value is a synchronous error: nothing was enqueued and u_out is
  *           untouched.  Conditions found on the device (invalid speeds, a cap on rounds) are
  *           recorded in the stream's workspace and returned by eik_stream_status(); u_out then
@@ -65,31 +66,52 @@ extern "C" {
  * FP32 storage accumulated along characteristics (max relative error about 1e-5, mean about
  * 1e-7 on the grids here), not the FP64 bar; exit values are rounded to FP32. */
 #define EIK_MODE_FP32 1
-/* FP32 bulk, FP64 polish: the method runs in EIK_MODE_FP32, its result is lifted above the FP64
- * solution (times 1 + max(2^-12, n 2^-20), n the longest side), the exits are re-seeded at
- * their exact values, and the FP64
- * method runs from there: the exits' cells decrease first and every changed face tags the cell
- * downwind of it, so only cells whose boundary changes are swept.  Values only decrease, so it
- * ends at the FP64 solution: same accuracy as EIK_MODE_FP64.  The polish costs about as much as
- * an FP64 solve from +inf (it needs the same chain of rounds), so the mode is slower than
- * EIK_MODE_FP64 by the FP32 phase.  Single solves and batches only. */
+/* FP32 bulk, FP64 polish: the method runs in EIK_MODE_FP32, its result is lifted (times
+ * 1 + max(2^-12, n 2^-20), n the longest side: an empirical margin over the FP32 error, not a
+ * proven bound), the exits are re-seeded at their exact values, and the FP64 method runs from
+ * there: the exits' cells decrease first and every changed face tags the cell downwind of it,
+ * so only cells whose boundary changes are swept.  Values only decrease, so the polish ends at
+ * the FP64 solution wherever the lifted start was not below it.  The polished result is then
+ * checked against eq. (2) at every node (each node's local solve must return its own value to
+ * within 1e-11 s + 2^-46 U); a grid that fails is solved again from +inf in FP64 on the same
+ * stream (counted in eik_stats.polish_redone), so the result meets the EIK_MODE_FP64 accuracy
+ * either way.  With tol > 0 the check is skipped (early termination stops above the fixed
+ * point by design).  The polish costs about as much as an FP64 solve from +inf (it needs the
+ * same chain of rounds), so the mode is slower than EIK_MODE_FP64 by the FP32 phase.  Single
+ * solves and batches only. */
 #define EIK_MODE_MIXED 2
 
 /* Cell values (eik_options.cell_value), the keys of the priority band:
- *   EIK_CELL_VALUE_EQ5  eq. (5): the smallest newly decreased inflow value across the shared
- *                       face; reset to +inf whenever the cell is taken (Section 4).
- *   EIK_CELL_VALUE_EQ9  eq. (9), the authors' earlier heuristic: the largest such value plus
- *                       (r h + h) / 2 over the speed at the middle of the tagged cell, combined
- *                       by min with the cell's previous value, which is never reset. */
-#define EIK_CELL_VALUE_EQ5 0
-#define EIK_CELL_VALUE_EQ9 1
+ *   EIK_CELL_VALUE_NEW  the cell value of Section 4 ("Assigning Cell Values", eq. (3)): the
+ *                       smallest newly decreased inflow value across the shared face; reset to
+ *                       +inf whenever the cell is taken.
+ *   EIK_CELL_VALUE_OLD  the authors' earlier heuristic (Section 6, "Other cell values",
+ *                       eq. (4)): the largest such value plus (r h + h) / 2 over the speed at
+ *                       the middle of the tagged cell, combined by min with the cell's previous
+ *                       value, which is never reset. */
+#define EIK_CELL_VALUE_NEW 0
+#define EIK_CELL_VALUE_OLD 1
+
+/* How the rounds of a solve are driven (eik_options.schedule):
+ *   EIK_SCHED_AUTO         one cooperative launch runs every round, with a grid barrier between
+ *                          rounds; if the runtime refuses the cooperative launch (another
+ *                          process on the device holds one, or the device cannot host the
+ *                          grid at once) the call falls back to EIK_SCHED_HOST_LOOP.
+ *   EIK_SCHED_COOPERATIVE  the cooperative launch only (EIK_EHIP if it is refused).
+ *   EIK_SCHED_HOST_LOOP    one ordinary launch per round, enqueued by the calling thread in
+ *                          batches; it waits for the stream after each batch to see whether the
+ *                          worklist has emptied, so the call blocks until the solve ends.  Needs
+ *                          no co-residency of the workgroups.  Same results. */
+#define EIK_SCHED_AUTO 0
+#define EIK_SCHED_COOPERATIVE 1
+#define EIK_SCHED_HOST_LOOP 2
 
 /* In-cell solvers (eik_options.inner).  All solve the cell sub-problem of Section 4 exactly:
- *   EIK_INNER_SWEEP  locking sweeps (Algorithm 3) in the 8 directions, each sweep visiting the
+ *   EIK_INNER_SWEEP  locking sweeps (Algorithm 2) in the 8 directions, each sweep visiting the
  *                    diagonal planes x'+y'+z' = p of the cell in order (one plane per wave step);
  *   EIK_INNER_LIST   relaxation over a compacted list of active nodes: every pass evaluates the
  *                    listed nodes in dense 64-lane chunks and a node that decreases lists its
- *                    larger neighbours (Algorithm 3 activation without an ordering of nodes);
+ *                    larger neighbours (Algorithm 2 activation without an ordering of nodes);
  *   EIK_INNER_DUAL   the locking sweeps run as two streams on the cell at once, half a sweep
  *                    apart, with directions that never put one node in both streams' planes;
  *                    cells of 4 and 8 only (EIK_EINVAL at 16).
@@ -131,8 +153,9 @@ typedef struct eik_options {
     int64_t round_log_len;
     int inner;            /* in-cell solver: 0 = default (EIK_INNER_SWEEP at cell 8 and 16,
                              EIK_INNER_LIST at cell 4), or one of EIK_INNER_*                */
-    int cell_value;       /* EIK_CELL_VALUE_EQ5 (default) or EIK_CELL_VALUE_EQ9; only the
+    int cell_value;       /* EIK_CELL_VALUE_NEW (default) or EIK_CELL_VALUE_OLD; only the
                              priority band (delta) reads cell values                        */
+    int schedule;         /* EIK_SCHED_*; default EIK_SCHED_AUTO                             */
 } eik_options;
 
 /* Per-solve counters, filled by eik_stream_status(). */
@@ -153,6 +176,8 @@ typedef struct eik_stats {
     int64_t cycles_wait;  /*   publishing the next list and waiting at the round barrier      */
     int64_t sweep_hist[32];             /* visits by sweep count (bucket 31: 31 or more)      */
     int64_t visit_cycles_log2_hist[32]; /* visits by duration, bucket floor(log2(cycles))     */
+    int64_t polish_redone; /* polished grids (EIK_MODE_MIXED, u_approx) whose result failed the
+                              eq. (2) check and were solved again from +inf in FP64           */
 } eik_stats;
 
 /*
@@ -160,9 +185,12 @@ typedef struct eik_stats {
  *   dims     host array {nx, ny, nz}, each >= 2, product < 2^31, and the grid rounded up to
  *            whole cells (ceil(n / cell) * cell per axis) also below 2^31 nodes.
  *   h        grid step, finite and > 0.
- *   F        device array of nx*ny*nz speeds of type f_dtype, each finite and > 0 (checked on
- *            the device; a violation yields EIK_EINVAL from eik_stream_status()).
- *   f_dtype  EIK_F64 or EIK_F32.  Speeds are widened exactly to FP64; s = h / F is formed in FP64.
+ *   F        device array of nx*ny*nz speeds of type f_dtype, each finite and > 0, with
+ *            s = h / F between 2^-500 and 2^500 (between 2^-60 and 2^60 in EIK_MODE_FP32 and
+ *            EIK_MODE_MIXED), the range in which the local solve's squares stay normal numbers;
+ *            checked on the device, a violation yields EIK_EINVAL from eik_stream_status().
+ *   f_dtype  EIK_F64 or EIK_F32.  Speeds are widened exactly to FP64; s = h / F is formed in
+ *            FP64 (and rounded once to FP32 in EIK_MODE_FP32).
  *   sources  exit nodes and values (see eik_sources).
  *   u_out    device array of nx*ny*nz doubles; receives U (+inf where no exit node is reachable,
  *            q at exit nodes).  May not alias F.
@@ -242,9 +270,13 @@ int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
  * with n the longest side, instead of +inf (NaN and +inf entries start at +inf) and sets the
  * exits to their exact values, as the second phase of EIK_MODE_MIXED does; the corrections
  * spread from the exits, and only cells whose boundary changes are swept.  Values only
- * decrease from their start, so the result is the FP64 solution (to the usual 1e-10 relative
- * accuracy) wherever the scaled start is not below it: that holds when u_approx is an upper
- * bound or at most about m relative below the solution.  u_approx is
+ * decrease from their start, so the polish reaches the FP64 solution wherever the scaled start
+ * is not below it (u_approx an upper bound, or at most about m relative below the solution).
+ * The result is checked against eq. (2) at every node as in EIK_MODE_MIXED; a grid whose start
+ * lay too low somewhere fails the check and is solved again from +inf (in a batch: on the
+ * stream, counted in eik_stats.polish_redone; in a server: at the step that would have retired
+ * it, counted by eik_server_polish_redone), so the result has the FP64 accuracy either way
+ * (tol = 0; with tol > 0 the check is skipped).  u_approx is
  * read when the problem starts (in the batch call or at the server step that admits it) and may
  * be the same buffer as u_out.  Ignored for problems without exits (their solution is +inf).
  * Not allowed with EIK_MODE_MIXED (EIK_EINVAL).
@@ -314,11 +346,18 @@ int eik_server_step(eik_server* srv, int64_t rounds, int* finished);
 int eik_server_poll(eik_server* srv, int max, int64_t* tickets, int* status, int* n_out);
 int eik_server_load(eik_server* srv, int* problems, int64_t* cells, size_t* pool_used);
 int eik_server_destroy(eik_server* srv);
+/* Problems of this server that started from u_approx, failed the eq. (2) check of their
+ * polished result and were restarted from +inf (see eik_problem.u_approx); EIK_EINVAL if srv is
+ * NULL. */
+int64_t eik_server_polish_redone(const eik_server* srv);
 
 /* Human-readable name of a status code (static storage). */
 const char* eik_strerror(int code);
 
-/* Frees every workspace (waits for their streams first). */
+/* Frees every workspace and the library's per-device events and pinned words, after waiting
+ * for every device that holds them (hipDeviceSynchronize; the streams they were used on may
+ * already be destroyed).  Must not run concurrently with any other call of the library; a
+ * later call allocates afresh. */
 void eik_release(void);
 
 /* Library version string (static storage). */

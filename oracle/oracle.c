@@ -20,7 +20,7 @@
  *   grid     nx*ny*nz nodes, node (i,j,k) at (i h, j h, k h); arrays are row-major with i
  *            fastest: lin = i + nx*(j + ny*k).  Values beyond the grid are +inf (Section 1.1).
  *   sources  the exit nodes Q' (Section 3 notation): fixed at U = q, never recomputed
- *            (Algorithm 3 only updates nodes outside Q').  A node listed twice keeps min q.
+ *            (Algorithm 2 only updates nodes outside Q').  A node listed twice keeps min q.
  *   F        speed, finite and > 0 at every node; s = h / F is the local travel time.
  *
  * Local solve Gamma.  The paper states that eq. (2) is solved for U_ijk given the neighbour

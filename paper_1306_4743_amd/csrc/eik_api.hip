@@ -79,9 +79,9 @@ bool grid_size(const int64_t dims[3], int cell, int f_dtype, int mode, GridSize*
 // Shared part of a workspace: control area, slot table, per-slot status and counts, and the
 // global per-cell arrays for `cells` cells.
 struct CommonLayout {
-    size_t off_small = 0, off_slots = 0, off_slot_status = 0, off_counts = 0, off_key = 0,
-           off_flags = 0, off_list = 0, off_cell_slot = 0, off_keep = 0, off_slot_minkey = 0,
-           total = 0;
+    size_t off_small = 0, off_slots = 0, off_slot_status = 0, off_counts = 0, off_redo = 0,
+           off_key = 0, off_flags = 0, off_list = 0, off_cell_slot = 0, off_keep = 0,
+           off_slot_minkey = 0, total = 0;
     int nslots = 1;
 };
 
@@ -93,6 +93,7 @@ CommonLayout common_layout(int64_t cells, int slots) {
     L.off_slots = o; o = align_up(o + ns * sizeof(Slot));
     L.off_slot_status = o; o = align_up(o + ns * sizeof(int));
     L.off_counts = o; o = align_up(o + ns * sizeof(int));
+    L.off_redo = o; o = align_up(o + ns * sizeof(int));
     L.off_key = o; o = align_up(o + 2 * n * 8);
     L.off_flags = o; o = align_up(o + 2 * n * 4);
     L.off_list = o; o = align_up(o + 2 * n * 4);
@@ -120,6 +121,7 @@ void bind_common(SolveParams* P, unsigned char* base, const CommonLayout& L, int
     P->status = (int*)(base + L.off_small + kSmallStatus);
     P->stats = (unsigned long long*)(base + L.off_small + kSmallStats);
     P->next_round = (int64_t*)(base + L.off_small + kSmallNextRound);
+    P->halted = (uint32_t*)(base + L.off_small + eik::kSmallHalted);
     P->slot_minkey = (uint64_t*)(base + L.off_slot_minkey);
     P->nslots = L.nslots;
 }
@@ -134,8 +136,9 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
         return EIK_EINVAL;
     if (opt->round_log_len < 0 || (opt->round_log_len > 0 && !opt->round_log)) return EIK_EINVAL;
     if (opt->inner < 0 || opt->inner > EIK_INNER_DUAL) return EIK_EINVAL;
-    if (opt->cell_value != EIK_CELL_VALUE_EQ5 && opt->cell_value != EIK_CELL_VALUE_EQ9)
+    if (opt->cell_value != EIK_CELL_VALUE_NEW && opt->cell_value != EIK_CELL_VALUE_OLD)
         return EIK_EINVAL;
+    if (opt->schedule < EIK_SCHED_AUTO || opt->schedule > EIK_SCHED_HOST_LOOP) return EIK_EINVAL;
     std::memset(P, 0, sizeof(*P));
     P->max_rounds = opt->max_rounds > 0 ? opt->max_rounds : (int64_t(1) << 20);
     // default in-cell solver: sweeps at r = 8 and 16, the list relaxation at r = 4 (measured
@@ -322,6 +325,7 @@ struct DeviceOrder {
     hipEvent_t ev[2] = {nullptr, nullptr};
     int next = 0;
     bool any = false;
+    uint32_t* halted_host = nullptr;  // pinned: the halted word read by the host-driven loop
 };
 std::mutex g_mu;
 std::map<int, DeviceOrder*> g_order;
@@ -335,10 +339,49 @@ DeviceOrder* device_order(int dev) {
     return d;
 }
 
+// Host-driven loop over rounds [P.round_begin, P.round_end): one ordinary launch per round (no
+// grid barrier, so no co-residency is needed), enqueued in growing batches; after each batch the
+// host waits for the stream and reads the halted word.  Blocks the calling thread.
+int host_loop_rounds(DeviceOrder* dord, SolveParams P, int cell, int f_dtype, hipStream_t stream,
+                     int workers) {
+    hipError_t e;
+    if (!dord->halted_host &&
+        (e = hipHostMalloc((void**)&dord->halted_host, 64, hipHostMallocDefault)) != hipSuccess) {
+        dord->halted_host = nullptr;
+        return hip_fail(e);
+    }
+    if ((e = eik::launch_halt_reset(P, stream)) != hipSuccess) return hip_fail(e);
+    const int64_t begin = P.round_begin, end = P.round_end;
+    P.single_round = 1;
+    int64_t t = begin;
+    int batch = 4;
+    while (t < end) {
+        for (int i = 0; i < batch && t < end; ++i, ++t) {
+            P.round_begin = t;
+            P.round_end = t + 1;
+            P.count_workers = t == begin;
+            int used = 0;
+            if ((e = eik::launch_solve_rounds(P, cell, f_dtype, stream, workers, &used, 0)) !=
+                hipSuccess)
+                return hip_fail(e);
+        }
+        if ((e = hipMemcpyAsync(dord->halted_host, P.halted, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return hip_fail(e);
+        if (*dord->halted_host) break;
+        batch = std::min(2 * batch, 64);
+    }
+    if ((e = eik::launch_hostloop_end(P, end, stream)) != hipSuccess) return hip_fail(e);
+    return EIK_OK;
+}
+
 // Launches the persistent solve kernel for rounds [P.round_begin, P.round_end), ordered after
-// every earlier solve kernel of the device.
+// every earlier solve kernel of the device.  EIK_SCHED_AUTO falls back to the host-driven loop
+// when the runtime refuses the cooperative launch (e.g. another process on the device holds
+// one).
 int ordered_solve(int dev, const SolveParams& P, int cell, int f_dtype, hipStream_t stream,
-                  int workers) {
+                  int workers, int schedule) {
     DeviceOrder* dord = device_order(dev);
     std::lock_guard<std::mutex> lk(dord->mu);
     for (auto& ev : dord->ev) {
@@ -350,9 +393,21 @@ int ordered_solve(int dev, const SolveParams& P, int cell, int f_dtype, hipStrea
     hipError_t e;
     if (dord->any && (e = hipStreamWaitEvent(stream, dord->ev[dord->next ^ 1], 0)) != hipSuccess)
         return hip_fail(e);
-    int used = 0;
-    e = eik::launch_solve_rounds(P, cell, f_dtype, stream, workers, &used);
-    if (e != hipSuccess) return hip_fail(e);
+    bool done = false;
+    if (schedule != EIK_SCHED_HOST_LOOP) {
+        SolveParams Pc = P;
+        Pc.single_round = 0;
+        Pc.count_workers = 1;
+        int used = 0;
+        e = eik::launch_solve_rounds(Pc, cell, f_dtype, stream, workers, &used, 1);
+        if (e == hipSuccess) done = true;
+        else if (schedule == EIK_SCHED_COOPERATIVE) return hip_fail(e);
+        else (void)hipGetLastError();  // refused: clear the error and take the host loop
+    }
+    if (!done) {
+        int rc = host_loop_rounds(dord, P, cell, f_dtype, stream, workers);
+        if (rc != EIK_OK) return rc;
+    }
     if ((e = hipEventRecord(dord->ev[dord->next], stream)) != hipSuccess) return hip_fail(e);
     dord->any = true;
     dord->next ^= 1;
@@ -409,6 +464,104 @@ int ensure_device(void** p, size_t* have, size_t need, hipStream_t stream) {
     e = hipMalloc(p, need);
     if (e != hipSuccess) { *p = nullptr; return hip_fail(e); }
     *have = need;
+    return EIK_OK;
+}
+
+// The kernel sequence of a solve of n problems whose workspace (common part at `base`, layout L,
+// grids' arrays where `slots` point) and device slot table are in place; refs holds each
+// problem's exits as device pointers.  ev: 4 events to record (or null).
+int enqueue_solve(int device, int n, const eik_problem* pbs, int f_dtype, int cell,
+                  const eik_options& opt, SolveParams P, const Slot* slots,
+                  const SourceRefs* refs, unsigned char* base, const CommonLayout& L,
+                  int64_t nsrc_total, hipEvent_t* ev, hipStream_t stream) {
+    hipError_t e;
+    int rc;
+    const bool mixed = opt.mode == EIK_MODE_MIXED;
+    bool polish = false;  // some problem starts from a given approximation
+    for (int i = 0; i < n; ++i) polish = polish || start_values(pbs[i]) != nullptr;
+    // Mixed precision runs the method twice: in FP32 on the twins, then in FP64 from the FP32
+    // result lifted above the FP64 solution, with the exits re-seeded at their exact values.  A
+    // given approximation is polished the same way.  Nothing else is queued: the exact exit
+    // values decrease the cells around them, whose changed faces tag their downwind neighbours,
+    // so the polish reaches every cell whose boundary changes, in the order of a solve from
+    // +inf, and visits no other.
+    SolveParams P1 = P;
+    const Slot* first = slots;
+    if (mixed) {
+        P1.fp32 = 1;
+        P1.slots = P.slots + n;
+        first = slots + n;
+    }
+    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return hip_fail(e);
+    if ((e = eik::launch_init_global(P, stream)) != hipSuccess) return hip_fail(e);
+    for (int i = 0; i < n; ++i) {
+        const double* u0 = start_values(pbs[i]);
+        e = eik::launch_init_slot(P1, first[i], i, cell, f_dtype, pbs[i].F, u0,
+                                  lift_factor(pbs[i].dims), stream);
+        if (e != hipSuccess) return hip_fail(e);
+        e = eik::launch_seed(P1, first[i], cell, f_dtype, 0, pbs[i].sources.n, refs[i].idx3,
+                             refs[i].q, stream, nullptr, u0 != nullptr);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return hip_fail(e);
+    if (nsrc_total > 0) {
+        P1.round_begin = 0;
+        P1.round_end = P1.max_rounds;
+        rc = ordered_solve(device, P1, cell, f_dtype, stream, opt.workers, opt.schedule);
+        if (rc != EIK_OK) return rc;
+        if (mixed) {
+            if ((e = eik::launch_reset_rounds(P, stream)) != hipSuccess) return hip_fail(e);
+            for (int i = 0; i < n; ++i) {
+                if ((e = eik::launch_lift(first[i], slots[i], cell, lift_factor(pbs[i].dims),
+                                          stream)) !=
+                        hipSuccess ||
+                    (e = eik::launch_seed(P, slots[i], cell, f_dtype, 0, pbs[i].sources.n,
+                                          refs[i].idx3, refs[i].q, stream, nullptr, true)) !=
+                        hipSuccess)
+                    return hip_fail(e);
+            }
+            P.round_begin = 0;
+            P.round_end = P.max_rounds;
+            rc = ordered_solve(device, P, cell, f_dtype, stream, opt.workers, opt.schedule);
+            if (rc != EIK_OK) return rc;
+        }
+    }
+    if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return hip_fail(e);
+    for (int i = 0; i < n; ++i)
+        if ((e = eik::launch_output(slots[i], cell, pbs[i].u_out, stream)) != hipSuccess)
+            return hip_fail(e);
+    // A polished result (mixed precision, or a given approximation) is checked against eq. (2)
+    // at every node; a grid that fails (its start lay below the solution somewhere) is solved
+    // again from +inf in FP64.  Everything stays on the stream: the re-solve's kernels do
+    // nothing for grids that passed, and its solve launch finds an empty list if all did.
+    if ((mixed || polish) && nsrc_total > 0) {
+        int* redo = (int*)(base + L.off_redo);
+        if ((e = eik::launch_clear_ints(redo, n, stream)) != hipSuccess) return hip_fail(e);
+        for (int i = 0; i < n; ++i) {
+            if (!mixed && !start_values(pbs[i])) continue;
+            if ((e = eik::launch_polish_check(slots[i], cell, f_dtype, pbs[i].u_out, redo + i,
+                                              P.stats, stream)) != hipSuccess)
+                return hip_fail(e);
+        }
+        if ((e = eik::launch_reset_rounds(P, stream)) != hipSuccess) return hip_fail(e);
+        for (int i = 0; i < n; ++i) {
+            if (!mixed && !start_values(pbs[i])) continue;
+            if ((e = eik::launch_restart_slot(P, slots[i], i, cell, f_dtype, 0, stream,
+                                              redo + i)) != hipSuccess)
+                return hip_fail(e);
+        }
+        P.round_begin = 0;
+        P.round_end = P.max_rounds;
+        rc = ordered_solve(device, P, cell, f_dtype, stream, opt.workers, opt.schedule);
+        if (rc != EIK_OK) return rc;
+        for (int i = 0; i < n; ++i) {
+            if (!mixed && !start_values(pbs[i])) continue;
+            if ((e = eik::launch_output(slots[i], cell, pbs[i].u_out, stream, redo + i)) !=
+                hipSuccess)
+                return hip_fail(e);
+        }
+    }
+    if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return hip_fail(e);
     return EIK_OK;
 }
 
@@ -478,57 +631,9 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
         ev = &w->ring[4 * (w->timed % Workspace::kRing)];
         w->timed++;
     }
-    // Mixed precision runs the method twice: in FP32 on the twins, then in FP64 from the FP32
-    // result lifted above the FP64 solution, with the exits re-seeded at their exact values.  A
-    // given approximation is polished the same way.  Nothing else is queued: the exact exit
-    // values decrease the cells around them, whose changed faces tag their downwind neighbours,
-    // so the polish reaches every cell whose boundary changes, in the order of a solve from
-    // +inf, and visits no other.
-    SolveParams P1 = P;
-    const Slot* first = slots.data();
-    if (mixed) {
-        P1.fp32 = 1;
-        P1.slots = P.slots + n;
-        first = slots.data() + n;
-    }
-    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return hip_fail(e);
-    if ((e = eik::launch_init_global(P, stream)) != hipSuccess) return hip_fail(e);
-    for (int i = 0; i < n; ++i) {
-        const double* u0 = start_values(pbs[i]);
-        e = eik::launch_init_slot(P1, first[i], i, cell, f_dtype, pbs[i].F, u0,
-                                  lift_factor(pbs[i].dims), stream);
-        if (e != hipSuccess) return hip_fail(e);
-        e = eik::launch_seed(P1, first[i], cell, f_dtype, 0, pbs[i].sources.n, refs[i].idx3,
-                             refs[i].q, stream);
-        if (e != hipSuccess) return hip_fail(e);
-    }
-    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return hip_fail(e);
-    if (nsrc_total > 0) {
-        P1.round_begin = 0;
-        P1.round_end = P1.max_rounds;
-        rc = ordered_solve(w->device, P1, cell, f_dtype, stream, opt.workers);
-        if (rc != EIK_OK) return rc;
-        if (mixed) {
-            if ((e = eik::launch_reset_rounds(P, stream)) != hipSuccess) return hip_fail(e);
-            for (int i = 0; i < n; ++i) {
-                if ((e = eik::launch_lift(first[i], slots[i], cell, lift_factor(pbs[i].dims),
-                                          stream)) !=
-                        hipSuccess ||
-                    (e = eik::launch_seed(P, slots[i], cell, f_dtype, 0, pbs[i].sources.n,
-                                          refs[i].idx3, refs[i].q, stream)) != hipSuccess)
-                    return hip_fail(e);
-            }
-            P.round_begin = 0;
-            P.round_end = P.max_rounds;
-            rc = ordered_solve(w->device, P, cell, f_dtype, stream, opt.workers);
-            if (rc != EIK_OK) return rc;
-        }
-    }
-    if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return hip_fail(e);
-    for (int i = 0; i < n; ++i)
-        if ((e = eik::launch_output(slots[i], cell, pbs[i].u_out, stream)) != hipSuccess)
-            return hip_fail(e);
-    if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return hip_fail(e);
+    rc = enqueue_solve(w->device, n, pbs, f_dtype, cell, opt, P, slots.data(), refs.data(), base,
+                       L, nsrc_total, ev, stream);
+    if (rc != EIK_OK) return rc;
     w->used = true;
     w->cells = cells;
     w->nslots = n;
@@ -594,6 +699,7 @@ struct eik_server {
         GridSize g;
         Slot slot;
         size_t pool_off = 0;
+        bool redone = false;   // restarted from +inf after its polish failed the check
     };
     std::vector<Problem> problems;                       // indexed by slot
     std::vector<std::pair<size_t, size_t>> free_pool;    // (offset, size), sorted
@@ -605,6 +711,7 @@ struct eik_server {
     int* host_words = nullptr;  // pinned: counts, statuses, next round, launch status
     size_t pool_used = 0;
     int64_t cells_used = 0;
+    int64_t polish_redone = 0;
 };
 
 extern "C" {
@@ -799,6 +906,7 @@ int eik_stream_status(hipStream_t stream, eik_stats* stats) {
         stats->cycles_sweep = (int64_t)st[eik::ST_CYC_SWEEP];
         stats->cycles_write = (int64_t)st[eik::ST_CYC_WRITE];
         stats->cycles_wait = (int64_t)st[eik::ST_CYC_WAIT];
+        stats->polish_redone = (int64_t)st[eik::ST_REDONE];
         for (int i = 0; i < 32; ++i) {
             stats->sweep_hist[i] = (int64_t)st[eik::ST_HIST_SWEEPS + i];
             stats->visit_cycles_log2_hist[i] = (int64_t)st[eik::ST_HIST_CYCLES + i];
@@ -851,10 +959,18 @@ void eik_release(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);
+    // Wait for each device that holds library state (not for the streams themselves: a
+    // caller may already have destroyed a stream it solved on).
+    std::vector<int> devs;
+    for (auto& kv : g_ws) devs.push_back(kv.second->device);
+    for (auto& kv : g_order) devs.push_back(kv.first);
+    std::sort(devs.begin(), devs.end());
+    devs.erase(std::unique(devs.begin(), devs.end()), devs.end());
+    for (int d : devs)
+        if (hipSetDevice(d) == hipSuccess) (void)hipDeviceSynchronize();
     for (auto& kv : g_ws) {
         Workspace* w = kv.second;
         (void)hipSetDevice(w->device);
-        (void)hipStreamSynchronize(kv.first.second);
         w->staging.release();
         if (w->base) (void)hipFree(w->base);
         for (auto& x : w->ring)
@@ -862,6 +978,16 @@ void eik_release(void) {
         delete w;
     }
     g_ws.clear();
+    // The events that order solve kernels across streams of a device.
+    for (auto& kv : g_order) {
+        DeviceOrder* d = kv.second;
+        (void)hipSetDevice(kv.first);
+        for (auto& ev : d->ev)
+            if (ev) (void)hipEventDestroy(ev);
+        if (d->halted_host) (void)hipHostFree(d->halted_host);
+        delete d;
+    }
+    g_order.clear();
     (void)hipSetDevice(cur);
 }
 
@@ -886,7 +1012,9 @@ int eik_server_create(eik_server** out, size_t pool_bytes, int64_t max_cells, in
     s->max_problems = max_problems;
     s->pool_bytes = pool_bytes;
     s->layout = common_layout(max_cells, max_problems);
-    const size_t hb = ((size_t)max_problems * 2 + 8) * sizeof(int) + 64;
+    // counts [0, n), statuses [n, 2n), next round and launch status [2n, 2n + 8), redo words
+    // [2n + 8, 3n + 8)
+    const size_t hb = ((size_t)max_problems * 3 + 8) * sizeof(int) + 64;
     if ((e = hipMalloc(&s->base, s->layout.total)) != hipSuccess ||
         (e = hipMalloc(&s->pool, pool_bytes)) != hipSuccess ||
         (e = hipHostMalloc((void**)&s->host_words, hb, hipHostMallocDefault)) != hipSuccess) {
@@ -968,7 +1096,8 @@ int eik_server_step(eik_server* s, int64_t rounds, int* finished) {
                                       lift_factor(p.pb.dims), st);
             if (e != hipSuccess) return hip_fail(e);
             e = eik::launch_seed(s->P, p.slot, s->cell, s->f_dtype, s->next_round,
-                                 p.pb.sources.n, refs[k].idx3, refs[k].q, st);
+                                 p.pb.sources.n, refs[k].idx3, refs[k].q, st, nullptr,
+                                 u0 != nullptr);
             if (e != hipSuccess) return hip_fail(e);
             p.started = true;
         }
@@ -980,7 +1109,7 @@ int eik_server_step(eik_server* s, int64_t rounds, int* finished) {
     P.round_end = s->next_round + rounds;
     P.max_rounds = int64_t(1) << 62;
     P.round_log_len = 0;
-    rc = ordered_solve(s->device, P, s->cell, s->f_dtype, st, s->opt.workers);
+    rc = ordered_solve(s->device, P, s->cell, s->f_dtype, st, s->opt.workers, s->opt.schedule);
     if (rc != EIK_OK) return rc;
     // 3. Per problem: whether a cell is still queued, status; the round where the launch
     //    stopped.
@@ -1002,9 +1131,11 @@ int eik_server_step(eik_server* s, int64_t rounds, int* finished) {
     std::memcpy(&nr, hw + 2 * ns, sizeof(nr));
     s->next_round = nr;
     const int launch_status = hw[2 * ns + 2];
-    // 4. Retire converged problems: write their results, free their space.
+    // 4. Retire converged problems: write their results, free their space.  A polished
+    //    problem's result is first checked against eq. (2); one that fails is restarted from
+    //    +inf (its staged speeds and exits) and stays on the device.
     int nfin = 0;
-    std::vector<int> done;
+    std::vector<int> done, checked;
     for (int i = 0; i < ns; ++i) {
         eik_server::Problem& p = s->problems[i];
         if (!p.active || !p.started) continue;
@@ -1012,9 +1143,43 @@ int eik_server_step(eik_server* s, int64_t rounds, int* finished) {
         if ((e = eik::launch_output(p.slot, s->cell, p.pb.u_out, st)) != hipSuccess)
             return hip_fail(e);
         const int status = hw[ns + i] != 0 ? hw[ns + i] : launch_status;
+        if (status == 0 && start_values(p.pb) && !p.redone && s->opt.mode == EIK_MODE_FP64 &&
+            p.pb.tol == 0.0) {
+            checked.push_back(i);
+            continue;
+        }
         s->finished.push_back({p.ticket, status});
         done.push_back(i);
         ++nfin;
+    }
+    if (!checked.empty()) {
+        int* redo_dev = (int*)(base + s->layout.off_redo);
+        int* redo = hw + 2 * ns + 8;
+        if ((e = eik::launch_clear_ints(redo_dev, ns, st)) != hipSuccess) return hip_fail(e);
+        for (int i : checked) {
+            eik_server::Problem& p = s->problems[i];
+            if ((e = eik::launch_polish_check(p.slot, s->cell, s->f_dtype, p.pb.u_out,
+                                              redo_dev + i, s->P.stats, st)) != hipSuccess)
+                return hip_fail(e);
+        }
+        if ((e = hipMemcpyAsync(redo, redo_dev, (size_t)ns * sizeof(int),
+                                hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(e);
+        for (int i : checked) {
+            eik_server::Problem& p = s->problems[i];
+            if (redo[i]) {
+                if ((e = eik::launch_restart_slot(s->P, p.slot, i, s->cell, s->f_dtype,
+                                                  s->next_round, st, nullptr)) != hipSuccess)
+                    return hip_fail(e);
+                p.redone = true;
+                ++s->polish_redone;
+                continue;
+            }
+            s->finished.push_back({p.ticket, 0});
+            done.push_back(i);
+            ++nfin;
+        }
     }
     if (!done.empty()) {
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e);
@@ -1057,6 +1222,10 @@ int eik_server_load(eik_server* s, int* problems, int64_t* cells, size_t* pool_u
     if (cells) *cells = s->cells_used;
     if (pool_used) *pool_used = s->pool_used;
     return EIK_OK;
+}
+
+int64_t eik_server_polish_redone(const eik_server* s) {
+    return s ? s->polish_redone : (int64_t)EIK_EINVAL;
 }
 
 int eik_server_destroy(eik_server* s) {

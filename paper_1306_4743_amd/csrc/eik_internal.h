@@ -27,6 +27,7 @@ enum {
     ST_ROUNDS = 0, ST_VISITS, ST_SWEEPS, ST_UPDATES, ST_DEFERRED, ST_REQUEUED,
     // shader-clock cycles summed over workers, by phase
     ST_CYC_POP, ST_CYC_STAGE, ST_CYC_SWEEP, ST_CYC_WRITE, ST_CYC_WAIT, ST_WORKERS,
+    ST_REDONE,  // polished grids that failed the eq. (2) check and were solved again
     ST_COUNT = 16,
     // histograms over visits: sweeps (bucket min(n, 31)) and duration (bucket floor(log2 cycles))
     ST_HIST_SWEEPS = 16, ST_HIST_CYCLES = 48, ST_TOTAL = 80
@@ -49,6 +50,7 @@ constexpr size_t kSmallCtl = 0;        // 4 x RoundCtl
 constexpr size_t kSmallBar = 1024;     // barrier: arrivals at [0], generation at [64] (uint32)
 constexpr size_t kSmallStatus = 2048;  // int
 constexpr size_t kSmallNextRound = 2112;  // int64: first round of the next launch
+constexpr size_t kSmallHalted = 2176;  // uint32: a one-round launch found nothing left to do
 constexpr size_t kSmallStats = 2304;   // ST_TOTAL x uint64
 constexpr size_t kSmallBytes = 4096;
 constexpr int kBarGen = 64;            // index of the generation word in the barrier array
@@ -73,9 +75,11 @@ struct SolveParams {
     int max_sweeps;
     int inner;             // in-cell solver: 0 sweeps, 1 active-list relaxation, 2 dual sweeps
     int fp32;              // value type of every slot of the launch: 1 FP32, 0 FP64
-    int cell_value;        // 0: eq. (5) cell values; 1: eq. (9), kept across visits
+    int cell_value;        // 0: eq. (3) cell values; 1: the earlier eq. (4), kept across visits
     int slot_band;         // 1: with a band, each slot's band starts at that slot's own minimum
     int nslots;            // entries of the slot table (row length of slot_minkey)
+    int single_round;      // 1: one round per launch, no grid barrier (host-driven loop)
+    int count_workers;     // 1: this launch adds its waves to the worker counter
     int64_t round_begin;   // first round of this launch
     int64_t round_end;     // the launch stops after round round_end - 1 (end of an epoch)
     int64_t max_rounds;    // absolute cap on rounds -> EIK_ENOCONV
@@ -85,7 +89,7 @@ struct SolveParams {
     const Slot* slots;     // slot table (device)
     const int* cell_slot;  // [global cells] slot of each cell
     uint64_t* key[2];      // cell values (FP64 bit patterns, all >= +0), global cell ids
-    uint64_t* key_keep;    // [global cells] eq. (9) cell values, never reset by a visit
+    uint64_t* key_keep;    // [global cells] eq. (4) cell values, never reset by a visit
     uint32_t* flags[2];
     int32_t* list[2];
     RoundCtl* ctl;         // [4] control blocks, slot = round & 3
@@ -94,6 +98,8 @@ struct SolveParams {
     int* status;           // device status word of the launch (watchdog, round cap)
     unsigned long long* stats;  // [ST_TOTAL]
     int64_t* next_round;   // written when the launch ends: the first round of the next launch
+    uint32_t* halted;      // host-driven loop: set by the first launch that finds its round's
+                           // list empty, the launch status set or the round cap reached
     int64_t* round_log;    // optional [2 * round_log_len]
     int64_t round_log_len;
 };
@@ -102,13 +108,36 @@ struct SolveParams {
 hipError_t launch_init_global(const SolveParams& P, hipStream_t s);
 // Cells of slot S cleared, speeds staged, values <- +inf or, if u_approx (row-major, device) is
 // given, <- |u_approx| * lift with face copies to match.
+// only_if (device, may be null): the init, seed and output kernels do nothing unless *only_if
+// is nonzero (the conditional re-solve after a failed polish check).
 hipError_t launch_init_slot(const SolveParams& P, const Slot& S, int slot, int cell, int f_dtype,
-                            const void* F, const double* u_approx, double lift, hipStream_t s);
+                            const void* F, const double* u_approx, double lift, hipStream_t s,
+                            const int* only_if = nullptr);
+// clear_first: the grid starts from an approximation, whose values at the exits are replaced
+// (not lowered) by q.
 hipError_t launch_seed(const SolveParams& P, const Slot& S, int cell, int f_dtype, int64_t round,
-                       int64_t nsrc, const int64_t* idx3, const double* q, hipStream_t s);
+                       int64_t nsrc, const int64_t* idx3, const double* q, hipStream_t s,
+                       const int* only_if = nullptr, bool clear_first = false);
+// The persistent solve kernel: a cooperative launch that runs rounds [P.round_begin,
+// P.round_end) with a grid barrier between rounds (coop = 1), or an ordinary launch of one
+// round (coop = 0, P.single_round = 1).
 hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipStream_t s,
-                               int workers, int* used);
-hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s);
+                               int workers, int* used, int coop);
+// Host-driven loop: *P.halted <- 0 before the first one-round launch; after the last one, the
+// round cap is checked for round `end` (EIK_ENOCONV if its list is not empty).
+hipError_t launch_halt_reset(const SolveParams& P, hipStream_t s);
+hipError_t launch_hostloop_end(const SolveParams& P, int64_t end, hipStream_t s);
+hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s,
+                         const int* only_if = nullptr);
+// *redo <- 1 (and stats[ST_REDONE] += 1 once) if the FP64 row-major result u_out of slot S
+// violates eq. (2) at some node beyond rounding (see k_polish_check).  *redo must be 0 before.
+hipError_t launch_polish_check(const Slot& S, int cell, int f_dtype, const double* u_out,
+                               int* redo, unsigned long long* stats, hipStream_t s);
+hipError_t launch_clear_ints(int* p, int n, hipStream_t s);
+// Slot S restarted from +inf with its staged speeds and exit values (nothing of the caller's
+// read) and its exit cells queued for `round`; does nothing unless *only_if (if given) is set.
+hipError_t launch_restart_slot(const SolveParams& P, const Slot& S, int slot, int cell,
+                               int f_dtype, int64_t round, hipStream_t s, const int* only_if);
 // Mixed precision: FP64 values (and faces) of S64 <- FP32 ones of S32 times factor.
 hipError_t launch_lift(const Slot& S32, const Slot& S64, int cell, double factor, hipStream_t s);
 // Round lists emptied and the round counter reset (launch status and counters kept).

@@ -2,15 +2,18 @@
 //
 // Method: Chacon & Vladimirsky, "A parallel Heap-Cell Method for Eikonal equations".
 //   * local solve of eq. (2) (Section 1.1) at one node from its three upwind axis values;
-//   * modified locking-sweeping update inside a cell (Algorithm 3): active flags, strict
+//   * modified locking-sweeping update inside a cell (Algorithm 2): active flags, strict
 //     decrease, activation of larger neighbours, tagging of "currently downwind" cells;
-//   * cell values of eq. (5) with the reset to +inf on removal (Section 4) and the initial
+//   * cell values of eq. (3) with the reset to +inf on removal (Section 4) and the initial
 //     cell values of the exit cells;
 //   * preferred sweep directions set by the tagging neighbour (Section 4, "Processing cells");
-//   * the parallel main loop of Algorithm 2, re-designed for one GPU: every wave64 is a
+//   * the parallel main loop of Algorithm 3, re-designed for one GPU: every wave64 is a
 //     worker that pops cells; cells are popped in rounds from a device worklist, and each
 //     round takes the cells whose value lies in the lowest band [min, min + delta) -- a
-//     bucketed priority queue in place of the per-thread heaps of Algorithms 2, 4 and 5.
+//     bucketed priority queue in place of the per-thread heaps and locks of Algorithms 3-5
+//     (the parallel main loop, "Set Cell Value", "Add Cell").
+// Algorithms are numbered in the paper's order: 1 the HCM main loop, 2 the modified LSM update at
+// a gridpoint (Section 4), 3 the pHCM pseudocode, 4 Set Cell Value, 5 Add Cell (Section 5).
 //
 // GPU design notes (what differs from the paper's shared-memory CPU design):
 //   * The grid is stored cell-blocked (each r^3 cell contiguous) and every cell also keeps a
@@ -330,12 +333,12 @@ __device__ __forceinline__ void face_node(int f, int a, int b, int& x, int& y, i
 }
 
 // ------------------------------------------------------------------------------------------
-// Per-wave LDS of one cell visit.  The active flag of an interior node (Algorithm 3) is the
+// Per-wave LDS of one cell visit.  The active flag of an interior node (Algorithm 2) is the
 // sign bit of its stored value: values are >= +0, so -|U| marks "active" without extra storage
 // and is read together with the value.  Every read of a value goes through fabs().
 
 // In-cell solvers.
-constexpr int INNER_SWEEP = 0;  // locking sweeps in diagonal-plane order (Algorithm 3)
+constexpr int INNER_SWEEP = 0;  // locking sweeps in diagonal-plane order (Algorithm 2)
 constexpr int INNER_LIST = 1;   // relaxation over a compacted list of active nodes
 constexpr int INNER_DUAL = 2;   // two sweep streams on one cell, half a sweep apart
 
@@ -412,11 +415,11 @@ __device__ __forceinline__ void mark_active(float* p, float) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Tagging a neighbour cell for the next round (Algorithm 2 "for each c_k in DN", with Set Cell
+// Tagging a neighbour cell for the next round (Algorithm 3 "for each c_k in DN", with Set Cell
 // Value = atomic min of the cell value and Add Cell = append to the next round's list unless
 // already queued).
 
-// With the eq. (9) cell values the value is first combined with the cell's kept value (which no
+// With the earlier cell values (eq. (4), Section 6 "Other cell values") the value is first combined with the cell's kept value (which no
 // visit resets), and the kept value lowered to the result.
 __device__ __forceinline__ double kept_value(const SolveParams& P, int c, double value) {
     if (!P.cell_value) return value;
@@ -555,7 +558,6 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
     const CellXYZ cc = cell_coords(S, lc);
     const UT* __restrict__ ug = reinterpret_cast<const UT*>(S.u) + (size_t)lc * R3;
     const UT* __restrict__ faces = reinterpret_cast<const UT*>(S.faces);
-    const UT hh = (UT)S.h;
     const FT* __restrict__ fg = reinterpret_cast<const FT*>(S.f) + (size_t)lc * R3;
 
     // Stage in: cell values, s = h/F and the halo (the neighbours' opposite face copies, +inf
@@ -594,7 +596,9 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
             const int l = lane + 64 * (k0 + k);
             const int x = l % R, y = (l / R) % R, z = l / R2;
             L.U[box_index<R>(x, y, z)] = uv[k];
-            L.S[l] = fv[k] > FT(0) ? hh / (UT)fv[k] : (fv[k] < FT(0) ? UT(-1) : UT(0));
+            // s = h / F formed in FP64 and rounded once to the value type.
+            L.S[l] = fv[k] > FT(0) ? (UT)(S.h / (double)fv[k])
+                                   : (fv[k] < FT(0) ? UT(-1) : UT(0));
         }
     }
 #pragma unroll
@@ -863,7 +867,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
         // Relaxation over a list of active nodes (the cell sub-problem of Section 4 solved by a
         // label-correcting iteration instead of sweeps, which Section 5 allows): every pass
         // evaluates the listed nodes in dense 64-lane chunks, and a node that decreases queues
-        // its larger in-cell neighbours for the next pass (Algorithm 3 activation).  The sign bit
+        // its larger in-cell neighbours for the next pass (Algorithm 2 activation).  The sign bit
         // of a value means "listed and not yet evaluated"; setting it with an LDS atomic
         // dedupes the lists.  Chunks see earlier chunks' results (values only decrease), so the
         // iteration reaches the same fixed point as the sweeps.
@@ -943,7 +947,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
     cnt.updates += upd;
     const unsigned long long t2 = cycles();
 
-    // Write back the cell and the faces that changed; tag downwind neighbours (eq. (5) value:
+    // Write back the cell and the faces that changed; tag downwind neighbours (eq. (3) value:
     // the smallest newly decreased border value below the neighbour's value across the face).
     // Lane f (f < 6) tags the neighbour across face f; lane 6 re-queues the cell itself.
     bool my_tag = false;
@@ -995,7 +999,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                         if (lane + 64 * j < R2) fw[((size_t)lc * 6 + f) * R2 + lane + 64 * j] = v[j];
                 }
                 if (nb >= 0 && __any(inflow)) {
-                    // eq. (5): the smallest newly decreased inflow value; eq. (9): the largest
+                    // eq. (3): the smallest newly decreased inflow value; eq. (4): the largest
                     // one plus the time to reach the middle of the neighbour, (r h + h) / 2 at
                     // the speed there (its middle node, or the nearest node inside the grid).
                     double kv = (double)wave_min(in_min);
@@ -1104,6 +1108,24 @@ k_solve(SolveParams P) {
         const int cur = (int)(t & 1), nxt = cur ^ 1;
         RoundCtl* ctl_cur = &P.ctl[t & 3];
         RoundCtl* ctl_next = &P.ctl[(t + 1) & 3];
+        if (P.single_round) {
+            // One round per launch (the host-driven loop): the launch runs round t unless an
+            // earlier launch stopped the loop, the list is empty, the launch status is set or
+            // the round cap is reached.  Every wave reads the same words, which no launch of
+            // this round changes except to stop, so all agree.
+            const uint32_t n0 = __hip_atomic_load(&ctl_cur->count, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t was_halted = __hip_atomic_load(P.halted, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+            const int st0 = __hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const bool stop = was_halted || n0 == 0 || st0 != 0 || t >= P.max_rounds;
+            if (blockIdx.x == 0 && threadIdx.x == 0 && !was_halted) {
+                *P.next_round = stop ? t : t + 1;
+                if (n0 != 0 && st0 == 0 && t >= P.max_rounds) atomicCAS(P.status, 0, EIK_ENOCONV_DEV);
+                if (stop) __hip_atomic_store(P.halted, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (stop) break;
+        }
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             RoundCtl* r2 = &P.ctl[(t + 2) & 3];
             r2->count = 0;
@@ -1139,7 +1161,7 @@ k_solve(SolveParams P) {
             // The last cells of the round go one per pop, so that the round's tail is short.
             if (n - base < (uint32_t)nwaves_total * 2u) chunk_now = 1u;
             // Lanes j < cnt_here take cell j of the chunk: its flags and value are exchanged
-            // for empty ones (the removal of Algorithm 2 with V^c <- +inf).
+            // for empty ones (the removal of Algorithm 3 with V^c <- +inf).
             int my_c = 0, my_slot = 0;
             uint32_t my_fl = 0;
             unsigned long long my_kb = 0;
@@ -1194,6 +1216,14 @@ k_solve(SolveParams P) {
                 atomicMin((unsigned long long*)&ctl_next->minkey, (unsigned long long)dbits(mk));
         }
         ++rounds_done;
+        if (P.single_round) {
+            // The launch ends here; the next launch on the stream runs round t + 1.
+            if (blockIdx.x == 0 && threadIdx.x == 0 && t < P.round_log_len) {
+                P.round_log[2 * t] = (int64_t)n;
+                P.round_log[2 * t + 1] = (int64_t)cycles();
+            }
+            break;
+        }
         const bool ok = grid_barrier(P);
         cyc_wait += cycles() - tw0;
         if (blockIdx.x == 0 && threadIdx.x == 0 && t < P.round_log_len) {
@@ -1226,7 +1256,7 @@ k_solve(SolveParams P) {
         atomicAdd(&P.stats[ST_CYC_SWEEP], cnt.cyc_sweep);
         atomicAdd(&P.stats[ST_CYC_WRITE], cnt.cyc_write);
         atomicAdd(&P.stats[ST_CYC_WAIT], cyc_wait);
-        atomicAdd(&P.stats[ST_WORKERS], 1ull);
+        if (P.count_workers) atomicAdd(&P.stats[ST_WORKERS], 1ull);
         if (blockIdx.x == 0 && wave == 0) atomicAdd(&P.stats[ST_ROUNDS], (unsigned long long)rounds_done);
     }
     // Every workgroup leaves the round loop in the same round, so all its waves get here.
@@ -1238,11 +1268,23 @@ k_solve(SolveParams P) {
 // ------------------------------------------------------------------------------------------
 // Stage inputs (a1): row-major F -> cell-blocked F of one slot with padding marked 0, u <- +inf
 // (NaN on padding), or, to polish a given approximation, u <- |u_approx| * lift.  Speeds that
-// are not finite and positive set the slot's status to EIK_EINVAL.
+// are not finite and positive, or whose s = h / F lies outside the range the local solve is
+// exact in, set the slot's status to EIK_EINVAL.
+
+// Range of s = h / F accepted per value type: the local solve squares s and differences of
+// values of the size of s, so s^2 must stay a normal number with room to spare (FP64:
+// 2^-500 .. 2^500; FP32: 2^-60 .. 2^60).
+template <typename UT>
+__device__ __forceinline__ bool s_in_range(double s) {
+    constexpr double lo = sizeof(UT) == 4 ? 0x1p-60 : 0x1p-500;
+    constexpr double hi = sizeof(UT) == 4 ? 0x1p60 : 0x1p500;
+    return s >= lo && s <= hi;
+}
 
 template <int R, typename FT, typename UT>
 __global__ void k_init_nodes(Slot S, const FT* __restrict__ F, const double* __restrict__ u_approx,
-                             double lift) {
+                             double lift, const int* only_if) {
+    if (only_if && *only_if == 0) return;
     constexpr int R3 = R * R * R;
     const size_t total = (size_t)S.ncell * R3;
     const UT INF = (UT)__builtin_inf();
@@ -1258,7 +1300,7 @@ __global__ void k_init_nodes(Slot S, const FT* __restrict__ F, const double* __r
         if (i < S.nx && j < S.ny && k < S.nz) {
             fv = F[(size_t)i + (size_t)S.nx * ((size_t)j + (size_t)S.ny * k)];
             const double dv = (double)fv;
-            if (!(dv > 0.0) || !(dv <= 1.7976931348623157e308)) {
+            if (!(dv > 0.0) || !(dv <= 1.7976931348623157e308) || !s_in_range<UT>(S.h / dv)) {
                 atomicCAS(S.status, 0, EIK_EINVAL_DEV);
                 fv = FT(1);
             }
@@ -1277,7 +1319,8 @@ __global__ void k_init_nodes(Slot S, const FT* __restrict__ F, const double* __r
 
 // Face copies <- the border layers of the (initialised) values, +inf for padding nodes.
 template <int R, typename UT>
-__global__ void k_faces_from_u(Slot S) {
+__global__ void k_faces_from_u(Slot S, const int* only_if) {
+    if (only_if && *only_if == 0) return;
     constexpr int R2 = R * R, R3 = R * R * R;
     const size_t nf = (size_t)S.ncell * 6 * R2;
     const UT* ub = reinterpret_cast<const UT*>(S.u);
@@ -1295,7 +1338,8 @@ __global__ void k_faces_from_u(Slot S) {
 
 // The slot's face copies <- +inf, its cells' state cleared and mapped to the slot.
 template <int R, typename UT>
-__global__ void k_init_cells(SolveParams P, Slot S, int slot) {
+__global__ void k_init_cells(SolveParams P, Slot S, int slot, const int* only_if) {
+    if (only_if && *only_if == 0) return;
     constexpr int R2 = R * R;
     const size_t nf = (size_t)S.ncell * 6 * R2;
     const double INF = __builtin_inf();
@@ -1345,9 +1389,34 @@ __device__ __forceinline__ void atomic_min_val(float* p, float v) {
     atomicMin((unsigned int*)p, __float_as_uint(v));
 }
 
+// Before seeding a grid that starts from an approximation: the exit nodes (and their face
+// copies) <- +inf, so that the seed's minimum over duplicate exits sets them to q exactly even
+// where the start held a smaller value.
+template <int R, typename UT>
+__global__ void k_seed_clear(Slot S, int64_t nsrc, const int64_t* __restrict__ idx3) {
+    constexpr int R2 = R * R, R3 = R * R * R;
+    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nsrc) return;
+    const int64_t i = idx3[3 * n], j = idx3[3 * n + 1], k = idx3[3 * n + 2];
+    if (i < 0 || i >= S.nx || j < 0 || j >= S.ny || k < 0 || k >= S.nz) return;  // k_seed reports it
+    const int x = (int)(i % R), y = (int)(j % R), z = (int)(k % R);
+    const int lc = (int)(i / R) + S.ncx * ((int)(j / R) + S.ncy * (int)(k / R));
+    const UT INF = (UT)__builtin_inf();
+    reinterpret_cast<UT*>(S.u)[(size_t)lc * R3 + x + R * (y + R * z)] = INF;
+    const int fx[6] = {x == 0, x == R - 1, y == 0, y == R - 1, z == 0, z == R - 1};
+    for (int f = 0; f < 6; ++f) {
+        if (!fx[f]) continue;
+        const int a = (f >> 1) == 0 ? y : x;
+        const int b = (f >> 1) == 2 ? y : z;
+        reinterpret_cast<UT*>(S.faces)[((size_t)lc * 6 + f) * R2 + a + R * b] = INF;
+    }
+}
+
 template <int R, typename FT, typename UT>
 __global__ void k_seed(SolveParams P, Slot S, int64_t round, int64_t nsrc,
-                       const int64_t* __restrict__ idx3, const double* __restrict__ q) {
+                       const int64_t* __restrict__ idx3, const double* __restrict__ q,
+                       const int* only_if) {
+    if (only_if && *only_if == 0) return;
     constexpr int R2 = R * R, R3 = R * R * R;
     const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (n >= nsrc) return;
@@ -1386,7 +1455,8 @@ __global__ void k_seed(SolveParams P, Slot S, int64_t round, int64_t nsrc,
 
 // Output (a8): cell-blocked u of one slot -> row-major u_out.
 template <int R, typename UT>
-__global__ void k_output(Slot S, double* __restrict__ out) {
+__global__ void k_output(Slot S, double* __restrict__ out, const int* only_if) {
+    if (only_if && *only_if == 0) return;
     const UT* ub = reinterpret_cast<const UT*>(S.u);
     constexpr int R3 = R * R * R;
     const size_t total = (size_t)S.nx * S.ny * S.nz;
@@ -1454,7 +1524,8 @@ template <int R, int W, int INNER, typename UT>
 constexpr size_t solve_lds_bytes() { return sizeof(WaveLds<R, INNER, UT>) * W; }
 
 template <int R, typename FT, int W, int INNER, typename UT>
-static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int workers, int* used) {
+static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int workers, int* used,
+                                 int coop) {
     const size_t lds = solve_lds_bytes<R, W, INNER, UT>();
     auto kern = k_solve<R, FT, W, INNER, UT>;
     int dev = 0;
@@ -1490,6 +1561,11 @@ static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int worker
                          prop.cooperativeLaunch, R, W, lds, per_cu, grid);
     }
     SolveParams Pc = P;
+    if (!coop) {
+        // One round, no grid barrier: the workgroups need not be resident together.
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), lds, s, Pc);
+        return hipGetLastError();
+    }
     void* args[] = {&Pc};
     e = hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(64 * W), args, lds, s);
     if (e != hipSuccess && std::getenv("EIK_DEBUG"))
@@ -1513,23 +1589,25 @@ constexpr int waves_per_group() {
 }
 
 template <int R, typename FT, typename UT>
-static hipError_t solve_rounds_ut(const SolveParams& P, hipStream_t s, int workers, int* used) {
+static hipError_t solve_rounds_ut(const SolveParams& P, hipStream_t s, int workers, int* used,
+                                  int coop) {
     if (P.inner == INNER_SWEEP)
         return launch_solve_t<R, FT, waves_per_group<R, INNER_SWEEP, UT>(), INNER_SWEEP, UT>(
-            P, s, workers, used);
+            P, s, workers, used, coop);
     if (P.inner == INNER_LIST)
         return launch_solve_t<R, FT, waves_per_group<R, INNER_LIST, UT>(), INNER_LIST, UT>(
-            P, s, workers, used);
+            P, s, workers, used, coop);
     if constexpr (R <= 8)
         return launch_solve_t<R, FT, waves_per_group<R, INNER_DUAL, UT>(), INNER_DUAL, UT>(
-            P, s, workers, used);
+            P, s, workers, used, coop);
     return hipErrorInvalidValue;  // the host refuses two sweep streams at r = 16
 }
 
 template <int R, typename FT>
-static hipError_t solve_rounds_t(const SolveParams& P, hipStream_t s, int workers, int* used) {
-    return P.fp32 ? solve_rounds_ut<R, FT, float>(P, s, workers, used)
-                  : solve_rounds_ut<R, FT, double>(P, s, workers, used);
+static hipError_t solve_rounds_t(const SolveParams& P, hipStream_t s, int workers, int* used,
+                                 int coop) {
+    return P.fp32 ? solve_rounds_ut<R, FT, float>(P, s, workers, used, coop)
+                  : solve_rounds_ut<R, FT, double>(P, s, workers, used, coop);
 }
 
 static int blocks_for(size_t n, int threads) {
@@ -1547,93 +1625,271 @@ hipError_t launch_init_global(const SolveParams& P, hipStream_t s) {
 template <int R, typename UT>
 static void init_slot_t(const SolveParams& P, const Slot& S, int slot, int f_dtype,
                         const void* F, const double* u_approx, double lift, int blocks,
-                        int threads, hipStream_t s) {
-    hipLaunchKernelGGL((k_init_cells<R, UT>), dim3(blocks), dim3(threads), 0, s, P, S, slot);
+                        int threads, hipStream_t s, const int* only_if) {
+    hipLaunchKernelGGL((k_init_cells<R, UT>), dim3(blocks), dim3(threads), 0, s, P, S, slot,
+                       only_if);
     if (f_dtype == EIK_F32)
         hipLaunchKernelGGL((k_init_nodes<R, float, UT>), dim3(blocks), dim3(threads), 0, s, S,
-                           reinterpret_cast<const float*>(F), u_approx, lift);
+                           reinterpret_cast<const float*>(F), u_approx, lift, only_if);
     else
         hipLaunchKernelGGL((k_init_nodes<R, double, UT>), dim3(blocks), dim3(threads), 0, s, S,
-                           reinterpret_cast<const double*>(F), u_approx, lift);
+                           reinterpret_cast<const double*>(F), u_approx, lift, only_if);
     if (u_approx)
-        hipLaunchKernelGGL((k_faces_from_u<R, UT>), dim3(blocks), dim3(threads), 0, s, S);
+        hipLaunchKernelGGL((k_faces_from_u<R, UT>), dim3(blocks), dim3(threads), 0, s, S,
+                           only_if);
 }
 
 hipError_t launch_init_slot(const SolveParams& P, const Slot& S, int slot, int cell, int f_dtype,
-                            const void* F, const double* u_approx, double lift, hipStream_t s) {
+                            const void* F, const double* u_approx, double lift, hipStream_t s,
+                            const int* only_if) {
     const int threads = 256;
     const size_t nodes = (size_t)S.ncell * cell * cell * cell;
     const int blocks = blocks_for(nodes, threads);
     if (cell == 16 && S.fp32)
-        init_slot_t<16, float>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+        init_slot_t<16, float>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s, only_if);
     else if (cell == 16)
-        init_slot_t<16, double>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+        init_slot_t<16, double>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s, only_if);
     else if (cell == 8 && S.fp32)
-        init_slot_t<8, float>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+        init_slot_t<8, float>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s, only_if);
     else if (cell == 8)
-        init_slot_t<8, double>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+        init_slot_t<8, double>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s, only_if);
     else if (cell == 4 && S.fp32)
-        init_slot_t<4, float>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+        init_slot_t<4, float>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s, only_if);
     else if (cell == 4)
-        init_slot_t<4, double>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s);
+        init_slot_t<4, double>(P, S, slot, f_dtype, F, u_approx, lift, blocks, threads, s, only_if);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 template <int R, typename UT>
 static void seed_t(const SolveParams& P, const Slot& S, int f_dtype, int64_t round, int64_t nsrc,
-                   const int64_t* idx3, const double* q, hipStream_t s) {
+                   const int64_t* idx3, const double* q, hipStream_t s, const int* only_if,
+                   bool clear_first) {
     const int sb = (int)((nsrc + 63) / 64);
+    if (clear_first)
+        hipLaunchKernelGGL((k_seed_clear<R, UT>), dim3(sb), dim3(64), 0, s, S, nsrc, idx3);
     if (f_dtype == EIK_F32)
         hipLaunchKernelGGL((k_seed<R, float, UT>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc,
-                           idx3, q);
+                           idx3, q, only_if);
     else
         hipLaunchKernelGGL((k_seed<R, double, UT>), dim3(sb), dim3(64), 0, s, P, S, round, nsrc,
-                           idx3, q);
+                           idx3, q, only_if);
 }
 
 hipError_t launch_seed(const SolveParams& P, const Slot& S, int cell, int f_dtype, int64_t round,
-                       int64_t nsrc, const int64_t* idx3, const double* q, hipStream_t s) {
+                       int64_t nsrc, const int64_t* idx3, const double* q, hipStream_t s,
+                       const int* only_if, bool clear_first) {
     if (nsrc <= 0) return hipSuccess;
-    if (cell == 16 && S.fp32) seed_t<16, float>(P, S, f_dtype, round, nsrc, idx3, q, s);
-    else if (cell == 16) seed_t<16, double>(P, S, f_dtype, round, nsrc, idx3, q, s);
-    else if (cell == 8 && S.fp32) seed_t<8, float>(P, S, f_dtype, round, nsrc, idx3, q, s);
-    else if (cell == 8) seed_t<8, double>(P, S, f_dtype, round, nsrc, idx3, q, s);
-    else if (cell == 4 && S.fp32) seed_t<4, float>(P, S, f_dtype, round, nsrc, idx3, q, s);
-    else if (cell == 4) seed_t<4, double>(P, S, f_dtype, round, nsrc, idx3, q, s);
+#define EIK_SEED(R, UT) seed_t<R, UT>(P, S, f_dtype, round, nsrc, idx3, q, s, only_if, clear_first)
+    if (cell == 16 && S.fp32) EIK_SEED(16, float);
+    else if (cell == 16) EIK_SEED(16, double);
+    else if (cell == 8 && S.fp32) EIK_SEED(8, float);
+    else if (cell == 8) EIK_SEED(8, double);
+    else if (cell == 4 && S.fp32) EIK_SEED(4, float);
+    else if (cell == 4) EIK_SEED(4, double);
     else return hipErrorInvalidValue;
+#undef EIK_SEED
     return hipGetLastError();
 }
 
 hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipStream_t s,
-                               int workers, int* used) {
+                               int workers, int* used, int coop) {
     if (cell == 16)
-        return f_dtype == EIK_F32 ? solve_rounds_t<16, float>(P, s, workers, used)
-                                  : solve_rounds_t<16, double>(P, s, workers, used);
+        return f_dtype == EIK_F32 ? solve_rounds_t<16, float>(P, s, workers, used, coop)
+                                  : solve_rounds_t<16, double>(P, s, workers, used, coop);
     if (cell == 8)
-        return f_dtype == EIK_F32 ? solve_rounds_t<8, float>(P, s, workers, used)
-                                  : solve_rounds_t<8, double>(P, s, workers, used);
+        return f_dtype == EIK_F32 ? solve_rounds_t<8, float>(P, s, workers, used, coop)
+                                  : solve_rounds_t<8, double>(P, s, workers, used, coop);
     if (cell == 4)
-        return f_dtype == EIK_F32 ? solve_rounds_t<4, float>(P, s, workers, used)
-                                  : solve_rounds_t<4, double>(P, s, workers, used);
+        return f_dtype == EIK_F32 ? solve_rounds_t<4, float>(P, s, workers, used, coop)
+                                  : solve_rounds_t<4, double>(P, s, workers, used, coop);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s) {
+__global__ void k_halt_reset(SolveParams P) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *P.halted = 0u;
+}
+
+// After the last one-round launch of a host-driven loop over rounds [begin, end): if no launch
+// stopped the loop, round `end` is where the next launch starts, and with `end` at the round
+// cap a non-empty list there means the cap was reached.
+__global__ void k_hostloop_end(SolveParams P, int64_t end) {
+    if (blockIdx.x != 0 || threadIdx.x != 0 || *P.halted) return;
+    *P.next_round = end;
+    if (end >= P.max_rounds && P.ctl[end & 3].count != 0) atomicCAS(P.status, 0, EIK_ENOCONV_DEV);
+}
+
+hipError_t launch_halt_reset(const SolveParams& P, hipStream_t s) {
+    hipLaunchKernelGGL(k_halt_reset, dim3(1), dim3(64), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_hostloop_end(const SolveParams& P, int64_t end, hipStream_t s) {
+    hipLaunchKernelGGL(k_hostloop_end, dim3(1), dim3(64), 0, s, P, end);
+    return hipGetLastError();
+}
+
+hipError_t launch_output(const Slot& S, int cell, double* u_out, hipStream_t s,
+                         const int* only_if) {
     const int threads = 256;
     const int ob = blocks_for((size_t)S.nx * S.ny * S.nz, threads);
     if (cell == 16 && S.fp32)
-        hipLaunchKernelGGL((k_output<16, float>), dim3(ob), dim3(threads), 0, s, S, u_out);
+        hipLaunchKernelGGL((k_output<16, float>), dim3(ob), dim3(threads), 0, s, S, u_out, only_if);
     else if (cell == 16)
-        hipLaunchKernelGGL((k_output<16, double>), dim3(ob), dim3(threads), 0, s, S, u_out);
+        hipLaunchKernelGGL((k_output<16, double>), dim3(ob), dim3(threads), 0, s, S, u_out, only_if);
     else if (cell == 8 && S.fp32)
-        hipLaunchKernelGGL((k_output<8, float>), dim3(ob), dim3(threads), 0, s, S, u_out);
+        hipLaunchKernelGGL((k_output<8, float>), dim3(ob), dim3(threads), 0, s, S, u_out, only_if);
     else if (cell == 8)
-        hipLaunchKernelGGL((k_output<8, double>), dim3(ob), dim3(threads), 0, s, S, u_out);
+        hipLaunchKernelGGL((k_output<8, double>), dim3(ob), dim3(threads), 0, s, S, u_out, only_if);
     else if (S.fp32)
-        hipLaunchKernelGGL((k_output<4, float>), dim3(ob), dim3(threads), 0, s, S, u_out);
+        hipLaunchKernelGGL((k_output<4, float>), dim3(ob), dim3(threads), 0, s, S, u_out, only_if);
     else
-        hipLaunchKernelGGL((k_output<4, double>), dim3(ob), dim3(threads), 0, s, S, u_out);
+        hipLaunchKernelGGL((k_output<4, double>), dim3(ob), dim3(threads), 0, s, S, u_out, only_if);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Restart of one slot from +inf with the inputs already staged (the conditional re-solve of a
+// polish that failed its check): the blocked speeds still mark the exits (-1) and padding (0),
+// and the exit nodes still hold q (they are never updated), so nothing of the caller's is read.
+
+template <int R, typename FT, typename UT>
+__global__ void k_restart_nodes(Slot S, const int* only_if) {
+    if (only_if && *only_if == 0) return;
+    constexpr int R3 = R * R * R;
+    const size_t total = (size_t)S.ncell * R3;
+    const FT* fb = reinterpret_cast<const FT*>(S.f);
+    UT* ub = reinterpret_cast<UT*>(S.u);
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < total;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const FT fv = fb[g];
+        if (fv > FT(0)) ub[g] = (UT)__builtin_inf();
+        else if (fv == FT(0)) ub[g] = (UT)__builtin_nan("");
+    }
+}
+
+// Queues, for round `round`, the cell of every exit node and the cells of its six grid
+// neighbours with every node active and cell value q, as k_seed does from the exit list.
+template <int R, typename FT, typename UT>
+__global__ void k_reseed(SolveParams P, Slot S, int64_t round, const int* only_if) {
+    if (only_if && *only_if == 0) return;
+    constexpr int R3 = R * R * R;
+    const size_t total = (size_t)S.ncell * R3;
+    const FT* fb = reinterpret_cast<const FT*>(S.f);
+    const UT* ub = reinterpret_cast<const UT*>(S.u);
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < total;
+         g += (size_t)gridDim.x * blockDim.x) {
+        if (!(fb[g] < FT(0))) continue;
+        const int lc = (int)(g / R3), l = (int)(g % R3);
+        const CellXYZ cc = cell_coords(S, lc);
+        const int64_t i = cc.x * R + l % R, j = cc.y * R + (l / R) % R, k = cc.z * R + l / (R * R);
+        const double qv = (double)ub[g];
+        tag_cell(P, round, S.cell_base + lc, FL_ALL, qv);
+        const int64_t nbr[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
+                                   {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+        for (int t = 0; t < 6; ++t) {
+            const int64_t a = nbr[t][0], b = nbr[t][1], e = nbr[t][2];
+            if (a < 0 || a >= S.nx || b < 0 || b >= S.ny || e < 0 || e >= S.nz) continue;
+            const int nc = (int)(a / R) + S.ncx * ((int)(b / R) + S.ncy * (int)(e / R));
+            if (nc != lc) tag_cell(P, round, S.cell_base + nc, FL_ALL, qv);
+        }
+    }
+}
+
+template <int R, typename FT, typename UT>
+static void restart_t(const SolveParams& P, const Slot& S, int slot, int64_t round, int blocks,
+                      int threads, hipStream_t s, const int* only_if) {
+    hipLaunchKernelGGL((k_init_cells<R, UT>), dim3(blocks), dim3(threads), 0, s, P, S, slot,
+                       only_if);
+    hipLaunchKernelGGL((k_restart_nodes<R, FT, UT>), dim3(blocks), dim3(threads), 0, s, S, only_if);
+    hipLaunchKernelGGL((k_faces_from_u<R, UT>), dim3(blocks), dim3(threads), 0, s, S, only_if);
+    hipLaunchKernelGGL((k_reseed<R, FT, UT>), dim3(blocks), dim3(threads), 0, s, P, S, round,
+                       only_if);
+}
+
+hipError_t launch_restart_slot(const SolveParams& P, const Slot& S, int slot, int cell,
+                               int f_dtype, int64_t round, hipStream_t s, const int* only_if) {
+    const int threads = 256;
+    const int blocks = blocks_for((size_t)S.ncell * cell * cell * cell, threads);
+#define EIK_RESTART(R, UT)                                                                   \
+    (f_dtype == EIK_F32 ? restart_t<R, float, UT>(P, S, slot, round, blocks, threads, s, only_if) \
+                        : restart_t<R, double, UT>(P, S, slot, round, blocks, threads, s, only_if))
+    if (cell == 16) { if (S.fp32) EIK_RESTART(16, float); else EIK_RESTART(16, double); }
+    else if (cell == 8) { if (S.fp32) EIK_RESTART(8, float); else EIK_RESTART(8, double); }
+    else if (cell == 4) { if (S.fp32) EIK_RESTART(4, float); else EIK_RESTART(4, double); }
+    else return hipErrorInvalidValue;
+#undef EIK_RESTART
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Check of a polished result (FP64, row-major u, tol 0): at the fixed point the method reaches,
+// every node outside the exit set satisfies eq. (2) with its final neighbours, i.e. its local
+// solve returns its own value up to rounding.  A polish that started below the solution
+// somewhere cannot raise those values (updates only decrease), and the node where such a
+// region meets correct upwind values has a local solve above its value.  A node whose local
+// solve differs from its value by more than 1e-11 s + 2^-46 U (rounding of the same operator on
+// the same values is a few units of 2^-53 U) flags the grid; an error that passes is at most
+// the sum of such residuals along a characteristic, below 1e-10 relative.
+__device__ __forceinline__ double nbr_min(const double* u, size_t g, size_t stride, bool lo,
+                                          bool hi) {
+    const double a = lo ? u[g - stride] : __builtin_inf();
+    const double b = hi ? u[g + stride] : __builtin_inf();
+    return vmin(a, b);
+}
+
+template <int R, typename FT>
+__global__ void k_polish_check(Slot S, const double* __restrict__ u, int* redo,
+                               unsigned long long* stats) {
+    if (S.tol > 0.0) return;  // early-terminated sweeps stop above the fixed point by design
+    constexpr int R3 = R * R * R;
+    const FT* fb = reinterpret_cast<const FT*>(S.f);
+    const size_t nx = S.nx, ny = S.ny, nz = S.nz, total = nx * ny * nz;
+    bool bad = false;
+    for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < total;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(g % nx), j = (int)((g / nx) % ny), k = (int)(g / (nx * ny));
+        const int lc = i / R + S.ncx * (j / R + S.ncy * (k / R));
+        const double fv = (double)fb[(size_t)lc * R3 + i % R + R * (j % R + R * (k % R))];
+        if (!(fv > 0.0)) continue;  // exit node (fixed at q)
+        const double U = u[g];
+        const double s = S.h / fv;
+        const double G = local_solve(nbr_min(u, g, 1, i > 0, i + 1 < S.nx),
+                                     nbr_min(u, g, nx, j > 0, j + 1 < S.ny),
+                                     nbr_min(u, g, nx * ny, k > 0, k + 1 < S.nz), s);
+        if (U == __builtin_inf() && G == __builtin_inf()) continue;  // unreachable
+        const double thr = 1e-11 * s + 0x1p-46 * U;
+        bad |= !(fabs(G - U) <= thr);  // NaN and a finite G at an unreached node fail too
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0 && atomicExch(redo, 1) == 0)
+        atomicAdd(&stats[ST_REDONE], 1ull);
+}
+
+__global__ void k_clear_int(int* p, int n) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) p[g] = 0;
+}
+
+hipError_t launch_polish_check(const Slot& S, int cell, int f_dtype, const double* u_out,
+                               int* redo, unsigned long long* stats, hipStream_t s) {
+    const int threads = 256;
+    const int ob = blocks_for((size_t)S.nx * S.ny * S.nz, threads);
+#define EIK_CHECK_LAUNCH(R, FT) \
+    hipLaunchKernelGGL((k_polish_check<R, FT>), dim3(ob), dim3(threads), 0, s, S, u_out, redo, stats)
+    if (cell == 16) {
+        if (f_dtype == EIK_F32) EIK_CHECK_LAUNCH(16, float); else EIK_CHECK_LAUNCH(16, double);
+    } else if (cell == 8) {
+        if (f_dtype == EIK_F32) EIK_CHECK_LAUNCH(8, float); else EIK_CHECK_LAUNCH(8, double);
+    } else {
+        if (f_dtype == EIK_F32) EIK_CHECK_LAUNCH(4, float); else EIK_CHECK_LAUNCH(4, double);
+    }
+#undef EIK_CHECK_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_ints(int* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_int, dim3(blocks_for((size_t)n, 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

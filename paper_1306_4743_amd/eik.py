@@ -6,8 +6,10 @@ computes values itself and has no CPU fallback: if the library is missing it rai
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -19,7 +21,8 @@ EIK_EBUSY = -6
 EIK_F64, EIK_F32 = 0, 1
 EIK_MODE_FP64, EIK_MODE_FP32, EIK_MODE_MIXED = 0, 1, 2
 EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL = 1, 2, 3
-EIK_CELL_VALUE_EQ5, EIK_CELL_VALUE_EQ9 = 0, 1
+EIK_CELL_VALUE_NEW, EIK_CELL_VALUE_OLD = 0, 1
+EIK_SCHED_AUTO, EIK_SCHED_COOPERATIVE, EIK_SCHED_HOST_LOOP = 0, 1, 2
 
 
 class EikError(RuntimeError):
@@ -38,7 +41,7 @@ class Options(ctypes.Structure):
                 ("max_rounds", ctypes.c_int64), ("max_sweeps", ctypes.c_int),
                 ("workers", ctypes.c_int), ("shuffle", ctypes.c_uint64), ("timing", ctypes.c_int),
                 ("round_log", ctypes.c_void_p), ("round_log_len", ctypes.c_int64),
-                ("inner", ctypes.c_int), ("cell_value", ctypes.c_int)]
+                ("inner", ctypes.c_int), ("cell_value", ctypes.c_int), ("schedule", ctypes.c_int)]
 
 
 class Problem(ctypes.Structure):
@@ -60,7 +63,8 @@ class Stats(ctypes.Structure):
                 ("rounds", "visits", "sweeps", "updates", "deferred", "requeued", "cells",
                  "status", "workers", "cycles_pop", "cycles_stage", "cycles_sweep",
                  "cycles_write", "cycles_wait")] + [
-                ("sweep_hist", ctypes.c_int64 * 32), ("visit_cycles_log2_hist", ctypes.c_int64 * 32)]
+                ("sweep_hist", ctypes.c_int64 * 32), ("visit_cycles_log2_hist", ctypes.c_int64 * 32),
+                ("polish_redone", ctypes.c_int64)]
 
     def as_dict(self):
         d = {n: int(getattr(self, n)) for n, t in self._fields_ if t is ctypes.c_int64}
@@ -75,8 +79,8 @@ _lib = None
 EXPORTS = ("eik_solve", "eik_solve_ex", "eik_query_workspace", "eik_problem_bytes",
            "eik_stream_status", "eik_kernel_times", "eik_solve_batch", "eik_batch_status",
            "eik_server_create", "eik_server_submit", "eik_server_step", "eik_server_poll",
-           "eik_server_load", "eik_server_destroy", "eik_autotune", "eik_strerror",
-           "eik_release", "eik_version")
+           "eik_server_load", "eik_server_destroy", "eik_server_polish_redone", "eik_autotune",
+           "eik_strerror", "eik_release", "eik_version")
 
 
 def load():
@@ -131,8 +135,31 @@ def load():
     lib.eik_autotune.restype = i32
     lib.eik_server_destroy.argtypes = [vp]
     lib.eik_server_destroy.restype = i32
+    lib.eik_server_polish_redone.argtypes = [vp]
+    lib.eik_server_polish_redone.restype = i64
     _lib = lib
+    atexit.register(_shutdown)
     return lib
+
+
+# Servers not yet closed; at interpreter exit they are closed and every workspace released
+# while the HIP runtime is still fully up, so that no library state (device memory, pinned
+# buffers, events) outlives the process's own teardown.
+_live_servers = weakref.WeakSet()
+
+
+def _shutdown():
+    if _lib is None:
+        return
+    for s in list(_live_servers):
+        try:
+            s.close()
+        except Exception:
+            pass
+    try:
+        _lib.eik_release()
+    except Exception:
+        pass
 
 
 def strerror(code: int) -> str:
@@ -215,7 +242,8 @@ def _sources(F, idx3, q, stream):
 
 
 def _options(delta=0.0, max_rounds=0, max_sweeps=0, workers=0, shuffle=0, timing=False,
-             round_log=None, inner=0, mode=EIK_MODE_FP64, cell_value=EIK_CELL_VALUE_EQ5):
+             round_log=None, inner=0, mode=EIK_MODE_FP64, cell_value=EIK_CELL_VALUE_NEW,
+             schedule=EIK_SCHED_AUTO):
     rl_ptr, rl_len = None, 0
     if round_log is not None:
         import torch
@@ -224,7 +252,7 @@ def _options(delta=0.0, max_rounds=0, max_sweeps=0, workers=0, shuffle=0, timing
         rl_ptr, rl_len = round_log.data_ptr(), round_log.numel() // 2
     return Options(int(mode), float(delta), int(max_rounds), int(max_sweeps), int(workers),
                    int(shuffle), int(bool(timing)), rl_ptr, rl_len, int(inner),
-                   int(cell_value))
+                   int(cell_value), int(schedule))
 
 
 def _approx(F, u_approx):
@@ -252,8 +280,8 @@ def _problem(F, h, idx3, q, tol, u_out, stream, u_approx=None):
 def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, stream=None,
           delta: float = 0.0, max_rounds: int = 0, max_sweeps: int = 0, workers: int = 0,
           shuffle: int = 0, timing: bool = False, round_log=None, inner: int = 0,
-          mode: int = EIK_MODE_FP64, cell_value: int = EIK_CELL_VALUE_EQ5,
-          check: bool = True, u_approx=None):
+          mode: int = EIK_MODE_FP64, cell_value: int = EIK_CELL_VALUE_NEW,
+          check: bool = True, u_approx=None, schedule: int = EIK_SCHED_AUTO):
     """Enqueue one solve of eq. (2) on ``stream`` (torch stream; default: current stream).
 
     F: torch CUDA tensor [nz, ny, nx] of float32 or float64 speeds (contiguous).
@@ -269,14 +297,14 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
                                  u_approx=u_approx)], cell=cell, stream=stream, check=check,
                            delta=delta, max_rounds=max_rounds, max_sweeps=max_sweeps,
                            workers=workers, shuffle=shuffle, timing=timing, round_log=round_log,
-                           inner=inner, mode=mode, cell_value=cell_value)
+                           inner=inner, mode=mode, cell_value=cell_value, schedule=schedule)
         return outs[0]
     lib = load()
     f_dtype = _f_dtype(F)
     u_out = _out_tensor(F, u_out)
     src, keep = _sources(F, idx3, q, stream)
     opts = _options(delta, max_rounds, max_sweeps, workers, shuffle, timing, round_log, inner,
-                    mode, cell_value)
+                    mode, cell_value, schedule)
     nz, ny, nx = F.shape
     dims = _dims_array((nx, ny, nz))
     rc = lib.eik_solve_ex(ctypes.cast(dims, ctypes.c_void_p), float(h),
@@ -381,6 +409,7 @@ class Server:
             raise EikError(rc, "eik_server_create: ")
         self._pending = {}   # ticket -> (u_out, keep-alive)
         self._staged = []    # keep-alive of problems whose inputs the next step reads
+        _live_servers.add(self)
 
     def submit(self, F, h, idx3, q, tol=0.0, u_out=None, u_approx=None):
         pb, u, keep = _problem(F, h, idx3, q, tol, u_out, None, u_approx)
@@ -425,6 +454,10 @@ class Server:
         if rc != EIK_OK:
             raise EikError(rc, "eik_server_load: ")
         return {"problems": np_.value, "cells": nc.value, "pool_bytes": pb.value}
+
+    def polish_redone(self) -> int:
+        """Problems restarted from +inf after their polished result failed the eq. (2) check."""
+        return int(self._lib.eik_server_polish_redone(self._h))
 
     def close(self):
         if self._h:

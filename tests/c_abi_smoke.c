@@ -2,6 +2,7 @@
  * include/eik_probe.h, linked with libeik.so and libeik_probe.so, and run without a GPU (only
  * the host-side entry points are called: sizes, argument checks, names; the fake device
  * pointers are refused before any use). */
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -53,6 +54,7 @@ int main(void) {
     CHECK(strcmp(eik_strerror(EIK_OK), "EIK_OK") == 0);
     CHECK(strncmp(eik_version(), "eik-mi355x", 10) == 0);
     CHECK(sizeof(eik_problem) == 96);
+    CHECK(sizeof(eik_options) == 80 && offsetof(eik_options, schedule) == 72);
     printf("%s: %d failures\n", eik_version(), fails);
     return fails != 0;
 }

@@ -164,6 +164,22 @@ def test_problem_struct_layout():
     assert eik.Problem.u_approx.offset == 88 and ctypes.sizeof(eik.Problem) == 96
 
 
+def test_options_struct_layout():
+    """The binding's eik_options matches the C layout (80 bytes, schedule last at 72; the C
+    side is checked in tests/c_abi_smoke.c)."""
+    assert eik.Options.schedule.offset == 72 and ctypes.sizeof(eik.Options) == 80
+
+
+def test_schedule_option_checked():
+    lib = eik.load()
+    pb, keep = _problem()
+    arr = (eik.Problem * 1)(pb)
+    for bad in (-1, 3):
+        opts = eik._options(schedule=bad)
+        assert lib.eik_solve_batch(1, arr, eik.EIK_F32, 8, None,
+                                   ctypes.byref(opts)) == eik.EIK_EINVAL
+
+
 def test_polish_not_allowed_with_mixed_mode():
     """A problem carrying an approximation cannot use EIK_MODE_MIXED (refused before any
     device work)."""

@@ -3,10 +3,10 @@ torch in its process: eik_solve, eik_solve_ex in the mixed mode, eik_solve_batch
 It checks what eq. (2) fixes for a constant-speed point source (axis values q + d h bit for bit,
 the two- and three-term roots next to the exit, a vanishing residual everywhere).
 
-The HIP runtime grants cooperative launches to one process per device at a time: once a
-process has launched the solver, another process's launches fail (EIK_EHIP) until it exits.
-The program therefore runs before any other GPU test of the session (this file sorts first
-among them), while the test process itself has launched nothing."""
+The HIP runtime grants cooperative launches to one process per device at a time.  The test
+process solves first (so it holds the device's cooperative launch while the program runs): the
+program's solves are then refused the cooperative launch and take the host-driven round loop
+(EIK_SCHED_AUTO), and must still pass every check."""
 import os
 import shutil
 import subprocess
@@ -41,7 +41,15 @@ def test_c_caller_builds(tmp_path):
 
 @pytest.mark.gpu
 def test_c_caller_solves_on_gpu(tmp_path):
+    import numpy as np
+    import torch
+    from paper_1306_4743_amd import eik
     exe = build_c_caller(tmp_path)
+    # A solve in this process first, whatever ran before.
+    eik.load()
+    F = torch.ones((17, 17, 17), dtype=torch.float32, device="cuda:0")
+    eik.solve(F, 1 / 16, np.array([[8, 8, 8]]), np.zeros(1), cell=8)
+    assert eik.status()[0] == 0
     print(f"running {exe}", flush=True)
     out = subprocess.run([exe], capture_output=True, text=True, timeout=100)
     print(out.stdout, out.stderr, flush=True)

@@ -158,7 +158,7 @@ def test_fp32_and_mixed_modes(orc, dev, inner):
 def test_eq9_cell_values(orc, dev):
     from paper_1306_4743_amd import eik
     for p in (W.shell_maze(65), W.maze(97, seed=3)):
-        check(orc, dev, p, delta=4.0 * 16 * p.h, cell_value=eik.EIK_CELL_VALUE_EQ9)
+        check(orc, dev, p, delta=4.0 * 16 * p.h, cell_value=eik.EIK_CELL_VALUE_OLD)
 
 
 def test_batch_and_server_match_alone(orc, dev):
