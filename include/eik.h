@@ -53,6 +53,7 @@ extern "C" {
 #define EIK_ENOCONV (-4)    /* the round cap was reached before the worklist emptied         */
 #define EIK_ECANCELLED (-5) /* the solve was stopped by the device watchdog                  */
 #define EIK_EBUSY (-6)      /* a server has no room for the problem now (retry after a step)  */
+#define EIK_ETOOBIG (-7)    /* eik_solve_noalloc: the workspace exceeds its static scratch    */
 
 /* Element types of F. */
 #define EIK_F64 0
@@ -211,6 +212,34 @@ int eik_solve(const int64_t dims[3], double h, const void* F, int f_dtype,
 int eik_solve_ex(const int64_t dims[3], double h, const void* F, int f_dtype,
                  const eik_sources* sources, double* u_out, int cell, double tol,
                  hipStream_t stream, const eik_options* options);
+
+/*
+ * eik_solve_noalloc -- eik_solve_ex for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same arguments, results and
+ * device-side status (eik_stream_status, eik_batch_status) as eik_solve_ex, but the call
+ * allocates nothing: no hipMalloc, hipFree, pinned or staging buffer and no events.  Its
+ * workspace is a static device array of 384 MiB (EIK_NOALLOC_SCRATCH_BYTES) that every device
+ * the library runs this entry point on holds until the process ends; the slot table and
+ * host-side exits reach the device through kernel arguments.
+ *   limits   the workspace (eik_query_workspace(dims, cell, f_dtype, mode) plus 1 KiB for
+ *            host-side exits) must fit the scratch, else EIK_ETOOBIG and nothing is enqueued:
+ *            up to 257^3 nodes at cell 8 in EIK_MODE_FP64 with FP32 speeds, 248^3 in
+ *            EIK_MODE_MIXED.  Host-side exits: at most 32 (EIK_EINVAL beyond; pass device
+ *            arrays, sources.on_device = 1, for more).  options.timing must be 0 (EIK_EINVAL).
+ *   set-up   the first call on a device (and the first after eik_release) looks up that
+ *            device's copy of the array and creates the two events that order solve kernels
+ *            on the device; later calls do no set-up.
+ *   sharing  every call on a device uses that device's one array, which keeps the last call's
+ *            contents (each call initialises what it reads).  Calls whose work overlaps on one
+ *            GPU race on the array and corrupt each other's results: serialise them (one
+ *            stream, or events).  A call that falls back to the host-driven round loop
+ *            (EIK_SCHED_AUTO with the cooperative launch refused) blocks as described there.
+ * Returns EIK_OK, EIK_EINVAL, EIK_ETOOBIG or EIK_EHIP (nothing enqueued on failure).
+ */
+#define EIK_NOALLOC_SCRATCH_BYTES ((size_t)384 << 20)
+int eik_solve_noalloc(const int64_t dims[3], double h, const void* F, int f_dtype,
+                      const eik_sources* sources, double* u_out, int cell, double tol,
+                      hipStream_t stream, const eik_options* options);
 
 /* Device bytes of the workspace one solve of this size needs (for admission control).
  * f_dtype as in eik_solve.  Returns EIK_OK or EIK_EINVAL. */

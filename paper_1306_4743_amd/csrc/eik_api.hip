@@ -8,11 +8,16 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
 
 #include "eik_internal.h"
+
+// Workspace of eik_solve_noalloc (see NoallocDevice below).
+constexpr size_t kScratchBytes = size_t(384) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -325,7 +330,7 @@ struct DeviceOrder {
     hipEvent_t ev[2] = {nullptr, nullptr};
     int next = 0;
     bool any = false;
-    uint32_t* halted_host = nullptr;  // pinned: the halted word read by the host-driven loop
+    uint32_t halted_word = 0;  // the halted word, read back by the host-driven loop
 };
 std::mutex g_mu;
 std::map<int, DeviceOrder*> g_order;
@@ -345,11 +350,6 @@ DeviceOrder* device_order(int dev) {
 int host_loop_rounds(DeviceOrder* dord, SolveParams P, int cell, int f_dtype, hipStream_t stream,
                      int workers) {
     hipError_t e;
-    if (!dord->halted_host &&
-        (e = hipHostMalloc((void**)&dord->halted_host, 64, hipHostMallocDefault)) != hipSuccess) {
-        dord->halted_host = nullptr;
-        return hip_fail(e);
-    }
     if ((e = eik::launch_halt_reset(P, stream)) != hipSuccess) return hip_fail(e);
     const int64_t begin = P.round_begin, end = P.round_end;
     P.single_round = 1;
@@ -365,11 +365,11 @@ int host_loop_rounds(DeviceOrder* dord, SolveParams P, int cell, int f_dtype, hi
                 hipSuccess)
                 return hip_fail(e);
         }
-        if ((e = hipMemcpyAsync(dord->halted_host, P.halted, sizeof(uint32_t),
+        if ((e = hipMemcpyAsync(&dord->halted_word, P.halted, sizeof(uint32_t),
                                 hipMemcpyDeviceToHost, stream)) != hipSuccess ||
             (e = hipStreamSynchronize(stream)) != hipSuccess)
             return hip_fail(e);
-        if (*dord->halted_host) break;
+        if (dord->halted_word) break;
         batch = std::min(2 * batch, 64);
     }
     if ((e = eik::launch_hostloop_end(P, end, stream)) != hipSuccess) return hip_fail(e);
@@ -430,7 +430,12 @@ struct Workspace {
     static constexpr int kRing = 256;
     std::vector<hipEvent_t> ring;  // 4 events per timed solve
     int64_t timed = 0;
+    int64_t seq = 0;  // order of the last solve enqueued with this workspace (see g_seq)
 };
+
+// Sequence number of solves enqueued by the process: tells which of a stream's workspace solve
+// and allocation-free solve came last.
+std::atomic<int64_t> g_seq{0};
 
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
@@ -634,10 +639,92 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
     rc = enqueue_solve(w->device, n, pbs, f_dtype, cell, opt, P, slots.data(), refs.data(), base,
                        L, nsrc_total, ev, stream);
     if (rc != EIK_OK) return rc;
+    w->seq = ++g_seq;
     w->used = true;
     w->cells = cells;
     w->nslots = n;
     w->layout = L;
+    return EIK_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Allocation-free solves (eik_solve_noalloc): the whole workspace of one solve lives in a static
+// device array.  Each device that runs one holds its own copy of the array until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name in host code is a host-side stand-in).
+
+constexpr int kMaxDevices = 64;
+
+struct NoallocDevice {
+    bool ready = false;
+    unsigned char* ptr = nullptr;  // this device's copy of the scratch array
+    std::mutex mu;                 // serialises the enqueues of allocation-free solves
+    // the last allocation-free solve enqueued on the device (for eik_stream_status)
+    hipStream_t stream = nullptr;
+    bool used = false;
+    int64_t seq = 0, cells = 0;
+    CommonLayout layout;
+};
+std::mutex g_noalloc_mu;
+NoallocDevice g_noalloc[kMaxDevices];
+
+// Where the last solve enqueued on a stream keeps its status and counters: the stream's
+// workspace, or this device's scratch if an allocation-free solve on that stream came later.
+struct LastSolve {
+    unsigned char* base = nullptr;
+    CommonLayout layout;
+    int nslots = 0;
+    int64_t cells = 0;
+};
+
+bool last_solve(hipStream_t stream, LastSolve* out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    Workspace* w = find_workspace(stream);
+    int64_t wseq = -1;
+    if (w) {
+        std::lock_guard<std::mutex> lk(w->mu);
+        if (w->used) {
+            wseq = w->seq;
+            out->base = (unsigned char*)w->base;
+            out->layout = w->layout;
+            out->nslots = w->nslots;
+            out->cells = w->cells;
+        }
+    }
+    if (dev >= 0 && dev < kMaxDevices) {
+        NoallocDevice& d = g_noalloc[dev];
+        std::lock_guard<std::mutex> lk(d.mu);
+        if (d.ready && d.used && d.stream == stream && d.seq > wseq) {
+            out->base = d.ptr;
+            out->layout = d.layout;
+            out->nslots = 1;
+            out->cells = d.cells;
+            return true;
+        }
+    }
+    return wseq >= 0;
+}
+
+// One-time set-up of allocation-free solves on device `dev` (current): the address of this
+// device's scratch array, and the events that order solve kernels on the device.
+int noalloc_setup(int dev, NoallocDevice** out) {
+    if (dev < 0 || dev >= kMaxDevices) return EIK_EINVAL;
+    NoallocDevice& d = g_noalloc[dev];
+    DeviceOrder* o = device_order(dev);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!d.ready) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return e != hipSuccess ? hip_fail(e) : EIK_EHIP;
+        std::lock_guard<std::mutex> lo(o->mu);
+        for (auto& ev : o->ev)
+            if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e);
+        d.ptr = (unsigned char*)p;
+        d.ready = true;
+    }
+    *out = &d;
     return EIK_OK;
 }
 
@@ -725,6 +812,9 @@ const char* eik_strerror(int code) {
         case EIK_ENOCONV: return "EIK_ENOCONV: round cap reached before convergence";
         case EIK_ECANCELLED: return "EIK_ECANCELLED: stopped by the device watchdog";
         case EIK_EBUSY: return "EIK_EBUSY: no room on the device now";
+        case EIK_ETOOBIG:
+            return "EIK_ETOOBIG: the problem's workspace exceeds the 384 MiB static scratch of "
+                   "eik_solve_noalloc";
         default: return "EIK: unknown status";
     }
 }
@@ -776,6 +866,68 @@ int eik_solve(const int64_t dims[3], double h, const void* F, int f_dtype,
 int eik_solve_batch(int n, const eik_problem* problems, int f_dtype, int cell, hipStream_t stream,
                     const eik_options* options) {
     return solve_batch_impl(n, problems, f_dtype, cell, stream, options);
+}
+
+int eik_solve_noalloc(const int64_t dims[3], double h, const void* F, int f_dtype,
+                      const eik_sources* sources, double* u_out, int cell, double tol,
+                      hipStream_t stream, const eik_options* options) {
+    if (!dims || !sources || !valid_cell(cell)) return EIK_EINVAL;
+    eik_problem pb;
+    std::memset(&pb, 0, sizeof(pb));
+    for (int a = 0; a < 3; ++a) pb.dims[a] = dims[a];
+    pb.h = h;
+    pb.F = F;
+    pb.sources = *sources;
+    pb.u_out = u_out;
+    pb.tol = tol;
+    eik_options opt;
+    SolveParams P;
+    int rc = parse_options(options, cell, &opt, &P);
+    if (rc != EIK_OK) return rc;
+    if (opt.timing) return EIK_EINVAL;  // timing would create events
+    if ((rc = validate_problem(pb, f_dtype)) != EIK_OK) return rc;
+    if (!sources->on_device && sources->n > eik::kHostExitsMax) return EIK_EINVAL;
+    GridSize g;
+    if (!grid_size(dims, cell, f_dtype, opt.mode, &g)) return EIK_EINVAL;
+    const bool mixed = opt.mode == EIK_MODE_MIXED;
+    const int ntab = mixed ? 2 : 1;
+    const CommonLayout L = common_layout(g.ncell, ntab);
+    const size_t exits_off = L.total + g.bytes();
+    const size_t need = exits_off + (sources->on_device ? 0 : align_up(eik::kHostExitsMax * 32));
+    if (need > kScratchBytes) return EIK_ETOOBIG;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    NoallocDevice* d = nullptr;
+    if ((rc = noalloc_setup(dev, &d)) != EIK_OK) return rc;
+    std::lock_guard<std::mutex> lk(d->mu);
+    unsigned char* base = d->ptr;
+    bind_common(&P, base, L, g.ncell);
+    int* slot_status = (int*)(base + L.off_slot_status);
+    Slot slots[2];
+    slots[0] = make_slot(pb, g, 0, base + L.total, slot_status, P.fp32);
+    slots[1] = mixed ? fp32_twin(slots[0], g) : slots[0];
+    if ((e = eik::launch_put_slots(slots[0], slots[1], ntab, (Slot*)(base + L.off_slots),
+                                   stream)) != hipSuccess)
+        return hip_fail(e);
+    SourceRefs ref{sources->idx3, sources->q};
+    if (!sources->on_device && sources->n > 0) {
+        int64_t* di = (int64_t*)(base + exits_off);
+        double* dq = (double*)(base + exits_off + eik::kHostExitsMax * 24);
+        if ((e = eik::launch_put_exits(sources->idx3, sources->q, (int)sources->n, di, dq,
+                                       stream)) != hipSuccess)
+            return hip_fail(e);
+        ref = SourceRefs{di, dq};
+    }
+    rc = enqueue_solve(dev, 1, &pb, f_dtype, cell, opt, P, slots, &ref, base, L, sources->n,
+                       nullptr, stream);
+    if (rc != EIK_OK) return rc;
+    d->stream = stream;
+    d->used = true;
+    d->cells = g.ncell;
+    d->layout = L;
+    d->seq = ++g_seq;
+    return EIK_OK;
 }
 
 int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
@@ -870,22 +1022,22 @@ int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
 }
 
 int eik_stream_status(hipStream_t stream, eik_stats* stats) {
-    Workspace* w = find_workspace(stream);
-    if (!w || !w->used) return EIK_EINVAL;
+    LastSolve ls;
+    if (!last_solve(stream, &ls)) return EIK_EINVAL;
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e);
-    unsigned char* base = (unsigned char*)w->base;
+    unsigned char* base = ls.base;
     int status = 0;
     unsigned long long st[eik::ST_TOTAL];
-    e = hipMemcpy(&status, base + w->layout.off_small + kSmallStatus, sizeof(int),
+    e = hipMemcpy(&status, base + ls.layout.off_small + kSmallStatus, sizeof(int),
                   hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e);
-    e = hipMemcpy(st, base + w->layout.off_small + kSmallStats, sizeof(st), hipMemcpyDeviceToHost);
+    e = hipMemcpy(st, base + ls.layout.off_small + kSmallStats, sizeof(st), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e);
     if (status == 0) {
         // otherwise the first failing grid's status
-        std::vector<int> ss((size_t)w->nslots);
-        e = hipMemcpy(ss.data(), base + w->layout.off_slot_status, ss.size() * sizeof(int),
+        std::vector<int> ss((size_t)ls.nslots);
+        e = hipMemcpy(ss.data(), base + ls.layout.off_slot_status, ss.size() * sizeof(int),
                       hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e);
         for (int v : ss)
@@ -898,7 +1050,7 @@ int eik_stream_status(hipStream_t stream, eik_stats* stats) {
         stats->updates = (int64_t)st[eik::ST_UPDATES];
         stats->deferred = (int64_t)st[eik::ST_DEFERRED];
         stats->requeued = (int64_t)st[eik::ST_REQUEUED];
-        stats->cells = w->cells;
+        stats->cells = ls.cells;
         stats->status = status;
         stats->workers = (int64_t)st[eik::ST_WORKERS];
         stats->cycles_pop = (int64_t)st[eik::ST_CYC_POP];
@@ -916,17 +1068,17 @@ int eik_stream_status(hipStream_t stream, eik_stats* stats) {
 }
 
 int eik_batch_status(hipStream_t stream, int n, int* status) {
-    Workspace* w = find_workspace(stream);
-    if (!w || !w->used || n < 0 || (n > 0 && !status)) return EIK_EINVAL;
+    LastSolve ls;
+    if (!last_solve(stream, &ls) || n < 0 || (n > 0 && !status)) return EIK_EINVAL;
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e);
     int launch = 0;
-    unsigned char* base = (unsigned char*)w->base;
-    e = hipMemcpy(&launch, base + w->layout.off_small + kSmallStatus, sizeof(int),
+    unsigned char* base = ls.base;
+    e = hipMemcpy(&launch, base + ls.layout.off_small + kSmallStatus, sizeof(int),
                   hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e);
-    n = std::min(n, w->nslots);
-    e = hipMemcpy(status, base + w->layout.off_slot_status, (size_t)n * sizeof(int),
+    n = std::min(n, ls.nslots);
+    e = hipMemcpy(status, base + ls.layout.off_slot_status, (size_t)n * sizeof(int),
                   hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e);
     for (int i = 0; i < n; ++i)
@@ -956,6 +1108,16 @@ int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_
 }
 
 void eik_release(void) {
+    // Allocation-free solves run their set-up again after this (their ordering events are
+    // freed below); the scratch arrays themselves stay until the process ends.
+    {
+        std::lock_guard<std::mutex> ln(g_noalloc_mu);
+        for (auto& d : g_noalloc) {
+            std::lock_guard<std::mutex> ld(d.mu);
+            d.ready = false;
+            d.used = false;
+        }
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);
@@ -984,7 +1146,6 @@ void eik_release(void) {
         (void)hipSetDevice(kv.first);
         for (auto& ev : d->ev)
             if (ev) (void)hipEventDestroy(ev);
-        if (d->halted_host) (void)hipHostFree(d->halted_host);
         delete d;
     }
     g_order.clear();

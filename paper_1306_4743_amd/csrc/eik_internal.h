@@ -104,7 +104,16 @@ struct SolveParams {
     int64_t round_log_len;
 };
 
+// Host-side exits that a kernel argument can carry (the allocation-free solve).
+constexpr int kHostExitsMax = 32;
+
 // Launchers (eik_kernels.hip).  All enqueue on `s` and return the first launch error.
+// Slot table entries dst[0..n) <- a, b written by a kernel from its arguments (n = 1 or 2).
+hipError_t launch_put_slots(const Slot& a, const Slot& b, int n, Slot* dst, hipStream_t s);
+// n <= kHostExitsMax host-side exits (idx3: n x 3, q: n) copied to device arrays through a
+// kernel's arguments.
+hipError_t launch_put_exits(const int64_t* idx3, const double* q, int n, int64_t* idx3_dst,
+                            double* q_dst, hipStream_t s);
 hipError_t launch_init_global(const SolveParams& P, hipStream_t s);
 // Cells of slot S cleared, speeds staged, values <- +inf or, if u_approx (row-major, device) is
 // given, <- |u_approx| * lift with face copies to match.

@@ -1706,6 +1706,43 @@ hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipS
     return hipErrorInvalidValue;
 }
 
+__global__ void k_put_slots(Slot a, Slot b, int n, Slot* dst) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        dst[0] = a;
+        if (n > 1) dst[1] = b;
+    }
+}
+
+struct HostExits {
+    int64_t idx3[3 * kHostExitsMax];
+    double q[kHostExitsMax];
+};
+
+__global__ void k_put_exits(HostExits x, int n, int64_t* idx3, double* q) {
+    const int t = threadIdx.x;
+    if (blockIdx.x != 0 || t >= n) return;
+    idx3[3 * t] = x.idx3[3 * t];
+    idx3[3 * t + 1] = x.idx3[3 * t + 1];
+    idx3[3 * t + 2] = x.idx3[3 * t + 2];
+    q[t] = x.q[t];
+}
+
+hipError_t launch_put_slots(const Slot& a, const Slot& b, int n, Slot* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_put_slots, dim3(1), dim3(64), 0, s, a, b, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_put_exits(const int64_t* idx3, const double* q, int n, int64_t* idx3_dst,
+                            double* q_dst, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n > kHostExitsMax) return hipErrorInvalidValue;
+    HostExits x;
+    for (int t = 0; t < 3 * n; ++t) x.idx3[t] = idx3[t];
+    for (int t = 0; t < n; ++t) x.q[t] = q[t];
+    hipLaunchKernelGGL(k_put_exits, dim3(1), dim3(64), 0, s, x, n, idx3_dst, q_dst);
+    return hipGetLastError();
+}
+
 __global__ void k_halt_reset(SolveParams P) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *P.halted = 0u;
 }

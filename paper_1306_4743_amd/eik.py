@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libeik.so")
 
 EIK_OK, EIK_EINVAL, EIK_ENOMEM, EIK_EHIP, EIK_ENOCONV, EIK_ECANCELLED = 0, -1, -2, -3, -4, -5
 EIK_EBUSY = -6
+EIK_ETOOBIG = -7
 EIK_F64, EIK_F32 = 0, 1
 EIK_MODE_FP64, EIK_MODE_FP32, EIK_MODE_MIXED = 0, 1, 2
 EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL = 1, 2, 3
@@ -76,7 +77,7 @@ class Stats(ctypes.Structure):
 _lib = None
 
 # Every symbol declared in include/eik.h.
-EXPORTS = ("eik_solve", "eik_solve_ex", "eik_query_workspace", "eik_problem_bytes",
+EXPORTS = ("eik_solve", "eik_solve_ex", "eik_solve_noalloc", "eik_query_workspace", "eik_problem_bytes",
            "eik_stream_status", "eik_kernel_times", "eik_solve_batch", "eik_batch_status",
            "eik_server_create", "eik_server_submit", "eik_server_step", "eik_server_poll",
            "eik_server_load", "eik_server_destroy", "eik_server_polish_redone", "eik_autotune",
@@ -98,6 +99,9 @@ def load():
     lib.eik_solve_ex.argtypes = [vp, dbl, vp, i32, ctypes.POINTER(Sources), vp, i32, dbl, vp,
                                  ctypes.POINTER(Options)]
     lib.eik_solve_ex.restype = i32
+    lib.eik_solve_noalloc.argtypes = [vp, dbl, vp, i32, ctypes.POINTER(Sources), vp, i32, dbl,
+                                      vp, ctypes.POINTER(Options)]
+    lib.eik_solve_noalloc.restype = i32
     lib.eik_query_workspace.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.eik_query_workspace.restype = i32
     lib.eik_stream_status.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -315,6 +319,31 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
     if rc != EIK_OK and check:
         raise EikError(rc, "eik_solve: ")
     return u_out
+
+
+def solve_noalloc(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None,
+                  stream=None, check: bool = True, **opt):
+    """Enqueue one solve through eik_solve_noalloc (the entry point that allocates nothing; its
+    workspace is the library's static device scratch).  Arguments as in ``solve``; u_out must be
+    given (the library allocates nothing, and neither does this wrapper).  Returns the C status
+    (raises on a negative one if ``check``)."""
+    lib = load()
+    f_dtype = _f_dtype(F)
+    if u_out is None:
+        raise ValueError("u_out is required: eik_solve_noalloc allocates nothing")
+    u_out = _out_tensor(F, u_out)
+    src, keep = _sources(F, idx3, q, stream)
+    opts = _options(**opt)
+    nz, ny, nx = F.shape
+    dims = _dims_array((nx, ny, nz))
+    rc = lib.eik_solve_noalloc(ctypes.cast(dims, ctypes.c_void_p), float(h),
+                               ctypes.c_void_p(F.data_ptr()), f_dtype, ctypes.byref(src),
+                               ctypes.c_void_p(u_out.data_ptr()), int(cell), float(tol),
+                               _stream_handle(stream), ctypes.byref(opts))
+    del keep
+    if rc != EIK_OK and check:
+        raise EikError(rc, "eik_solve_noalloc: ")
+    return rc
 
 
 def autotune(F, h: float, idx3, q, tol: float = 0.0, reps: int = 2, u_out=None, stream=None):

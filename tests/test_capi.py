@@ -349,3 +349,30 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     F = torch.ones((4, 4, 4), dtype=torch.float64)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         eik.solve(F, 0.25, np.zeros((1, 3), np.int64), np.zeros(1), cell=8)
+
+
+def test_noalloc_limits_checked_on_the_host():
+    """eik_solve_noalloc refuses, before any device call, a problem whose workspace exceeds the
+    static scratch (EIK_ETOOBIG), more host-side exits than a kernel argument carries, and
+    timing (which would create events)."""
+    lib = eik.load()
+    idx = np.array([[1, 2, 3]], dtype=np.int64)
+    q = np.zeros(1)
+    src = eik.Sources(1, idx.ctypes.data, q.ctypes.data, 0)
+    dims = (ctypes.c_int64 * 3)(300, 300, 300)
+    opts = eik._options()
+    assert lib.eik_solve_noalloc(ctypes.cast(dims, ctypes.c_void_p), 1 / 299, ctypes.c_void_p(16),
+                                 eik.EIK_F32, ctypes.byref(src), ctypes.c_void_p(16), 8, 0.0, None,
+                                 ctypes.byref(opts)) == eik.EIK_ETOOBIG
+    dims = (ctypes.c_int64 * 3)(40, 40, 40)
+    many = np.array([[i, i, i] for i in range(33)], dtype=np.int64)
+    qs = np.zeros(33)
+    src33 = eik.Sources(33, many.ctypes.data, qs.ctypes.data, 0)
+    assert lib.eik_solve_noalloc(ctypes.cast(dims, ctypes.c_void_p), 1 / 39, ctypes.c_void_p(16),
+                                 eik.EIK_F32, ctypes.byref(src33), ctypes.c_void_p(16), 8, 0.0,
+                                 None, ctypes.byref(opts)) == eik.EIK_EINVAL
+    timed = eik._options(timing=True)
+    assert lib.eik_solve_noalloc(ctypes.cast(dims, ctypes.c_void_p), 1 / 39, ctypes.c_void_p(16),
+                                 eik.EIK_F32, ctypes.byref(src), ctypes.c_void_p(16), 8, 0.0, None,
+                                 ctypes.byref(timed)) == eik.EIK_EINVAL
+    assert "384 MiB" in eik.strerror(eik.EIK_ETOOBIG)
