@@ -210,6 +210,9 @@ def main():
     ap.add_argument("--delta", type=float, default=0.0)
     ap.add_argument("--inner", type=int, default=0,
                     help="in-cell solver: 0 default, 1 sweeps, 2 active-list, 3 dual sweeps")
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="0 auto (rounds in one cooperative launch), 1 cooperative, "
+                         "2 host-driven rounds, 3 no rounds (ring of queued cells)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests of the mixed-size serving stream (0: skip the serving leg)")
@@ -251,7 +254,7 @@ def main():
 
     def solve(timing=False):
         eik.solve(F, p.h, p.src, p.q, cell=args.cell, tol=p.tol, u_out=u, delta=args.delta,
-                  timing=timing, inner=args.inner)
+                  timing=timing, inner=args.inner, schedule=args.schedule)
 
     for _ in range(args.warmup):
         solve()
@@ -300,7 +303,8 @@ def main():
         "config": {"workload": p.meta["workload"], "grid": list(p.dims), "h": p.h,
                    "cell": args.cell, "tol": p.tol, "sources": int(len(p.src)),
                    "f_dtype": str(p.F.dtype), "delta": args.delta or "inf",
-                   "inner": args.inner or "default"},
+                   "inner": args.inner or "default",
+                   "schedule": ["auto", "cooperative", "host loop", "no rounds"][args.schedule]},
         "grid_node_updates_per_s": upd_per_s,
         "visits_per_cell": visits / st["cells"],
         "sweeps_per_visit": st["sweeps"] / max(visits, 1),

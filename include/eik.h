@@ -106,6 +106,20 @@ extern "C" {
 #define EIK_SCHED_AUTO 0
 #define EIK_SCHED_COOPERATIVE 1
 #define EIK_SCHED_HOST_LOOP 2
+/*   EIK_SCHED_ASYNC        no rounds (the pHCM main loop of Section 5 without per-thread heaps):
+ *                          one cooperative launch in which every wave pops a queued cell from
+ *                          a device ring, visits it and pushes the neighbours it tags, with no
+ *                          barrier between visits.  With delta = 0 cells are taken in the
+ *                          order they were queued; with delta > 0 they are kept in 64 buckets
+ *                          of cell values of width delta (the heap of Algorithm 1 coarsened to
+ *                          buckets) and each wave takes a cell of the lowest non-empty bucket
+ *                          (the workspace then holds 64 rings of cells + 16384 8-byte entries).
+ *                          When nothing is queued or being visited
+ *                          the launch checks every cell against eq. (2) and re-queues any cell
+ *                          with a node above its local solve, so the result is the same fixed
+ *                          point.  Single solves and batches (EIK_EINVAL for a server); falls
+ *                          back to EIK_SCHED_HOST_LOOP if the cooperative launch is refused. */
+#define EIK_SCHED_ASYNC 3
 
 /* In-cell solvers (eik_options.inner).  All solve the cell sub-problem of Section 4 exactly:
  *   EIK_INNER_SWEEP  locking sweeps (Algorithm 2) in the 8 directions, each sweep visiting the

@@ -86,11 +86,13 @@ bool grid_size(const int64_t dims[3], int cell, int f_dtype, int mode, GridSize*
 struct CommonLayout {
     size_t off_small = 0, off_slots = 0, off_slot_status = 0, off_counts = 0, off_redo = 0,
            off_key = 0, off_flags = 0, off_list = 0, off_cell_slot = 0, off_keep = 0,
-           off_slot_minkey = 0, total = 0;
+           off_slot_minkey = 0, off_bq = 0, total = 0;
     int nslots = 1;
+    int64_t bq_cap = 0;  // entries per bucket ring (0: no buckets)
 };
 
-CommonLayout common_layout(int64_t cells, int slots) {
+// buckets: room for the bucketed rings of the solve without rounds with a band.
+CommonLayout common_layout(int64_t cells, int slots, bool buckets = false) {
     CommonLayout L;
     size_t o = 0;
     const size_t n = (size_t)std::max<int64_t>(cells, 1), ns = (size_t)std::max(slots, 1);
@@ -101,10 +103,15 @@ CommonLayout common_layout(int64_t cells, int slots) {
     L.off_redo = o; o = align_up(o + ns * sizeof(int));
     L.off_key = o; o = align_up(o + 2 * n * 8);
     L.off_flags = o; o = align_up(o + 2 * n * 4);
-    L.off_list = o; o = align_up(o + 2 * n * 4);
+    L.off_list = o; o = align_up(o + (2 * n + (size_t)eik::kRingExtra) * 4);
     L.off_cell_slot = o; o = align_up(o + n * 4);
     L.off_keep = o; o = align_up(o + n * 8);
     L.off_slot_minkey = o; o = align_up(o + 4 * ns * 8);
+    if (buckets) {
+        L.bq_cap = (int64_t)n + eik::kRingExtra;
+        L.off_bq = o;
+        o = align_up(o + eik::kBucketCtlBytes + (size_t)eik::kBuckets * (size_t)L.bq_cap * 8);
+    }
     L.nslots = (int)ns;
     L.total = o;
     return L;
@@ -127,6 +134,14 @@ void bind_common(SolveParams* P, unsigned char* base, const CommonLayout& L, int
     P->stats = (unsigned long long*)(base + L.off_small + kSmallStats);
     P->next_round = (int64_t*)(base + L.off_small + kSmallNextRound);
     P->halted = (uint32_t*)(base + L.off_small + eik::kSmallHalted);
+    P->ncells = cells;
+    P->async_head = (unsigned long long*)(base + L.off_small + eik::kSmallAsyncHead);
+    P->async_tail = (unsigned long long*)(base + L.off_small + eik::kSmallAsyncTail);
+    P->async_pending = (unsigned long long*)(base + L.off_small + eik::kSmallAsyncPending);
+    P->async_done = (uint32_t*)(base + L.off_small + eik::kSmallAsyncDone);
+    P->bq_ctl = L.bq_cap ? (unsigned long long*)(base + L.off_bq) : nullptr;
+    P->bq_ring = L.bq_cap ? (int32_t*)(base + L.off_bq + eik::kBucketCtlBytes) : nullptr;
+    P->bq_cap = L.bq_cap;
     P->slot_minkey = (uint64_t*)(base + L.off_slot_minkey);
     P->nslots = L.nslots;
 }
@@ -143,7 +158,7 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
     if (opt->inner < 0 || opt->inner > EIK_INNER_DUAL) return EIK_EINVAL;
     if (opt->cell_value != EIK_CELL_VALUE_NEW && opt->cell_value != EIK_CELL_VALUE_OLD)
         return EIK_EINVAL;
-    if (opt->schedule < EIK_SCHED_AUTO || opt->schedule > EIK_SCHED_HOST_LOOP) return EIK_EINVAL;
+    if (opt->schedule < EIK_SCHED_AUTO || opt->schedule > EIK_SCHED_ASYNC) return EIK_EINVAL;
     std::memset(P, 0, sizeof(*P));
     P->max_rounds = opt->max_rounds > 0 ? opt->max_rounds : (int64_t(1) << 20);
     // default in-cell solver: sweeps at r = 8 and 16, the list relaxation at r = 4 (measured
@@ -394,7 +409,15 @@ int ordered_solve(int dev, const SolveParams& P, int cell, int f_dtype, hipStrea
     if (dord->any && (e = hipStreamWaitEvent(stream, dord->ev[dord->next ^ 1], 0)) != hipSuccess)
         return hip_fail(e);
     bool done = false;
-    if (schedule != EIK_SCHED_HOST_LOOP) {
+    if (schedule == EIK_SCHED_ASYNC) {
+        SolveParams Pc = P;
+        Pc.single_round = 0;
+        Pc.count_workers = 1;
+        int used = 0;
+        e = eik::launch_solve_async(Pc, cell, f_dtype, stream, workers, &used);
+        if (e == hipSuccess) done = true;
+        else (void)hipGetLastError();  // refused: the host-driven loop below
+    } else if (schedule != EIK_SCHED_HOST_LOOP) {
         SolveParams Pc = P;
         Pc.single_round = 0;
         Pc.count_workers = 1;
@@ -595,7 +618,8 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
     for (int i = 0; i < n; ++i) polish = polish || start_values(pbs[i]) != nullptr;
     if (polish && mixed) return EIK_EINVAL;
     const int ntab = mixed ? 2 * n : n;  // slot table entries (FP64 slots, then FP32 twins)
-    const CommonLayout L = common_layout(cells, ntab);
+    const CommonLayout L =
+        common_layout(cells, ntab, opt.schedule == EIK_SCHED_ASYNC && opt.delta > 0.0);
 
     Workspace* w = get_workspace(stream, &rc);
     if (!w) return rc;
@@ -891,7 +915,8 @@ int eik_solve_noalloc(const int64_t dims[3], double h, const void* F, int f_dtyp
     if (!grid_size(dims, cell, f_dtype, opt.mode, &g)) return EIK_EINVAL;
     const bool mixed = opt.mode == EIK_MODE_MIXED;
     const int ntab = mixed ? 2 : 1;
-    const CommonLayout L = common_layout(g.ncell, ntab);
+    const CommonLayout L =
+        common_layout(g.ncell, ntab, opt.schedule == EIK_SCHED_ASYNC && opt.delta > 0.0);
     const size_t exits_off = L.total + g.bytes();
     const size_t need = exits_off + (sources->on_device ? 0 : align_up(eik::kHostExitsMax * 32));
     if (need > kScratchBytes) return EIK_ETOOBIG;
@@ -1163,6 +1188,7 @@ int eik_server_create(eik_server** out, size_t pool_bytes, int64_t max_cells, in
     eik_server* s = new eik_server();
     int rc = parse_options(options, cell, &s->opt, &s->P);
     if (rc == EIK_OK && s->opt.mode == EIK_MODE_MIXED) rc = EIK_EINVAL;  // one precision per server
+    if (rc == EIK_OK && s->opt.schedule == EIK_SCHED_ASYNC) rc = EIK_EINVAL;  // steps are rounds
     if (rc != EIK_OK) { delete s; return rc; }
     hipError_t e = hipGetDevice(&s->device);
     if (e != hipSuccess) { delete s; return hip_fail(e); }

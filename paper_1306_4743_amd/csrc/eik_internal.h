@@ -15,6 +15,7 @@ constexpr uint32_t FL_QUEUED = 1u << 7;   // already in that round's list
 constexpr int FL_DIR_SHIFT = 8;           // bits 8..15: preferred sweep directions
 constexpr int FL_GRAY_SHIFT = 16;         // bits 16..18: Gray-cycle position to resume at
 constexpr uint32_t FL_GRAY_SET = 1u << 19;  // bits 16..18 are valid (a capped visit resumes)
+constexpr uint32_t FL_RUNNING = 1u << 20;   // without rounds: a worker owns the cell now
 
 // Device status values are the public codes.
 constexpr int EIK_EINVAL_DEV = EIK_EINVAL;
@@ -52,6 +53,12 @@ constexpr size_t kSmallStatus = 2048;  // int
 constexpr size_t kSmallNextRound = 2112;  // int64: first round of the next launch
 constexpr size_t kSmallHalted = 2176;  // uint32: a one-round launch found nothing left to do
 constexpr size_t kSmallStats = 2304;   // ST_TOTAL x uint64
+// Scheduling without rounds: ring head and tail (uint64 tickets), queued-or-running cell count
+// (uint64) and the done word (uint32), each on its own 256-byte line.
+constexpr size_t kSmallAsyncHead = 3072;
+constexpr size_t kSmallAsyncTail = 3328;
+constexpr size_t kSmallAsyncPending = 3584;
+constexpr size_t kSmallAsyncDone = 3840;
 constexpr size_t kSmallBytes = 4096;
 constexpr int kBarGen = 64;            // index of the generation word in the barrier array
 
@@ -102,7 +109,31 @@ struct SolveParams {
                            // list empty, the launch status set or the round cap reached
     int64_t* round_log;    // optional [2 * round_log_len]
     int64_t round_log_len;
+    // Scheduling without rounds (k_solve_async): the ring of queued cells is list[0..1] taken as
+    // one array of 2 * ncells + kRingExtra entries (-1 = empty).
+    int64_t ncells;        // global cells of the launch
+    unsigned long long* async_head;     // next ticket to pop
+    unsigned long long* async_tail;     // next position to push
+    unsigned long long* async_pending;  // cells queued or being visited
+    uint32_t* async_done;               // set when async_pending reaches 0
+    unsigned long long* bq_ctl;         // bucket heads, tails and the lowest bucket (or null)
+    int32_t* bq_ring;                   // kBuckets rings of bq_cap 64-bit words (lap, cell)
+    int64_t bq_cap;
 };
+
+// Positions of the ring of queued cells (scheduling without rounds) beyond twice the cells: a
+// ring position is in use from the push or the ticket that claims it, whichever comes first,
+// until the item is read; at most one item per cell is queued and at most one ticket per wave
+// is outstanding, so 2 * cells + this (above the waves of any launch) positions never wrap
+// onto a position in use.
+constexpr int64_t kRingExtra = 16384;
+// Scheduling without rounds with a priority band (delta > 0): cells are kept in kBuckets rings
+// by cell value, bucket floor(value / delta) (relative to a moving lowest bucket), each ring
+// with room for every cell plus kRingExtra; a wave pops from the lowest non-empty bucket.
+constexpr int kBuckets = 64;
+// Control words of the buckets (byte offsets in their region): head and tail of bucket b at
+// b * 128 and b * 128 + 64, the lowest bucket (absolute number) at kBuckets * 128.
+constexpr size_t kBucketCtlBytes = (size_t)kBuckets * 128 + 256;
 
 // Host-side exits that a kernel argument can carry (the allocation-free solve).
 constexpr int kHostExitsMax = 32;
@@ -132,6 +163,12 @@ hipError_t launch_seed(const SolveParams& P, const Slot& S, int cell, int f_dtyp
 // round (coop = 0, P.single_round = 1).
 hipError_t launch_solve_rounds(const SolveParams& P, int cell, int f_dtype, hipStream_t s,
                                int workers, int* used, int coop);
+// The persistent solve kernel without rounds (cooperative launch): cells queued in round
+// P.round_begin's list are visited as they are popped from a ring, neighbours pushed as they
+// are tagged, and the launch ends when no cell is queued or being visited and a verification
+// pass over every cell finds eq. (2) satisfied.
+hipError_t launch_solve_async(const SolveParams& P, int cell, int f_dtype, hipStream_t s,
+                              int workers, int* used);
 // Host-driven loop: *P.halted <- 0 before the first one-round launch; after the last one, the
 // round cap is checked for round `end` (EIK_ENOCONV if its list is not empty).
 hipError_t launch_halt_reset(const SolveParams& P, hipStream_t s);

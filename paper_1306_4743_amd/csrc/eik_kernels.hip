@@ -196,6 +196,27 @@ __device__ __forceinline__ uint64_t ld_relaxed_u64(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Accesses to cell values and face copies.  Under the round barrier (ASYNC = false) they are
+// plain loads and stores: the barrier's release/acquire publishes a round's writes to the eight
+// XCD-local L2 caches.  Without rounds (ASYNC = true) every such access is an agent-scope
+// relaxed atomic, which the hardware keeps coherent across the XCDs without writing back or
+// invalidating an L2 (a release or acquire fence costs tens of microseconds there when every
+// wave issues one per visit); mem_wait() then orders them against the cell-state atomics.
+template <bool ASYNC, typename T>
+__device__ __forceinline__ T ld_val(const T* p) {
+    if constexpr (ASYNC) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <bool ASYNC, typename T>
+__device__ __forceinline__ void st_val(T* p, T v) {
+    if constexpr (ASYNC) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+// Waits until every earlier vector memory access of the wave has completed (stores are then
+// visible device-wide, atomics have returned), and keeps the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void mem_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // ------------------------------------------------------------------------------------------
 // Square root of d >= 0 for the local solve: hardware reciprocal square root refined by one
 // Goldschmidt step (which squares its relative error to ~2^-50) and one Newton correction
@@ -518,6 +539,240 @@ __device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCt
 }
 
 // ------------------------------------------------------------------------------------------
+// Scheduling without rounds.  A cell's flag word (flags[0]) carries, besides the tag bits,
+// QUEUED (the cell is in the ring or will be pushed by its owner) and RUNNING (a worker is
+// visiting it).  A tag ORs its bits and QUEUED in; whoever turns QUEUED on for a cell that is
+// not RUNNING pushes it.  A pop exchanges the word for RUNNING (taking the tag bits); at the end
+// of the visit the owner clears RUNNING and, if a tag arrived meanwhile (QUEUED set), pushes the
+// cell again.  `pending` counts cells queued or being visited: a push adds before the pushed
+// cell can be popped, a visit subtracts only after its own pushes, so it reaches 0 exactly when
+// no work is left (the pHCM's active cell count, decremented after propagation).
+
+__device__ __forceinline__ void async_cancel(const SolveParams& P) {
+    atomicCAS(P.status, 0, EIK_ECANCELLED_DEV);
+    __hip_atomic_store(P.async_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// FIFO ring (no band): lanes with `push` set append their cell (one counter update per wave).
+__device__ __forceinline__ void fifo_push(const SolveParams& P, int lane, bool push, int c) {
+    const uint64_t mask = __ballot(push);
+    const int k = __popcll(mask);
+    if (k == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) {
+        atomicAdd(P.async_pending, (unsigned long long)k);
+        mem_wait();  // counted before any of them can be popped and visited
+        base = atomicAdd(P.async_tail, (unsigned long long)k);
+    }
+    base = __shfl(base, 0, 64);
+    if (push) {
+        const uint64_t pos = base + (uint64_t)__popcll(mask & ((1ull << lane) - 1ull));
+        int32_t* slotp = &P.list[0][pos % (uint64_t)(2 * P.ncells + kRingExtra)];
+        // The position is empty unless its previous occupant is still being read by the
+        // worker that took it (see kRingExtra).
+        uint64_t polls = 0;
+        while (__hip_atomic_load(slotp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != -1) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > P.watchdog_polls) {
+                async_cancel(P);
+                break;
+            }
+        }
+        __hip_atomic_store(slotp, (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Bucketed rings (a band of width delta): control words and the bucket of a cell value.
+__device__ __forceinline__ unsigned long long* bq_head(const SolveParams& P, int b) {
+    return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(P.bq_ctl) + b * 128);
+}
+__device__ __forceinline__ unsigned long long* bq_tail(const SolveParams& P, int b) {
+    return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(P.bq_ctl) + b * 128 + 64);
+}
+__device__ __forceinline__ unsigned long long* bq_low(const SolveParams& P) {
+    return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(P.bq_ctl) +
+                                                 kBuckets * 128);
+}
+// Absolute bucket floor(value / delta), moved into the window [low, low + kBuckets): a value
+// below the lowest bucket joins it (the front moved past it), one beyond the window joins the
+// last bucket.
+__device__ __forceinline__ uint64_t bucket_of(const SolveParams& P, double value, uint64_t low) {
+    const double a = value / P.delta;
+    uint64_t A = a < 1.0e18 ? (uint64_t)a : ~0ull;
+    if (A < low) A = low;
+    if (A > low + (kBuckets - 1)) A = low + (kBuckets - 1);
+    return A;
+}
+
+// A bucket ring position p holds a 64-bit word: the lap p / bq_cap + 1 in its high half and a
+// cell id (or kAbandoned) in its low half; a word of an older lap means "free".  Tickets are
+// taken with fetch-and-add on both ends, so no pop retries on a contended head: a wave that
+// took a ticket past the last push waits briefly, then marks the position abandoned, and the
+// push that reaches it takes another position.
+constexpr uint32_t kAbandoned = 0xFFFFFFFFu;
+
+__device__ __forceinline__ unsigned long long* bq_slot(const SolveParams& P, int b, uint64_t pos) {
+    return reinterpret_cast<unsigned long long*>(P.bq_ring) + (size_t)b * (size_t)P.bq_cap +
+           pos % (uint64_t)P.bq_cap;
+}
+
+__device__ __forceinline__ void bq_push(const SolveParams& P, int lane, bool push, int c,
+                                        double value) {
+    const uint64_t mask = __ballot(push);
+    const int k = __popcll(mask);
+    if (k == 0) return;
+    if (lane == 0) {
+        atomicAdd(P.async_pending, (unsigned long long)k);
+        mem_wait();  // counted before any of them can be popped and visited
+    }
+    if (push) {
+        const uint64_t low =
+            __hip_atomic_load(bq_low(P), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int b = (int)(bucket_of(P, value, low) % (uint64_t)kBuckets);
+        uint64_t tries = 0;
+        for (bool done = false; !done;) {
+            const uint64_t pos = atomicAdd(bq_tail(P, b), 1ull);
+            const uint64_t lap = pos / (uint64_t)P.bq_cap + 1;
+            unsigned long long* sp = bq_slot(P, b, pos);
+            unsigned long long v = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while ((v >> 32) < lap) {  // free in this lap: claim it for the cell
+                const unsigned long long prev =
+                    atomicCAS(sp, v, (unsigned long long)((lap << 32) | (uint32_t)c));
+                if (prev == v) {
+                    done = true;
+                    break;
+                }
+                v = prev;
+            }
+            // Otherwise the wave holding this ticket gave up on it: take another position.
+            if (!done && ++tries > P.watchdog_polls) {
+                async_cancel(P);
+                break;
+            }
+        }
+    }
+}
+
+// Pop of one ticket of bucket b by lane 0: the cell, or -1 if the position stayed empty for a
+// short while (and is now marked abandoned).
+__device__ __forceinline__ int bq_take(const SolveParams& P, int b) {
+    const uint64_t t = atomicAdd(bq_head(P, b), 1ull);
+    const uint64_t lap = t / (uint64_t)P.bq_cap + 1;
+    unsigned long long* sp = bq_slot(P, b, t);
+    int waits = 0;
+    unsigned long long v = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if ((v >> 32) == lap) return (int)(uint32_t)v;  // the push of position t
+        if (++waits > 8) {
+            const unsigned long long prev =
+                atomicCAS(sp, v, (unsigned long long)((lap << 32) | kAbandoned));
+            if (prev == v) return -1;
+            v = prev;  // the push arrived meanwhile
+            continue;
+        }
+        __builtin_amdgcn_s_sleep(4);
+        v = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ __forceinline__ void queue_push(const SolveParams& P, int lane, bool push, int c,
+                                           double value) {
+    if (P.delta > 0.0) bq_push(P, lane, push, c, value);
+    else fifo_push(P, lane, push, c);
+}
+
+// Every lane with do_tag set tags one cell (see above); with a band the cell value is lowered
+// to `value` first (eq. (3), or eq. (4) combined with the kept value) and a pushed cell goes to
+// the bucket of its value.
+__device__ __forceinline__ void tag_lanes_async(const SolveParams& P, int lane, bool do_tag,
+                                                int target, uint32_t bits, double value) {
+    bool push = false;
+    double key = value;
+    if (do_tag) {
+        if (P.delta > 0.0) {
+            key = kept_value(P, target, value);
+            const uint64_t old = atomicMin((unsigned long long*)&P.key[0][target],
+                                           (unsigned long long)dbits(key));
+            key = fmin(bitsd(old), key);
+        }
+        const uint32_t old = atomicOr(&P.flags[0][target], bits | FL_QUEUED);
+        push = !(old & (FL_QUEUED | FL_RUNNING));
+    }
+    queue_push(P, lane, push, target, key);
+}
+
+// Pop of one cell by lane 0 of a wave: the next ticket of the FIFO ring, or a ticket of the
+// lowest non-empty bucket.  Returns the cell, or -1 once no cell is queued or being visited
+// (or the watchdog cancelled the launch).
+__device__ __forceinline__ int pop_cell(const SolveParams& P, int lane) {
+    int c = -1;
+    if (P.delta > 0.0) {
+        uint64_t polls = 0;
+        for (;;) {
+            // Lane j looks at bucket low + j; one memory round trip for the whole window.
+            const uint64_t low =
+                __hip_atomic_load(bq_low(P), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int b = (int)((low + (uint64_t)lane) % (uint64_t)kBuckets);
+            const uint64_t hd = __hip_atomic_load(bq_head(P, b), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t tl = __hip_atomic_load(bq_tail(P, b), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t nonempty = __ballot(hd < tl);
+            if (nonempty) {
+                const int j = __builtin_ctzll(nonempty);
+                int got = -1;
+                if (lane == 0) {
+                    // The lowest bucket is empty: the window starts at the first non-empty one.
+                    if (j > 0)
+                        atomicCAS(bq_low(P), (unsigned long long)low,
+                                  (unsigned long long)(low + (uint64_t)j));
+                    got = bq_take(P, (int)((low + (uint64_t)j) % (uint64_t)kBuckets));
+                }
+                got = __shfl(got, 0, 64);
+                if (got >= 0) return got;
+                if (__hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    return -1;
+                if (++polls > P.watchdog_polls) {
+                    if (lane == 0) async_cancel(P);
+                    return -1;
+                }
+                continue;  // overtaken by other waves: look again
+            }
+            if (__hip_atomic_load(P.async_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                return -1;
+            if (++polls > P.watchdog_polls) {
+                if (lane == 0) async_cancel(P);
+                return -1;
+            }
+            __builtin_amdgcn_s_sleep(16);
+        }
+    }
+    if (lane == 0) {
+        const uint64_t cap = (uint64_t)(2 * P.ncells + kRingExtra);
+        const uint64_t t = atomicAdd(P.async_head, 1ull);
+        int32_t* sp = &P.list[0][t % cap];
+        uint64_t polls = 0;
+        for (;;) {
+            const int v = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v >= 0) {
+                c = v;
+                break;
+            }
+            if ((polls & 3) == 0 &&
+                __hip_atomic_load(P.async_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+            if (++polls > P.watchdog_polls) {
+                async_cancel(P);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(16);
+        }
+        if (c >= 0) __hip_atomic_store(sp, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return __shfl(c, 0, 64);
+}
+
+// ------------------------------------------------------------------------------------------
 // One visit of cell c by one wave: stage in, locking sweeps until no change, write back,
 // tag currently-downwind neighbours.
 
@@ -536,30 +791,17 @@ __device__ __forceinline__ int face_step(int f) {
     return dir * (axis == 0 ? 1 : (axis == 1 ? B : B * B));
 }
 
-template <int R, typename FT, int INNER, typename UT>
-__device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot, uint32_t fl,
-                                           double popped_key, WaveLds<R, INNER, UT>& L,
-                                           const PlaneRegs<R, INNER>& pr, int lane,
-                                           RoundCtl* ctl_next, int nxt, VisitCounters& cnt,
-                                           WaveQueue& wq) {
-    constexpr int R2 = R * R, R3 = R * R * R, B = R + 2, NP = 3 * R - 2;
-    constexpr int NS = PlaneRegs<R, INNER>::NS;
-    // face nodes per lane: one up to r = 8, four at r = 16
+// Stage-in of one cell into the wave's LDS: cell values, s = h/F and the halo (the
+// neighbours' opposite face copies, +inf beyond the grid).
+template <int R, typename FT, int INNER, typename UT, bool ASYNC>
+__device__ __forceinline__ void stage_cell(const Slot& S, int lc, CellXYZ cc,
+                                           WaveLds<R, INNER, UT>& L, int lane) {
+    constexpr int R2 = R * R, R3 = R * R * R;
     constexpr int FPL = (R2 + 63) / 64;
-    constexpr int BOFF = 1 + B + B * B;
     const UT INF = (UT)__builtin_inf();
-    const unsigned long long t0 = cycles();
-    // The cell's grid (slot, looked up by the pop) and its local index there; c itself is a
-    // global cell id.
-    c = __builtin_amdgcn_readfirstlane(c);
-    slot = __builtin_amdgcn_readfirstlane(slot);
-    const Slot S = P.slots[slot];
-    const int lc = c - S.cell_base;
-    const CellXYZ cc = cell_coords(S, lc);
     const UT* __restrict__ ug = reinterpret_cast<const UT*>(S.u) + (size_t)lc * R3;
     const UT* __restrict__ faces = reinterpret_cast<const UT*>(S.faces);
     const FT* __restrict__ fg = reinterpret_cast<const FT*>(S.f) + (size_t)lc * R3;
-
     // Stage in: cell values, s = h/F and the halo (the neighbours' opposite face copies, +inf
     // beyond the grid).  Every load is issued before any is used, so the visit waits for one
     // memory round trip instead of one per load (up to r = 8; at r = 16, one per 16 nodes a
@@ -574,7 +816,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
         FT fv[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            uv[k] = ug[lane + 64 * (k0 + k)];
+            uv[k] = ld_val<ASYNC>(&ug[lane + 64 * (k0 + k)]);
             fv[k] = fg[lane + 64 * (k0 + k)];
         }
         if (k0 == 0) {
@@ -586,7 +828,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                 const size_t src = ((size_t)(nb >= 0 ? nb : lc) * 6 + (f ^ 1)) * R2 + lane;
 #pragma unroll
                 for (int j = 0; j < FPL; ++j) {
-                    hv[f][j] = lane + 64 * j < R2 ? faces[src + 64 * j] : INF;
+                    hv[f][j] = lane + 64 * j < R2 ? ld_val<ASYNC>(&faces[src + 64 * j]) : INF;
                     if (nb < 0) hv[f][j] = INF;
                 }
             }
@@ -614,6 +856,29 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
         }
     }
     wave_sync();
+}
+
+template <int R, typename FT, int INNER, typename UT, bool ASYNC = false>
+__device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot, uint32_t fl,
+                                           double popped_key, WaveLds<R, INNER, UT>& L,
+                                           const PlaneRegs<R, INNER>& pr, int lane,
+                                           RoundCtl* ctl_next, int nxt, VisitCounters& cnt,
+                                           WaveQueue& wq) {
+    constexpr int R2 = R * R, R3 = R * R * R, B = R + 2, NP = 3 * R - 2;
+    constexpr int NS = PlaneRegs<R, INNER>::NS;
+    // face nodes per lane: one up to r = 8, four at r = 16
+    constexpr int FPL = (R2 + 63) / 64;
+    constexpr int BOFF = 1 + B + B * B;
+    const UT INF = (UT)__builtin_inf();
+    const unsigned long long t0 = cycles();
+    // The cell's grid (slot, looked up by the pop) and its local index there; c itself is a
+    // global cell id.
+    c = __builtin_amdgcn_readfirstlane(c);
+    slot = __builtin_amdgcn_readfirstlane(slot);
+    const Slot S = P.slots[slot];
+    const int lc = c - S.cell_base;
+    const CellXYZ cc = cell_coords(S, lc);
+    stage_cell<R, FT, INNER, UT, ASYNC>(S, lc, cc, L, lane);
     // Border values before the visit (every visit publishes its border, so these equal the
     // published face copies; a border node below them has decreased), then the initial active
     // set: every node on a first visit, otherwise the layer next to each face that received new
@@ -968,7 +1233,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
         for (int l = lane; l < R3; l += 64) {
             const int x = l % R, y = (l / R) % R, z = l / R2;
             const UT v = L.U[box_index<R>(x, y, z)];
-            uw[l] = keep_active ? v : fabs(v);
+            st_val<ASYNC>(&uw[l], keep_active ? v : fabs(v));
         }
         {
 #pragma unroll
@@ -996,7 +1261,8 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                 if (__any(ch)) {
 #pragma unroll
                     for (int j = 0; j < FPL; ++j)
-                        if (lane + 64 * j < R2) fw[((size_t)lc * 6 + f) * R2 + lane + 64 * j] = v[j];
+                        if (lane + 64 * j < R2)
+                            st_val<ASYNC>(&fw[((size_t)lc * 6 + f) * R2 + lane + 64 * j], v[j]);
                 }
                 if (nb >= 0 && __any(inflow)) {
                     // eq. (3): the smallest newly decreased inflow value; eq. (4): the largest
@@ -1036,8 +1302,13 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
         }
         cnt.requeued += 1;
     }
-    tag_lanes<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits, my_value,
-                            slot);
+    if constexpr (ASYNC) {
+        mem_wait();  // the visit's values and faces are visible before any neighbour is tagged
+        tag_lanes_async(P, lane, my_tag, my_target, my_bits, my_value);
+    } else {
+        tag_lanes<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits,
+                                my_value, slot);
+    }
     const unsigned long long t3 = cycles();
     cnt.cyc_stage += t1 - t0;
     cnt.cyc_sweep += t2 - t1;
@@ -1260,6 +1531,189 @@ k_solve(SolveParams P) {
         if (blockIdx.x == 0 && wave == 0) atomicAdd(&P.stats[ST_ROUNDS], (unsigned long long)rounds_done);
     }
     // Every workgroup leaves the round loop in the same round, so all its waves get here.
+    __syncthreads();
+    if (threadIdx.x < 64 && s_hist[threadIdx.x])
+        atomicAdd(&P.stats[ST_HIST_SWEEPS + threadIdx.x], (unsigned long long)s_hist[threadIdx.x]);
+}
+
+// ------------------------------------------------------------------------------------------
+// The solver without rounds: each wave pops one cell at a time from a ring of queued cells,
+// visits it, pushes the neighbours it tags, and pops again; there is no barrier between
+// visits.  When no cell is queued or being visited, every wave leaves the pop loop and, after a
+// grid barrier, the waves check every cell against eq. (2): a node whose local solve is below
+// its value (by more than rounding) re-queues its cell with every node active, and the pop loop
+// runs again.  The check makes the result independent of the order in which one visit's writes
+// become visible to another: every value ever stored is an upper bound of the solution (the
+// local solve is monotone and the exits hold q), so a stale read can only leave values too high,
+// which the check finds; it ends when eq. (2) holds at every node, whose solution is unique.
+
+// Whether some node of cell lc (stage already in L) has a local solve below its value.
+template <int R, int INNER, typename UT>
+__device__ __forceinline__ bool cell_above_fixed_point(WaveLds<R, INNER, UT>& L, int lane) {
+    constexpr int R2 = R * R, R3 = R * R * R, B = R + 2;
+    bool bad = false;
+    for (int l = lane; l < R3; l += 64) {
+        const UT s = L.S[l];
+        if (!(s > UT(0))) continue;  // exit or padding
+        const int x = l % R, y = (l / R) % R, z = l / R2;
+        const int b = box_index<R>(x, y, z);
+        const UT u = fabs(L.U[b]);
+        const UT g = local_solve(vmin_abs(L.U[b - 1], L.U[b + 1]), vmin_abs(L.U[b - B], L.U[b + B]),
+                                 vmin_abs(L.U[b - B * B], L.U[b + B * B]), s);
+        bad |= g < u && (u == (UT)__builtin_inf() || u - g > u * (UT)0x1p-44);
+    }
+    return __any(bad);
+}
+
+template <int R, typename FT, int W, int INNER, typename UT>
+__global__ void __launch_bounds__(64 * W)
+    __attribute__((amdgpu_waves_per_eu(R == 16 ? 1 : (sizeof(UT) == 4 ? 4 : 3))))
+k_solve_async(SolveParams P) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    WaveLds<R, INNER, UT>& L = reinterpret_cast<WaveLds<R, INNER, UT>*>(lds_raw)[wave];
+    VisitCounters cnt{0, 0, 0, 0, 0, 0};
+    unsigned long long cyc_pop = 0, cyc_wait = 0, visits = 0;
+    PlaneRegs<R, INNER> pr;
+    load_plane_regs<R, INNER>(pr, lane);
+    __shared__ unsigned int s_hist[64];
+    if (threadIdx.x < 64) s_hist[threadIdx.x] = 0u;
+    const int nwaves_total = (int)gridDim.x * W;
+    const int gwave = (int)blockIdx.x * W + wave;
+    const bool band = P.delta > 0.0;
+    // The exits' cells were queued for the first round by the seed: the first n0 entries of
+    // list[0] (with QUEUED set in flags[0] and their cell values in key[0]).
+    const uint32_t n0 = P.ctl[P.round_begin & 3].count;
+    const size_t gtid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t gthreads = (size_t)gridDim.x * blockDim.x;
+    if (!band) {
+        // The FIFO ring is list[0..1] itself: the seeded cells are its first n0 entries.
+        const uint64_t cap = (uint64_t)(2 * P.ncells + kRingExtra);
+        for (uint64_t i = n0 + gtid; i < cap; i += gthreads) P.list[0][i] = -1;
+        if (gtid == 0) {
+            *P.async_head = 0;
+            *P.async_tail = n0;
+        }
+    } else {
+        const uint64_t total = (uint64_t)kBuckets * (uint64_t)P.bq_cap;
+        unsigned long long* words = reinterpret_cast<unsigned long long*>(P.bq_ring);
+        for (uint64_t i = gtid; i < total; i += gthreads) words[i] = 0ull;  // lap 0: free
+        for (size_t i = gtid; i < (size_t)kBuckets; i += gthreads) {
+            *bq_head(P, (int)i) = 0;
+            *bq_tail(P, (int)i) = 0;
+        }
+        if (gtid == 0) *bq_low(P) = 0;
+    }
+    if (gtid == 0) {
+        *P.async_pending = n0;
+        *P.async_done = n0 == 0 ? 1u : 0u;
+    }
+    int passes = 0;
+    bool ok = grid_barrier(P);
+    if (ok && band) {
+        // Seeded cells into the buckets of their values.
+        for (size_t i = gtid; i < n0; i += gthreads) {
+            const int c = P.list[0][i];
+            const int b = (int)(bucket_of(P, bitsd(P.key[0][c]), 0) % (uint64_t)kBuckets);
+            const uint64_t pos = atomicAdd(bq_tail(P, b), 1ull);
+            *bq_slot(P, b, pos) = (unsigned long long)(((pos / (uint64_t)P.bq_cap + 1) << 32) |
+                                                       (uint32_t)c);
+        }
+        ok = grid_barrier(P);
+    }
+    while (ok) {
+        // Pop loop.
+        for (;;) {
+            const unsigned long long tp0 = cycles();
+            const int c = pop_cell(P, lane);
+            if (c < 0) {
+                cyc_wait += cycles() - tp0;
+                break;
+            }
+            uint32_t fl = 0;
+            int slot = 0;
+            unsigned long long kb = 0;
+            if (lane == 0) {
+                fl = atomicExch(&P.flags[0][c], FL_RUNNING);
+                if (band)  // the removal of the cell from the heap resets its value to +inf
+                    kb = atomicExch((unsigned long long*)&P.key[0][c],
+                                    (unsigned long long)dbits(__builtin_inf()));
+                slot = P.cell_slot[c];
+            }
+            fl = __shfl(fl, 0, 64) & ~FL_QUEUED;
+            slot = __shfl(slot, 0, 64);
+            kb = __shfl(kb, 0, 64);
+            mem_wait();  // the exchange has returned before the visit reads the cell
+            cyc_pop += cycles() - tp0;
+            ++visits;
+            const unsigned long long sw0 = cnt.sweeps, tv0 = cycles();
+            WaveQueue wq{0, __builtin_inf()};
+            visit_cell<R, FT, INNER, UT, true>(P, c, slot, fl, bitsd(kb), L, pr, lane, nullptr, 0,
+                                               cnt, wq);
+            // Release the cell; a tag that arrived during the visit left QUEUED set (and, with a
+            // band, lowered its value).
+            bool again = false;
+            double again_key = 0.0;
+            if (lane == 0) {
+                again = (atomicAnd(&P.flags[0][c], ~FL_RUNNING) & FL_QUEUED) != 0;
+                if (again && band) again_key = bitsd(ld_relaxed_u64(&P.key[0][c]));
+            }
+            again = __shfl((int)again, 0, 64) != 0;
+            queue_push(P, lane, lane == 0 && again, c, again_key);
+            if (lane == 0) {
+                if (atomicAdd(P.async_pending, ~0ull) == 1ull)
+                    __hip_atomic_store(P.async_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long dsw = cnt.sweeps - sw0, dt = cycles() - tv0;
+                atomicAdd(&s_hist[dsw < 31 ? dsw : 31], 1u);
+                const int lg = dt ? 63 - __builtin_clzll(dt) : 0;
+                atomicAdd(&s_hist[32 + (lg < 31 ? lg : 31)], 1u);
+            }
+        }
+        // No cell queued or being visited.  Abandon the tickets taken past the last push (so
+        // that later pushes are popped), then check every cell.
+        const unsigned long long tw0 = cycles();
+        if (!(ok = grid_barrier(P))) break;
+        if (__hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (!band) *P.async_head = *P.async_tail;
+            *P.async_done = 0u;
+        }
+        if (!(ok = grid_barrier(P))) break;
+        ++passes;
+        for (int64_t c = gwave; c < P.ncells; c += nwaves_total) {
+            const int cs = __builtin_amdgcn_readfirstlane(P.cell_slot[c]);
+            const Slot S = P.slots[cs];
+            const int lc = (int)c - S.cell_base;
+            stage_cell<R, FT, INNER, UT, true>(S, lc, cell_coords(S, lc), L, lane);
+            const bool redo = cell_above_fixed_point<R, INNER, UT>(L, lane);
+            wave_sync();
+            tag_lanes_async(P, lane, redo && lane == 0, (int)c, FL_ALL, 0.0);
+        }
+        if (!(ok = grid_barrier(P))) break;
+        cyc_wait += cycles() - tw0;
+        const unsigned long long left =
+            __hip_atomic_load(P.async_pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (left == 0) break;
+        if (passes >= 64) {  // a bound on check passes that a correct solve never nears
+            if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(P.status, 0, EIK_ENOCONV_DEV);
+            break;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *P.next_round = P.round_begin + 1;
+    cnt.updates = wave_sum(cnt.updates);
+    if (lane == 0) {
+        atomicAdd(&P.stats[ST_VISITS], visits);
+        atomicAdd(&P.stats[ST_SWEEPS], cnt.sweeps);
+        atomicAdd(&P.stats[ST_UPDATES], cnt.updates);
+        atomicAdd(&P.stats[ST_REQUEUED], cnt.requeued);
+        atomicAdd(&P.stats[ST_CYC_POP], cyc_pop);
+        atomicAdd(&P.stats[ST_CYC_STAGE], cnt.cyc_stage);
+        atomicAdd(&P.stats[ST_CYC_SWEEP], cnt.cyc_sweep);
+        atomicAdd(&P.stats[ST_CYC_WRITE], cnt.cyc_write);
+        atomicAdd(&P.stats[ST_CYC_WAIT], cyc_wait);
+        atomicAdd(&P.stats[ST_WORKERS], 1ull);
+        if (blockIdx.x == 0 && wave == 0) atomicAdd(&P.stats[ST_ROUNDS], (unsigned long long)passes);
+    }
     __syncthreads();
     if (threadIdx.x < 64 && s_hist[threadIdx.x])
         atomicAdd(&P.stats[ST_HIST_SWEEPS + threadIdx.x], (unsigned long long)s_hist[threadIdx.x]);
@@ -1523,11 +1977,11 @@ __global__ void k_slot_counts(SolveParams P, int* counts) {
 template <int R, int W, int INNER, typename UT>
 constexpr size_t solve_lds_bytes() { return sizeof(WaveLds<R, INNER, UT>) * W; }
 
-template <int R, typename FT, int W, int INNER, typename UT>
+template <int R, typename FT, int W, int INNER, typename UT, bool ASYNCK = false>
 static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int workers, int* used,
                                  int coop) {
     const size_t lds = solve_lds_bytes<R, W, INNER, UT>();
-    auto kern = k_solve<R, FT, W, INNER, UT>;
+    auto kern = ASYNCK ? k_solve_async<R, FT, W, INNER, UT> : k_solve<R, FT, W, INNER, UT>;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -1549,6 +2003,9 @@ static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int worker
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     int grid = per_cu * ncu;
     if (workers > 0) grid = workers < grid ? workers : grid;
+    // The ring of the launch without rounds holds one outstanding ticket per wave beyond its
+    // cells (kRingExtra).
+    if (ASYNCK && (int64_t)grid * W * 2 > kRingExtra) return hipErrorInvalidConfiguration;
     *used = grid;
     if (std::getenv("EIK_DEBUG")) {
         hipDeviceProp_t prop;
@@ -1588,26 +2045,40 @@ constexpr int waves_per_group() {
     return by_regs < by_lds ? by_regs : by_lds;
 }
 
-template <int R, typename FT, typename UT>
+template <int R, typename FT, typename UT, bool ASYNCK>
 static hipError_t solve_rounds_ut(const SolveParams& P, hipStream_t s, int workers, int* used,
                                   int coop) {
     if (P.inner == INNER_SWEEP)
-        return launch_solve_t<R, FT, waves_per_group<R, INNER_SWEEP, UT>(), INNER_SWEEP, UT>(
-            P, s, workers, used, coop);
+        return launch_solve_t<R, FT, waves_per_group<R, INNER_SWEEP, UT>(), INNER_SWEEP, UT,
+                              ASYNCK>(P, s, workers, used, coop);
     if (P.inner == INNER_LIST)
-        return launch_solve_t<R, FT, waves_per_group<R, INNER_LIST, UT>(), INNER_LIST, UT>(
-            P, s, workers, used, coop);
+        return launch_solve_t<R, FT, waves_per_group<R, INNER_LIST, UT>(), INNER_LIST, UT,
+                              ASYNCK>(P, s, workers, used, coop);
     if constexpr (R <= 8)
-        return launch_solve_t<R, FT, waves_per_group<R, INNER_DUAL, UT>(), INNER_DUAL, UT>(
-            P, s, workers, used, coop);
+        return launch_solve_t<R, FT, waves_per_group<R, INNER_DUAL, UT>(), INNER_DUAL, UT,
+                              ASYNCK>(P, s, workers, used, coop);
     return hipErrorInvalidValue;  // the host refuses two sweep streams at r = 16
 }
 
-template <int R, typename FT>
+template <int R, typename FT, bool ASYNCK = false>
 static hipError_t solve_rounds_t(const SolveParams& P, hipStream_t s, int workers, int* used,
                                  int coop) {
-    return P.fp32 ? solve_rounds_ut<R, FT, float>(P, s, workers, used, coop)
-                  : solve_rounds_ut<R, FT, double>(P, s, workers, used, coop);
+    return P.fp32 ? solve_rounds_ut<R, FT, float, ASYNCK>(P, s, workers, used, coop)
+                  : solve_rounds_ut<R, FT, double, ASYNCK>(P, s, workers, used, coop);
+}
+
+hipError_t launch_solve_async(const SolveParams& P, int cell, int f_dtype, hipStream_t s,
+                              int workers, int* used) {
+    if (cell == 16)
+        return f_dtype == EIK_F32 ? solve_rounds_t<16, float, true>(P, s, workers, used, 1)
+                                  : solve_rounds_t<16, double, true>(P, s, workers, used, 1);
+    if (cell == 8)
+        return f_dtype == EIK_F32 ? solve_rounds_t<8, float, true>(P, s, workers, used, 1)
+                                  : solve_rounds_t<8, double, true>(P, s, workers, used, 1);
+    if (cell == 4)
+        return f_dtype == EIK_F32 ? solve_rounds_t<4, float, true>(P, s, workers, used, 1)
+                                  : solve_rounds_t<4, double, true>(P, s, workers, used, 1);
+    return hipErrorInvalidValue;
 }
 
 static int blocks_for(size_t n, int threads) {

@@ -23,7 +23,7 @@ EIK_F64, EIK_F32 = 0, 1
 EIK_MODE_FP64, EIK_MODE_FP32, EIK_MODE_MIXED = 0, 1, 2
 EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL = 1, 2, 3
 EIK_CELL_VALUE_NEW, EIK_CELL_VALUE_OLD = 0, 1
-EIK_SCHED_AUTO, EIK_SCHED_COOPERATIVE, EIK_SCHED_HOST_LOOP = 0, 1, 2
+EIK_SCHED_AUTO, EIK_SCHED_COOPERATIVE, EIK_SCHED_HOST_LOOP, EIK_SCHED_ASYNC = 0, 1, 2, 3
 
 
 class EikError(RuntimeError):

@@ -174,7 +174,7 @@ def test_schedule_option_checked():
     lib = eik.load()
     pb, keep = _problem()
     arr = (eik.Problem * 1)(pb)
-    for bad in (-1, 3):
+    for bad in (-1, 4):
         opts = eik._options(schedule=bad)
         assert lib.eik_solve_batch(1, arr, eik.EIK_F32, 8, None,
                                    ctypes.byref(opts)) == eik.EIK_EINVAL
@@ -376,3 +376,4 @@ def test_noalloc_limits_checked_on_the_host():
                                  eik.EIK_F32, ctypes.byref(src), ctypes.c_void_p(16), 8, 0.0, None,
                                  ctypes.byref(timed)) == eik.EIK_EINVAL
     assert "384 MiB" in eik.strerror(eik.EIK_ETOOBIG)
+
