@@ -217,7 +217,13 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests of the mixed-size serving stream (0: skip the serving leg)")
     ap.add_argument("--serving-rounds", type=int, default=16,
-                    help="worklist rounds per server step in the serving leg")
+                    help="worklist rounds per server step in the serving leg (with "
+                         "--no-serving-tune)")
+    ap.add_argument("--no-serving-tune", action="store_true",
+                    help="serve with --cell and --serving-rounds instead of the tuned server "
+                         "configuration (tuning cache, measured on a sample of the stream)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuning cache file (JSON); default: a fresh file for this run")
     ap.add_argument("--precision-n", type=int, default=1025,
                     help="side of the Gaussian-bumps grid of the precision leg (0: skip it)")
     ap.add_argument("--copy-reference-mib", type=int, default=0,
@@ -401,15 +407,20 @@ def serving_leg(args):
     """The mixed-size request stream (33..257 nodes per side, barrier mazes, 1-4 exits) through
     the continuous-batching servers, against one-at-a-time solves of the same stream."""
     from paper_1306_4743_amd import serve
+    cache = args.tune_cache
+    if cache is None and not args.no_serving_tune:
+        import tempfile
+        cache = os.path.join(tempfile.mkdtemp(prefix="eik_tune_"), "tuning.json")
     r = serve.serve_benchmark(args.serving_requests, rounds=args.serving_rounds, cell=args.cell,
-                              log=sys.stderr)
+                              log=sys.stderr, tune=not args.no_serving_tune, tune_cache=cache)
     sat, one = r["saturated"], r["one_at_a_time_saturated"]
     mix = r["mode_mix"]
     pick = ("p50_ms", "p99_ms", "requests_per_s", "arrival_rate_per_s")
     return {
         "workload": f"{r['requests']} requests, n uniform over {r['sizes']}, barrier mazes seed "
                     f"5000+i, 1-4 exits, FP32 speeds, FP64 values, tol 0, inputs resident",
-        "rounds_per_step": r["rounds_per_step"], "pool_bytes": r["pool_bytes"],
+        "rounds_per_step": r["rounds_per_step"], "cell": r["cell"],
+        "pool_bytes": r["pool_bytes"], "tuned_configuration": r["tuned"],
         "mode_mix": {
             "modes": f"fair coin per request: FP64 or FP32 + FP64 polish "
                      f"({mix['saturated']['polish_requests']} of {r['requests']} polish)",

@@ -47,7 +47,9 @@ namespace eik {
 // Constant tables.
 
 // Nodes of a cell of side R grouped by diagonal plane p = x + y + z (canonical direction +++),
-// packed as x | y << 5 | z << 10; 0xFFFF marks an unused (step, lane) slot.  A sweep takes the
+// stored as the node's index x + R y + R^2 z in the cell; 0xFFFF marks an unused (step, lane)
+// slot.  R is a power of two, so the reflection R - 1 - x of a coordinate is x ^ (R - 1) and a
+// sweep direction reflects the whole index with one XOR.  A sweep takes the
 // planes in order, 64 nodes per wave step: one step per plane up to r = 8 (at most 48 nodes), and
 // a plane of more than 64 nodes (r = 16: up to 192) over consecutive steps.  Nodes of one plane
 // are not neighbours of each other, so splitting a plane over steps keeps the plane order.
@@ -78,7 +80,7 @@ struct PlaneTable {
                 for (int y = 0; y < R; ++y) {
                     int x = p - y - z;
                     if (x < 0 || x >= R) continue;
-                    slot[(step + n / 64) * 64 + n % 64] = (uint16_t)(x | (y << 5) | (z << 10));
+                    slot[(step + n / 64) * 64 + n % 64] = (uint16_t)(x + R * (y + R * z));
                     ++n;
                 }
             step += (n + 63) / 64;
@@ -110,7 +112,7 @@ struct DualTable {
                     for (int y = 0; y < R; ++y) {
                         int x = p - y - z;
                         if (x < 0 || x >= R) continue;
-                        slot[t * 64 + n] = (uint16_t)(x | (y << 5) | (z << 10) | (stream << 15));
+                        slot[t * 64 + n] = (uint16_t)((x + R * (y + R * z)) | (stream << 15));
                         ++n;
                     }
             }
@@ -378,6 +380,25 @@ template <int R>
 __device__ __forceinline__ int box_index(int x, int y, int z) {
     constexpr int B = R + 2;
     return (x + 1) + B * ((y + 1) + B * (z + 1));
+}
+
+constexpr int log2_side(int R) { return R == 16 ? 4 : (R == 8 ? 3 : 2); }
+
+// Box index of the cell node with index l = x + R y + R^2 z: (x + 1) + B (y + 1) + B^2 (z + 1)
+// = l + (B - R) y + (B^2 - R^2) z + (1 + B + B^2).
+template <int R>
+__device__ __forceinline__ int box_of_cell_index(uint32_t l) {
+    constexpr int B = R + 2, LG = log2_side(R);
+    const int y = (int)((l >> LG) & (uint32_t)(R - 1)), z = (int)(l >> (2 * LG));
+    return (int)l + (B - R) * y + (B * B - R * R) * z + (1 + B + B * B);
+}
+
+// XOR mask that reflects a cell index for sweep direction d (bit a set: descending along a).
+template <int R>
+__device__ __forceinline__ uint32_t reflect_mask(int d) {
+    constexpr int LG = log2_side(R);
+    return ((d & 1) ? (uint32_t)(R - 1) : 0u) | ((d & 2) ? (uint32_t)(R - 1) << LG : 0u) |
+           ((d & 4) ? (uint32_t)(R - 1) << (2 * LG) : 0u);
 }
 
 // Per-lane node coordinates of every sweep step (a diagonal plane, or 64 nodes of one), packed
@@ -955,19 +976,18 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                 d = kGray[last_gi];
                 ++ci;
             }
-            const int mx = (d & 1) ? R - 1 : 0, my = (d & 2) ? R - 1 : 0, mz = (d & 4) ? R - 1 : 0;
+            const uint32_t mref = reflect_mask<R>(d);
             bool changed = false;
             UT maxdec = UT(0);
     #pragma unroll
             for (int p = 0; p < NS; ++p) {
                 uint32_t e = (pr.pk[p >> 1] >> ((p & 1) * 16)) & 0xFFFFu;
-                // Keep the decode inside the sweep loop: hoisting the 3 x NS decoded coordinates
-                // out of it costs more registers than the few ALU operations it saves.
+                // Keep the decode inside the sweep loop: hoisting the NS decoded addresses out
+                // of it costs more registers than the few ALU operations it saves.
                 asm volatile("" : "+v"(e));
-                const int x = (int)(e & 31u) ^ mx, y = (int)((e >> 5) & 31u) ^ my,
-                          z = (int)((e >> 10) & 31u) ^ mz;
-                const int b = x + B * (y + B * z) + BOFF;
-                const int l = x + R * (y + R * z);
+                const uint32_t lr = e ^ mref;
+                const int l = (int)lr;
+                const int b = box_of_cell_index<R>(lr);
                 UT raw = L.U[b];
                 UT s = L.S[l];
                 UT xm = L.U[b - 1], xp = L.U[b + 1];
@@ -990,7 +1010,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                                              vmin_abs(zm, zp), s);
                     const bool live = act && s > UT(0);
                     const bool dec = live && g < old;
-                    upd += live ? 1u : 0u;
+                    upd += (unsigned)__popcll(__ballot(live));  // wave total, scalar unit
                     UT* const ub = &L.U[b];
                     if (act) ub[0] = dec ? g : old;
                     changed |= dec;
@@ -1062,14 +1082,12 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                     d1 = next_dir();
                     if (__popc((uint32_t)(d0 ^ d1)) == 3) d1 = d0;
                 }
+                const uint32_t mref0 = reflect_mask<R>(d0), mref1 = reflect_mask<R>(d1);
                 uint32_t e = (pr.pk[t >> 1] >> ((t & 1) * 16)) & 0xFFFFu;
                 asm volatile("" : "+v"(e));
-                const int dd = (e & 0x8000u) ? d1 : d0;
-                const int x = (int)(e & 31u) ^ ((dd & 1) ? R - 1 : 0);
-                const int y = (int)((e >> 5) & 31u) ^ ((dd & 2) ? R - 1 : 0);
-                const int z = (int)((e >> 10) & 31u) ^ ((dd & 4) ? R - 1 : 0);
-                const int b = x + B * (y + B * z) + BOFF;
-                const int l = x + R * (y + R * z);
+                const uint32_t lr = (e & 0x7FFFu) ^ ((e & 0x8000u) ? mref1 : mref0);
+                const int l = (int)lr;
+                const int b = box_of_cell_index<R>(lr);
                 UT old = L.U[b];
                 UT s = L.S[l];
                 UT xm = L.U[b - 1], xp = L.U[b + 1];
@@ -1083,7 +1101,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                     const UT g = local_solve(vmin(xm, xp), vmin(ym, yp), vmin(zm, zp), s);
                     const bool live = act && s > UT(0);
                     const bool dec = live && g < old;
-                    upd += live ? 1u : 0u;
+                    upd += (unsigned)__popcll(__ballot(live));  // wave total, scalar unit
                     changed |= dec;
                     if (track_dec && dec) maxdec = vmax(maxdec, old - g);
                     L.U[dec ? b : dm] = g;
@@ -1172,7 +1190,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                 const UT g = local_solve(fmin(xm, xp), fmin(ym, yp), fmin(zm, zp), s);
                 const bool live = valid && s > UT(0);
                 const bool dec = live && g < old;
-                upd += live ? 1u : 0u;
+                upd += (unsigned)__popcll(__ballot(live));  // wave total, scalar unit
                 L.U[valid ? b : 0] = dec ? g : old;  // positive: no longer listed
                 if (dec) {
                     maxdec = vmax(maxdec, old - g);
@@ -1515,7 +1533,6 @@ k_solve(SolveParams P) {
         }
     }
     // Counters.
-    cnt.updates = wave_sum(cnt.updates);
     if (lane == 0) {
         atomicAdd(&P.stats[ST_VISITS], visits);
         atomicAdd(&P.stats[ST_SWEEPS], cnt.sweeps);
@@ -1700,7 +1717,6 @@ k_solve_async(SolveParams P) {
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *P.next_round = P.round_begin + 1;
-    cnt.updates = wave_sum(cnt.updates);
     if (lane == 0) {
         atomicAdd(&P.stats[ST_VISITS], visits);
         atomicAdd(&P.stats[ST_SWEEPS], cnt.sweeps);

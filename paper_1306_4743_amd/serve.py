@@ -292,8 +292,12 @@ def check_against_alone(reqs, sample: int = 10, cell: int = 8):
 
 def serve_benchmark(count: int = 2000, rounds: int = 8, cell: int = 8,
                     fractions=(0.5, 0.8, 1.0), seq_fraction: float = 0.8,
-                    pool_bytes: int = 32 << 30, log=None):
-    """The whole serving measurement; returns a JSON-able dict."""
+                    pool_bytes: int = 32 << 30, log=None, tune: bool = False,
+                    tune_cache: str | None = None):
+    """The whole serving measurement; returns a JSON-able dict.  With ``tune`` the servers'
+    cell size and rounds per step come from the tuning cache (``tuning.tuned_server_config``,
+    measured on a sample of this stream when the cache has no entry for it) instead of
+    ``cell`` and ``rounds``."""
     import torch
     from . import eik
     eik.load()
@@ -316,12 +320,22 @@ def serve_benchmark(count: int = 2000, rounds: int = 8, cell: int = 8,
     t = time.perf_counter()
     reqs = make_requests(count, dev)
     say(f"serve: {count} requests generated in {time.perf_counter() - t:.1f} s")
+    tuned = None
+    if tune:
+        from . import tuning
+        cache = tuning.TuneCache(tune_cache) if tune_cache else tuning.TuneCache()
+        cfg, key, table = tuning.tuned_server_config(reqs, SIZES, eik.EIK_MODE_FP64, cache,
+                                                     log=log, pool_bytes=pool_bytes)
+        cell, rounds = cfg["cell"], cfg["rounds_per_step"]
+        tuned = {"key": key, "cell": cell, "rounds_per_step": rounds,
+                 "measured_now": table is not None, "table": table}
+        say(f"serve: tuned server configuration {key}: cell {cell}, {rounds} rounds per step")
     # warm-up: a few requests through each kind of server and alone
     run_server(reqs[:8], np.zeros(8), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
     run_stream(reqs[:8], np.zeros(8), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
     run_sequential(reqs[:4], np.zeros(4), cell=cell, by_mode=True)
     out = {"requests": count, "sizes": list(SIZES), "cell": cell, "rounds_per_step": rounds,
-           "pool_bytes": pool_bytes}
+           "pool_bytes": pool_bytes, "tuned": tuned}
     # Every request in FP64.
     sat = run_server(reqs, np.zeros(count), cell=cell, rounds=rounds, pool_bytes=pool_bytes)
     say(f"serve: FP64 saturated {sat['requests_per_s']:.1f} req/s, {sat['steps']} steps")
@@ -378,9 +392,12 @@ def main():
     ap.add_argument("--rounds", type=int, default=8, help="worklist rounds per server step")
     ap.add_argument("--cell", type=int, default=8)
     ap.add_argument("--pool-gib", type=float, default=32.0)
+    ap.add_argument("--tune", action="store_true",
+                    help="cell size and rounds per step from the tuning cache (measured if absent)")
+    ap.add_argument("--tune-cache", default=None, help="tuning cache file (JSON)")
     a = ap.parse_args()
     res = serve_benchmark(a.requests, a.rounds, a.cell, pool_bytes=int(a.pool_gib * (1 << 30)),
-                          log=sys.stderr)
+                          log=sys.stderr, tune=a.tune, tune_cache=a.tune_cache)
     print(json.dumps(res), flush=True)
 
 
