@@ -135,6 +135,12 @@ extern "C" {
 #define EIK_INNER_SWEEP 1
 #define EIK_INNER_LIST 2
 #define EIK_INNER_DUAL 3
+/*   EIK_INNER_PAIR   the locking sweeps of EIK_INNER_SWEEP on two cells of a round at once, one
+ *                    wave sweeping both half a sweep apart (each cell its own directions, stop
+ *                    test and cap), so a wave instruction serves up to twice the nodes; cells
+ *                    of 4 and 8 only, not with EIK_SCHED_ASYNC (EIK_EINVAL).  A CU holds half
+ *                    as many such waves in FP64 (two cells' LDS each). */
+#define EIK_INNER_PAIR 4
 
 /* Exit set Q' and its values q (Section 4 notation: Q' = X intersect Q, values prescribed). */
 typedef struct eik_sources {
@@ -278,7 +284,7 @@ int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_
 /* One configuration tried by eik_autotune and its time. */
 typedef struct eik_tune_entry {
     int cell;             /* r: 4, 8 or 16                                                    */
-    int inner;            /* EIK_INNER_SWEEP, EIK_INNER_LIST or EIK_INNER_DUAL                 */
+    int inner;            /* EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL or EIK_INNER_PAIR  */
     int workers;          /* persistent workgroups (0 = one per CU)                            */
     double delta;         /* priority band width (0 = every queued cell each round)            */
     double ms;            /* fastest of `reps` whole eik_solve_ex calls (stream events);       */
@@ -290,7 +296,8 @@ typedef struct eik_tune_entry {
  * eik_autotune -- time the solver's configurations on one problem and return the fastest.
  * The best cell size, in-cell solver, worker count and priority band depend on the problem
  * (Section 6 finds the best cell size problem-dependent), so they are measured, not guessed:
- * every combination of r in {8, 4, 16}, inner in {SWEEP, LIST, DUAL} (DUAL up to r = 8) and
+ * every combination of r in {8, 4, 16}, inner in {SWEEP, LIST, DUAL, PAIR} (DUAL and PAIR up to
+ * r = 8) and
  * workers in {all, half the CUs} with no band, then the best of those with bands of 4, 16 and 64 cell
  * crossings (delta = 4 r h, 16 r h, 64 r h).  Each configuration is solved once to warm up and `reps` (1..100)
  * times timed; the problem's arguments are those of eik_solve_ex (u_out receives the result of

@@ -155,7 +155,7 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
     if (std::isnan(opt->delta) || opt->max_rounds < 0 || opt->max_sweeps < 0 || opt->workers < 0)
         return EIK_EINVAL;
     if (opt->round_log_len < 0 || (opt->round_log_len > 0 && !opt->round_log)) return EIK_EINVAL;
-    if (opt->inner < 0 || opt->inner > EIK_INNER_DUAL) return EIK_EINVAL;
+    if (opt->inner < 0 || opt->inner > EIK_INNER_PAIR) return EIK_EINVAL;
     if (opt->cell_value != EIK_CELL_VALUE_NEW && opt->cell_value != EIK_CELL_VALUE_OLD)
         return EIK_EINVAL;
     if (opt->schedule < EIK_SCHED_AUTO || opt->schedule > EIK_SCHED_ASYNC) return EIK_EINVAL;
@@ -164,12 +164,15 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
     // default in-cell solver: sweeps at r = 8 and 16, the list relaxation at r = 4 (measured
     // fastest); two sweep streams need both planes in one wave, which r = 16 does not allow
     const int inner = opt->inner ? opt->inner : (cell == 4 ? EIK_INNER_LIST : EIK_INNER_SWEEP);
-    if (inner == EIK_INNER_DUAL && cell == 16) return EIK_EINVAL;
+    if ((inner == EIK_INNER_DUAL || inner == EIK_INNER_PAIR) && cell == 16) return EIK_EINVAL;
+    if (inner == EIK_INNER_PAIR && opt->schedule == EIK_SCHED_ASYNC) return EIK_EINVAL;
     // default sweep cap: 8 directional sweeps (one Gray cycle) per visit for the sweeps -- a
     // longer visit publishes what it has and resumes next round, which keeps rounds short --
     // and effectively none for the others (their passes are short)
     P->max_sweeps = opt->max_sweeps > 0 ? opt->max_sweeps : (inner == EIK_INNER_SWEEP ? 8 : 512);
-    P->inner = inner == EIK_INNER_SWEEP ? 0 : (inner == EIK_INNER_LIST ? 1 : 2);
+    P->inner = inner == EIK_INNER_SWEEP ? 0
+             : inner == EIK_INNER_LIST ? 1
+             : inner == EIK_INNER_DUAL ? 2 : 3;
     P->delta = opt->delta > 0.0 ? opt->delta : 0.0;
     P->fp32 = opt->mode == EIK_MODE_FP32 ? 1 : 0;
     P->cell_value = opt->cell_value;
@@ -982,11 +985,11 @@ int eik_autotune(const int64_t dims[3], double h, const void* F, int f_dtype,
         if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(e);
     std::vector<eik_tune_entry> cand;
     const int cells[3] = {8, 4, 16};
-    const int inners[3] = {EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL};
+    const int inners[4] = {EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL, EIK_INNER_PAIR};
     for (int cell : cells)
         for (int inner : inners)
             for (int workers : {0, ncu / 2}) {
-                if (inner == EIK_INNER_DUAL && cell == 16) continue;
+                if ((inner == EIK_INNER_DUAL || inner == EIK_INNER_PAIR) && cell == 16) continue;
                 eik_tune_entry t;
                 std::memset(&t, 0, sizeof(t));
                 t.cell = cell;

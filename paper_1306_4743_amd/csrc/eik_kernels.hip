@@ -364,13 +364,15 @@ __device__ __forceinline__ void face_node(int f, int a, int b, int& x, int& y, i
 constexpr int INNER_SWEEP = 0;  // locking sweeps in diagonal-plane order (Algorithm 2)
 constexpr int INNER_LIST = 1;   // relaxation over a compacted list of active nodes
 constexpr int INNER_DUAL = 2;   // two sweep streams on one cell, half a sweep apart
+constexpr int INNER_PAIR = 3;   // two cells swept by one wave, half a sweep apart
 
 template <int R, int INNER, typename UT>
 struct WaveLds {
     static constexpr int B = R + 2;
     static constexpr int BOX = B * B * B;
-    UT U[BOX];            // cell values with a one-node halo (edges/corners unused)
-    UT S[R * R * R];      // s = h/F; -1 marks an exit node, 0 a padding node
+    static constexpr int NC = INNER == INNER_PAIR ? 2 : 1;  // cells held by the wave
+    UT U[NC * BOX];       // cell values with a one-node halo (edges/corners unused), per cell
+    UT S[NC * R * R * R]; // s = h/F; -1 marks an exit node, 0 a padding node
     int32_t q[64];        // cells newly queued for the next round, not yet published
     uint16_t lst[INNER == INNER_LIST ? 2 : 0][R * R * R];  // lists of the list relaxation
     uint8_t A[INNER == INNER_DUAL ? ((BOX + 7) & ~7) : 0];  // active flags of the dual sweep
@@ -406,7 +408,8 @@ __device__ __forceinline__ uint32_t reflect_mask(int d) {
 // once per kernel.
 template <int R, int INNER>
 struct PlaneRegs {
-    static constexpr int NS = INNER == INNER_DUAL ? 3 * R - 2 : PlaneTable<R>::NSTEP;
+    static constexpr int NS =
+        (INNER == INNER_DUAL || INNER == INNER_PAIR) ? 3 * R - 2 : PlaneTable<R>::NSTEP;
     uint32_t pk[(NS + 1) / 2];
     uint32_t valid[(NS + 31) / 32];
     int dummy;  // this lane's scratch slot: a box node on a halo edge, never read
@@ -415,9 +418,10 @@ struct PlaneRegs {
 
 template <int R, int INNER>
 __device__ __forceinline__ void load_plane_regs(PlaneRegs<R, INNER>& pr, int lane) {
-    static_assert(INNER != INNER_DUAL || R <= 8, "two sweep streams fit one wave up to r = 8");
+    static_assert((INNER != INNER_DUAL && INNER != INNER_PAIR) || R <= 8,
+                  "two sweep streams fit one wave up to r = 8");
     const uint16_t* slots;
-    if constexpr (INNER == INNER_DUAL) slots = dual_slots<R>();
+    if constexpr (INNER == INNER_DUAL || INNER == INNER_PAIR) slots = dual_slots<R>();
     else slots = plane_slots<R>();
     // Halo edges: lines where two coordinates are -1 or R (12 R nodes); lane -> one of them.
     {
@@ -814,9 +818,9 @@ __device__ __forceinline__ int face_step(int f) {
 
 // Stage-in of one cell into the wave's LDS: cell values, s = h/F and the halo (the
 // neighbours' opposite face copies, +inf beyond the grid).
-template <int R, typename FT, int INNER, typename UT, bool ASYNC>
-__device__ __forceinline__ void stage_cell(const Slot& S, int lc, CellXYZ cc,
-                                           WaveLds<R, INNER, UT>& L, int lane) {
+template <int R, typename FT, typename UT, bool ASYNC>
+__device__ __forceinline__ void stage_cell(const Slot& S, int lc, CellXYZ cc, UT* __restrict__ U,
+                                           UT* __restrict__ Sv, int lane) {
     constexpr int R2 = R * R, R3 = R * R * R;
     constexpr int FPL = (R2 + 63) / 64;
     const UT INF = (UT)__builtin_inf();
@@ -858,9 +862,9 @@ __device__ __forceinline__ void stage_cell(const Slot& S, int lc, CellXYZ cc,
         for (int k = 0; k < CH; ++k) {
             const int l = lane + 64 * (k0 + k);
             const int x = l % R, y = (l / R) % R, z = l / R2;
-            L.U[box_index<R>(x, y, z)] = uv[k];
+            U[box_index<R>(x, y, z)] = uv[k];
             // s = h / F formed in FP64 and rounded once to the value type.
-            L.S[l] = fv[k] > FT(0) ? (UT)(S.h / (double)fv[k])
+            Sv[l] = fv[k] > FT(0) ? (UT)(S.h / (double)fv[k])
                                    : (fv[k] < FT(0) ? UT(-1) : UT(0));
         }
     }
@@ -872,11 +876,88 @@ __device__ __forceinline__ void stage_cell(const Slot& S, int lc, CellXYZ cc,
             if (e < R2) {
                 int x, y, z;
                 face_node<R>(f, e % R, e / R, x, y, z);
-                L.U[box_index<R>(x, y, z) + face_step<R>(f)] = hv[f][j];
+                U[box_index<R>(x, y, z) + face_step<R>(f)] = hv[f][j];
             }
         }
     }
     wave_sync();
+}
+
+// Write-back of one visited cell whose box (with halo) is U: the cell's values (with their
+// active flags if keep_active), every face copy with a decreased border node, and the tag of each
+// neighbour across a face with new inflow (eq. (3) value: the smallest newly decreased border
+// value below the neighbour's value; eq. (4): the largest one plus the time to the middle of the
+// neighbour).  Lane tag_base + f takes the tag of face f.
+template <int R, typename FT, typename UT, bool ASYNC>
+__device__ __forceinline__ void publish_cell(const SolveParams& P, const Slot& S, int lc,
+                                             CellXYZ cc, const UT* __restrict__ U,
+                                             const UT (&before)[6][(R * R + 63) / 64],
+                                             bool visit_changed, bool keep_active, int lane,
+                                             int tag_base, bool& my_tag, int& my_target,
+                                             uint32_t& my_bits, double& my_value) {
+    constexpr int R2 = R * R, R3 = R * R * R;
+    constexpr int FPL = (R2 + 63) / 64;
+    const UT INF = (UT)__builtin_inf();
+    if (!visit_changed) return;
+    UT* __restrict__ uw = reinterpret_cast<UT*>(S.u) + (size_t)lc * R3;
+    UT* __restrict__ fw = reinterpret_cast<UT*>(S.faces);
+    for (int l = lane; l < R3; l += 64) {
+        const int x = l % R, y = (l / R) % R, z = l / R2;
+        const UT v = U[box_index<R>(x, y, z)];
+        st_val<ASYNC>(&uw[l], keep_active ? v : fabs(v));
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int nb = cell_neighbour(S, lc, cc, f);
+        bool ch = false, inflow = false;
+        UT v[FPL], in_min = INF, in_max = -INF;
+#pragma unroll
+        for (int j = 0; j < FPL; ++j) {
+            const int e = lane + 64 * j;
+            v[j] = INF;
+            if (e < R2) {
+                int x, y, z;
+                face_node<R>(f, e % R, e / R, x, y, z);
+                const int b = box_index<R>(x, y, z);
+                v[j] = fabs(U[b]);
+                const bool chj = v[j] < before[f][j];
+                const bool inj = chj && v[j] < fabs(U[b + face_step<R>(f)]);
+                ch |= chj;
+                inflow |= inj;
+                in_min = inj ? vmin(in_min, v[j]) : in_min;
+                in_max = inj ? vmax(in_max, v[j]) : in_max;
+            }
+        }
+        if (__any(ch)) {
+#pragma unroll
+            for (int j = 0; j < FPL; ++j)
+                if (lane + 64 * j < R2)
+                    st_val<ASYNC>(&fw[((size_t)lc * 6 + f) * R2 + lane + 64 * j], v[j]);
+        }
+        if (nb >= 0 && __any(inflow)) {
+            double kv = (double)wave_min(in_min);
+            if (P.cell_value) {
+                kv = (double)wave_max(in_max);
+                if (lane == tag_base + f) {
+                    const CellXYZ nc = cell_coords(S, nb);
+                    const int ex = min(R, S.nx - nc.x * R), ey = min(R, S.ny - nc.y * R),
+                              ez = min(R, S.nz - nc.z * R);
+                    const int mx = min(R / 2, ex - 1), my = min(R / 2, ey - 1),
+                              mz = min(R / 2, ez - 1);
+                    const double fv = (double)reinterpret_cast<const FT*>(S.f)[
+                        (size_t)nb * R3 + mx + R * (my + R * mz)];
+                    if (fv > 0.0) kv += 0.5 * (R * S.h + S.h) / fv;
+                }
+            }
+            if (lane == tag_base + f) {
+                const int g = f ^ 1;
+                my_tag = true;
+                my_target = S.cell_base + nb;
+                my_bits = (1u << g) | (pref_mask_for_face(g) << FL_DIR_SHIFT);
+                my_value = kv;
+            }
+        }
+    }
 }
 
 template <int R, typename FT, int INNER, typename UT, bool ASYNC = false>
@@ -899,7 +980,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
     const Slot S = P.slots[slot];
     const int lc = c - S.cell_base;
     const CellXYZ cc = cell_coords(S, lc);
-    stage_cell<R, FT, INNER, UT, ASYNC>(S, lc, cc, L, lane);
+    stage_cell<R, FT, UT, ASYNC>(S, lc, cc, L.U, L.S, lane);
     // Border values before the visit (every visit publishes its border, so these equal the
     // published face copies; a border node below them has decreased), then the initial active
     // set: every node on a first visit, otherwise the layer next to each face that received new
@@ -1245,72 +1326,8 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
     // (Publishing the partial result lets the neighbours start a round earlier; measured, that
     // beats holding it back until the cell completes.)
     const bool keep_active = requeue && INNER != INNER_DUAL;
-    if (visit_changed) {
-        UT* __restrict__ uw = reinterpret_cast<UT*>(S.u) + (size_t)lc * R3;
-        UT* __restrict__ fw = reinterpret_cast<UT*>(S.faces);
-        for (int l = lane; l < R3; l += 64) {
-            const int x = l % R, y = (l / R) % R, z = l / R2;
-            const UT v = L.U[box_index<R>(x, y, z)];
-            st_val<ASYNC>(&uw[l], keep_active ? v : fabs(v));
-        }
-        {
-#pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                const int nb = cell_neighbour(S, lc, cc, f);
-                bool ch = false, inflow = false;
-                UT v[FPL], in_min = INF, in_max = -INF;
-#pragma unroll
-                for (int j = 0; j < FPL; ++j) {
-                    const int e = lane + 64 * j;
-                    v[j] = INF;
-                    if (e < R2) {
-                        int x, y, z;
-                        face_node<R>(f, e % R, e / R, x, y, z);
-                        const int b = box_index<R>(x, y, z);
-                        v[j] = fabs(L.U[b]);
-                        const bool chj = v[j] < before[f][j];
-                        const bool inj = chj && v[j] < fabs(L.U[b + face_step<R>(f)]);
-                        ch |= chj;
-                        inflow |= inj;
-                        in_min = inj ? vmin(in_min, v[j]) : in_min;
-                        in_max = inj ? vmax(in_max, v[j]) : in_max;
-                    }
-                }
-                if (__any(ch)) {
-#pragma unroll
-                    for (int j = 0; j < FPL; ++j)
-                        if (lane + 64 * j < R2)
-                            st_val<ASYNC>(&fw[((size_t)lc * 6 + f) * R2 + lane + 64 * j], v[j]);
-                }
-                if (nb >= 0 && __any(inflow)) {
-                    // eq. (3): the smallest newly decreased inflow value; eq. (4): the largest
-                    // one plus the time to reach the middle of the neighbour, (r h + h) / 2 at
-                    // the speed there (its middle node, or the nearest node inside the grid).
-                    double kv = (double)wave_min(in_min);
-                    if (P.cell_value) {
-                        kv = (double)wave_max(in_max);
-                        if (lane == f) {
-                            const CellXYZ nc = cell_coords(S, nb);
-                            const int ex = min(R, S.nx - nc.x * R), ey = min(R, S.ny - nc.y * R),
-                                      ez = min(R, S.nz - nc.z * R);
-                            const int mx = min(R / 2, ex - 1), my = min(R / 2, ey - 1),
-                                      mz = min(R / 2, ez - 1);
-                            const double fv = (double)reinterpret_cast<const FT*>(S.f)[
-                                (size_t)nb * R3 + mx + R * (my + R * mz)];
-                            if (fv > 0.0) kv += 0.5 * (R * S.h + S.h) / fv;
-                        }
-                    }
-                    if (lane == f) {
-                        const int g = f ^ 1;
-                        my_tag = true;
-                        my_target = S.cell_base + nb;
-                        my_bits = (1u << g) | (pref_mask_for_face(g) << FL_DIR_SHIFT);
-                        my_value = kv;
-                    }
-                }
-            }
-        }
-    }
+    publish_cell<R, FT, UT, ASYNC>(P, S, lc, cc, L.U, before, visit_changed, keep_active, lane, 0,
+                                   my_tag, my_target, my_bits, my_value);
     if (requeue) {
         if (lane == 6) {
             my_tag = true;
@@ -1327,6 +1344,244 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
         tag_lanes<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits,
                                 my_value, slot);
     }
+    const unsigned long long t3 = cycles();
+    cnt.cyc_stage += t1 - t0;
+    cnt.cyc_sweep += t2 - t1;
+    cnt.cyc_write += t3 - t2;
+}
+
+// ------------------------------------------------------------------------------------------
+// One visit of two cells by one wave (INNER_PAIR): both are staged side by side in the wave's
+// LDS and swept at once with the two-stream plane table -- at step t the lanes of stream 0 take
+// plane t of cell 0's current sweep and the lanes of stream 1 plane (t + H) mod NP of cell 1's,
+// at most 49 nodes at r = 8 -- so a wave instruction updates up to twice the nodes of a
+// one-cell sweep.  Each cell has its own direction sequence, sweep count, stop test and cap, as
+// in visit_cell; the cells are independent (their boxes are disjoint and a wave visits them
+// within one round, like two workers would), so the locking sweeps of each are exactly those of
+// a one-cell visit.  Cell 1 may be absent (c1 < 0).
+
+template <int R, typename FT, typename UT>
+__device__ __forceinline__ void visit_pair(const SolveParams& P, int c0, int slot0, uint32_t fl0,
+                                           double key0, int c1, int slot1, uint32_t fl1,
+                                           double key1, WaveLds<R, INNER_PAIR, UT>& L,
+                                           const PlaneRegs<R, INNER_PAIR>& pr, int lane,
+                                           RoundCtl* ctl_next, int nxt, VisitCounters& cnt,
+                                           WaveQueue& wq, uint32_t (&sweeps_out)[2]) {
+    constexpr int R2 = R * R, R3 = R * R * R, B = R + 2, NP = 3 * R - 2, H = NP / 2;
+    constexpr int BOX = WaveLds<R, INNER_PAIR, UT>::BOX;
+    static_assert(R2 <= 64, "one face node per lane");
+    const UT INF = (UT)__builtin_inf();
+    const unsigned long long t0 = cycles();
+    const int cc_[2] = {__builtin_amdgcn_readfirstlane(c0), __builtin_amdgcn_readfirstlane(c1)};
+    const int sl_[2] = {__builtin_amdgcn_readfirstlane(slot0),
+                        __builtin_amdgcn_readfirstlane(slot1)};
+    const uint32_t fl_[2] = {fl0, fl1};
+    const bool has1 = cc_[1] >= 0;
+    Slot S_[2];
+    int lc_[2];
+    CellXYZ xyz_[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int ck = k == 0 || has1 ? cc_[k] : cc_[0];
+        S_[k] = P.slots[k == 0 || has1 ? sl_[k] : sl_[0]];
+        lc_[k] = ck - S_[k].cell_base;
+        xyz_[k] = cell_coords(S_[k], lc_[k]);
+    }
+    stage_cell<R, FT, UT, false>(S_[0], lc_[0], xyz_[0], L.U, L.S, lane);
+    if (has1) {
+        stage_cell<R, FT, UT, false>(S_[1], lc_[1], xyz_[1], L.U + BOX, L.S + R3, lane);
+    } else {
+        for (int l = lane; l < R3; l += 64) L.S[R3 + l] = UT(0);  // no live node in the box
+    }
+    wave_sync();
+    // Border values before the visit, then the initial active sets (as in visit_cell).
+    UT before[2][6][1];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            before[k][f][0] = INF;
+            if (lane < R2) {
+                int x, y, z;
+                face_node<R>(f, lane % R, lane / R, x, y, z);
+                before[k][f][0] = fabs(L.U[k * BOX + box_index<R>(x, y, z)]);
+            }
+        }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && !has1) continue;
+        UT* Uk = L.U + k * BOX;
+        const UT* Sk = L.S + k * R3;
+        if (fl_[k] & FL_ALL) {
+            for (int l = lane; l < R3; l += 64) {
+                const int x = l % R, y = (l / R) % R, z = l / R2;
+                if (Sk[l] > UT(0)) Uk[box_index<R>(x, y, z)] = -fabs(Uk[box_index<R>(x, y, z)]);
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                if ((fl_[k] & (1u << f)) && lane < R2) {
+                    int x, y, z;
+                    face_node<R>(f, lane % R, lane / R, x, y, z);
+                    if (Sk[x + R * (y + R * z)] > UT(0)) {
+                        const int b = box_index<R>(x, y, z);
+                        Uk[b] = -fabs(Uk[b]);
+                    }
+                }
+            }
+        }
+    }
+    wave_sync();
+
+    const unsigned long long t1 = cycles();
+    const bool track_dec = S_[0].tol > 0.0 || (has1 && S_[1].tol > 0.0);
+    // Per cell: preferred directions (taken first, in Gray order), Gray-cycle position (a capped
+    // visit resumes there), running flag, sweeps, decreases, cap.
+    uint32_t pref[2], nsw[2] = {0, 0};
+    int pi[2] = {0, 0}, ci[2], last_gi[2] = {0, 0}, dir[2] = {0, 0};
+    bool run[2] = {true, has1}, inflight[2] = {false, false}, vchg[2] = {false, false};
+    bool requeue[2] = {false, false};
+    uint32_t requeue_bits[2] = {0u, 0u};
+    uint64_t chg[2] = {0ull, 0ull};
+    UT maxdec[2] = {UT(0), UT(0)};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        pref[k] = (fl_[k] >> FL_DIR_SHIFT) & 0xFFu;
+        ci[k] = (fl_[k] & FL_GRAY_SET) ? (int)((fl_[k] >> FL_GRAY_SHIFT) & 7u) : 0;
+    }
+    auto next_dir = [&](int k) {
+        while (pi[k] < 8) {
+            const int gi = pi[k]++;
+            if (pref[k] & (1u << kGray[gi])) {
+                last_gi[k] = gi;
+                return kGray[gi];
+            }
+        }
+        last_gi[k] = ci[k] & 7;
+        ++ci[k];
+        return kGray[last_gi[k]];
+    };
+    // End of a sweep of cell k: stop when it changed nothing, when no node is left active, when
+    // its largest decrease is within tol, or at the sweep cap (re-queued, resuming the cycle).
+    auto end_sweep = [&](int k) {
+        inflight[k] = false;
+        ++nsw[k];
+        if (chg[k] == 0ull) {
+            run[k] = false;
+            return;
+        }
+        vchg[k] = true;
+        const UT* Uk = L.U + k * BOX;
+        bool left = false;
+        for (int l = lane; l < R3; l += 64) {
+            const int x = l % R, y = (l / R) % R, z = l / R2;
+            left |= is_active(Uk[box_index<R>(x, y, z)]);
+        }
+        if (!__any(left)) {
+            run[k] = false;
+            return;
+        }
+        if (track_dec && (double)wave_max(maxdec[k]) <= S_[k].tol) {
+            run[k] = false;
+            return;
+        }
+        if ((int)nsw[k] >= P.max_sweeps) {
+            run[k] = false;
+            requeue[k] = true;
+            requeue_bits[k] = FL_GRAY_SET | ((uint32_t)((last_gi[k] + 1) & 7) << FL_GRAY_SHIFT);
+        }
+    };
+    unsigned int upd = 0;
+    while (run[0] || run[1]) {
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+            if (t == 0 && run[0]) {
+                dir[0] = next_dir(0);
+                inflight[0] = true;
+                chg[0] = 0ull;
+                maxdec[0] = UT(0);
+            }
+            if (t == H && run[1]) {
+                dir[1] = next_dir(1);
+                inflight[1] = true;
+                chg[1] = 0ull;
+                maxdec[1] = UT(0);
+            }
+            const uint32_t mref0 = reflect_mask<R>(dir[0]), mref1 = reflect_mask<R>(dir[1]);
+            uint32_t e = (pr.pk[t >> 1] >> ((t & 1) * 16)) & 0xFFFFu;
+            asm volatile("" : "+v"(e));
+            const bool st1 = (e & 0x8000u) != 0u;
+            const uint32_t lr = (e & 0x7FFFu) ^ (st1 ? mref1 : mref0);
+            const int b = box_of_cell_index<R>(lr) + (st1 ? BOX : 0);
+            const int l = (int)lr + (st1 ? R3 : 0);
+            UT raw = L.U[b];
+            UT sv = L.S[l];
+            UT xm = L.U[b - 1], xp = L.U[b + 1];
+            UT ym = L.U[b - B], yp = L.U[b + B];
+            UT zm = L.U[b - B * B], zp = L.U[b + B * B];
+            asm volatile("" : "+v"(raw), "+v"(sv), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
+                         "+v"(zm), "+v"(zp));
+            const bool on = st1 ? inflight[1] : inflight[0];
+            const bool act = pr.has(t) && on && is_active(raw);
+            if (__any(act)) {
+                const UT old = fabs(raw);
+                const UT g = local_solve(vmin_abs(xm, xp), vmin_abs(ym, yp), vmin_abs(zm, zp), sv);
+                const bool live = act && sv > UT(0);
+                const bool dec = live && g < old;
+                upd += (unsigned)__popcll(__ballot(live));  // wave total, scalar unit
+                UT* const ub = &L.U[b];
+                if (act) ub[0] = dec ? g : old;
+                const uint64_t decm = __ballot(dec), st1m = __ballot(st1);
+                chg[0] |= decm & ~st1m;
+                chg[1] |= decm & st1m;
+                if (track_dec && dec) {
+                    if (st1) maxdec[1] = vmax(maxdec[1], old - g);
+                    else maxdec[0] = vmax(maxdec[0], old - g);
+                }
+                if (dec && xm > g) mark_active(ub - 1, xm);
+                if (dec && xp > g) mark_active(ub + 1, xp);
+                if (dec && ym > g) mark_active(ub - B, ym);
+                if (dec && yp > g) mark_active(ub + B, yp);
+                if (dec && zm > g) mark_active(ub - B * B, zm);
+                if (dec && zp > g) mark_active(ub + B * B, zp);
+            }
+            wave_sync();
+            if (t == NP - 1 && inflight[0]) end_sweep(0);
+            if (t == H - 1 && inflight[1]) end_sweep(1);
+            if (!run[0] && !run[1] && !inflight[0] && !inflight[1]) break;
+        }
+    }
+    cnt.sweeps += (unsigned long long)(nsw[0] + nsw[1]);
+    cnt.updates += upd;
+    sweeps_out[0] = nsw[0];
+    sweeps_out[1] = nsw[1];
+    const unsigned long long t2 = cycles();
+
+    // Write-back of each cell; lanes 0-5 tag across the faces of cell 0, lanes 8-13 across those
+    // of cell 1; lanes 6 and 14 re-queue a capped cell.
+    bool my_tag = false;
+    int my_target = 0;
+    uint32_t my_bits = 0;
+    double my_value = __builtin_inf();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && !has1) continue;
+        publish_cell<R, FT, UT, false>(P, S_[k], lc_[k], xyz_[k], L.U + k * BOX, before[k],
+                                       vchg[k], requeue[k], lane, 8 * k, my_tag, my_target,
+                                       my_bits, my_value);
+        if (requeue[k]) {
+            if (lane == 8 * k + 6) {
+                my_tag = true;
+                my_target = cc_[k];
+                my_bits = requeue_bits[k];
+                my_value = k == 0 ? key0 : key1;
+            }
+            cnt.requeued += 1;
+        }
+    }
+    tag_lanes<R, INNER_PAIR, UT>(P, nxt, ctl_next, L, lane, wq, my_tag, my_target, my_bits,
+                                 my_value, has1 && sl_[0] != sl_[1] ? -1 : sl_[0]);
     const unsigned long long t3 = cycles();
     cnt.cyc_stage += t1 - t0;
     cnt.cyc_sweep += t2 - t1;
@@ -1376,7 +1631,8 @@ __device__ bool grid_barrier(const SolveParams& P) {
 
 template <int R, typename FT, int W, int INNER, typename UT>
 __global__ void __launch_bounds__(64 * W)
-    __attribute__((amdgpu_waves_per_eu(R == 16 ? 1 : (sizeof(UT) == 4 ? 4 : 3))))
+    __attribute__((amdgpu_waves_per_eu(R == 16 ? 1
+                                       : INNER == INNER_PAIR ? 2 : (sizeof(UT) == 4 ? 4 : 3))))
 k_solve(SolveParams P) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1435,9 +1691,13 @@ k_solve(SolveParams P) {
         const uint64_t* smk_cur = slot_band ? slot_minkeys(P, t) : nullptr;
         // Cells per pop: one when the list is short (balance), more when it is long (fewer
         // atomics on the shared cursor).
-        const uint32_t chunk = n >= (uint32_t)nwaves_total * 32u ? 8u
-                             : (n >= (uint32_t)nwaves_total * 8u ? 4u
-                             : (n >= (uint32_t)nwaves_total * 2u ? 2u : 1u));
+        // Cells per pop: one when the list is short (balance), more when it is long (fewer
+        // atomics on the shared cursor); a wave sweeping two cells at once takes at least two.
+        constexpr uint32_t kMinChunk = INNER == INNER_PAIR ? 2u : 1u;
+        uint32_t chunk = n >= (uint32_t)nwaves_total * 32u ? 8u
+                       : (n >= (uint32_t)nwaves_total * 8u ? 4u
+                       : (n >= (uint32_t)nwaves_total * 2u ? 2u : 1u));
+        if (chunk < kMinChunk) chunk = kMinChunk;
         WaveQueue wq{0, __builtin_inf()};
         uint32_t chunk_now = chunk;
         for (;;) {
@@ -1448,7 +1708,7 @@ k_solve(SolveParams P) {
             if (base >= n) { cyc_pop += cycles() - tp0; break; }
             const uint32_t cnt_here = n - base < chunk_now ? n - base : chunk_now;
             // The last cells of the round go one per pop, so that the round's tail is short.
-            if (n - base < (uint32_t)nwaves_total * 2u) chunk_now = 1u;
+            if (n - base < (uint32_t)nwaves_total * 2u) chunk_now = kMinChunk;
             // Lanes j < cnt_here take cell j of the chunk: its flags and value are exchanged
             // for empty ones (the removal of Algorithm 3 with V^c <- +inf).
             int my_c = 0, my_slot = 0;
@@ -1479,6 +1739,35 @@ k_solve(SolveParams P) {
             tag_lanes<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq, defer, my_c, my_fl & ~FL_QUEUED,
                          bitsd(my_kb), -1);
             cyc_pop += cycles() - tp0;
+            if constexpr (INNER == INNER_PAIR) {
+                // The cells of the chunk that were not deferred, two per visit.
+                uint64_t todo = ~defer_mask & ((1ull << cnt_here) - 1ull);
+                while (todo) {
+                    const int ja = __builtin_ctzll(todo);
+                    todo &= todo - 1ull;
+                    const int jb = todo ? __builtin_ctzll(todo) : -1;
+                    if (jb >= 0) todo &= todo - 1ull;
+                    const int jj = jb >= 0 ? jb : ja;
+                    const int ca = __shfl(my_c, ja, 64), cb = __shfl(my_c, jj, 64);
+                    const int sa = __shfl(my_slot, ja, 64), sb = __shfl(my_slot, jj, 64);
+                    const uint32_t fa = __shfl(my_fl, ja, 64), fb = __shfl(my_fl, jj, 64);
+                    const double ka = bitsd(__shfl(my_kb, ja, 64));
+                    const double kb2 = bitsd(__shfl(my_kb, jj, 64));
+                    const unsigned long long tv0 = cycles();
+                    uint32_t nsw[2] = {0u, 0u};
+                    visit_pair<R, FT, UT>(P, ca, sa, fa, ka, jb >= 0 ? cb : -1, sb, fb, kb2, L,
+                                          pr, lane, ctl_next, nxt, cnt, wq, nsw);
+                    visits += jb >= 0 ? 2 : 1;
+                    if (lane == 0) {
+                        const unsigned long long dt = cycles() - tv0;
+                        const int lg = dt ? 63 - __builtin_clzll(dt) : 0;
+                        for (int k = 0; k < (jb >= 0 ? 2 : 1); ++k) {
+                            atomicAdd(&s_hist[nsw[k] < 31 ? nsw[k] : 31], 1u);
+                            atomicAdd(&s_hist[32 + (lg < 31 ? lg : 31)], 1u);
+                        }
+                    }
+                }
+            } else
             for (uint32_t j = 0; j < cnt_here; ++j) {
                 const int c = __shfl(my_c, (int)j, 64);
                 const int cs = __shfl(my_slot, (int)j, 64);
@@ -1701,7 +1990,7 @@ k_solve_async(SolveParams P) {
             const int cs = __builtin_amdgcn_readfirstlane(P.cell_slot[c]);
             const Slot S = P.slots[cs];
             const int lc = (int)c - S.cell_base;
-            stage_cell<R, FT, INNER, UT, true>(S, lc, cell_coords(S, lc), L, lane);
+            stage_cell<R, FT, UT, true>(S, lc, cell_coords(S, lc), L.U, L.S, lane);
             const bool redo = cell_above_fixed_point<R, INNER, UT>(L, lane);
             wave_sync();
             tag_lanes_async(P, lane, redo && lane == 0, (int)c, FL_ALL, 0.0);
@@ -2055,7 +2344,8 @@ static hipError_t launch_solve_t(const SolveParams& P, hipStream_t s, int worker
 // workgroups).
 template <int R, int INNER, typename UT>
 constexpr int waves_per_group() {
-    constexpr int by_regs = sizeof(UT) == 4 ? 16 : 12;
+    // Two cells per wave need up to 256 registers: two waves per SIMD.
+    constexpr int by_regs = INNER == INNER_PAIR ? 8 : (sizeof(UT) == 4 ? 16 : 12);
     constexpr unsigned budget = (R == 16 ? 159u : 150u) * 1024u;
     constexpr int by_lds = (int)(budget / sizeof(WaveLds<R, INNER, UT>));
     return by_regs < by_lds ? by_regs : by_lds;
@@ -2070,10 +2360,16 @@ static hipError_t solve_rounds_ut(const SolveParams& P, hipStream_t s, int worke
     if (P.inner == INNER_LIST)
         return launch_solve_t<R, FT, waves_per_group<R, INNER_LIST, UT>(), INNER_LIST, UT,
                               ASYNCK>(P, s, workers, used, coop);
-    if constexpr (R <= 8)
-        return launch_solve_t<R, FT, waves_per_group<R, INNER_DUAL, UT>(), INNER_DUAL, UT,
-                              ASYNCK>(P, s, workers, used, coop);
-    return hipErrorInvalidValue;  // the host refuses two sweep streams at r = 16
+    if constexpr (R <= 8) {
+        if (P.inner == INNER_DUAL)
+            return launch_solve_t<R, FT, waves_per_group<R, INNER_DUAL, UT>(), INNER_DUAL, UT,
+                                  ASYNCK>(P, s, workers, used, coop);
+        // Two cells per wave are taken from the rounds' lists, not from the ring.
+        if (P.inner == INNER_PAIR && !ASYNCK)
+            return launch_solve_t<R, FT, waves_per_group<R, INNER_PAIR, UT>(), INNER_PAIR, UT,
+                                  false>(P, s, workers, used, coop);
+    }
+    return hipErrorInvalidValue;  // the host refuses two streams at r = 16 and pairs without rounds
 }
 
 template <int R, typename FT, bool ASYNCK = false>

@@ -21,7 +21,7 @@ EIK_EBUSY = -6
 EIK_ETOOBIG = -7
 EIK_F64, EIK_F32 = 0, 1
 EIK_MODE_FP64, EIK_MODE_FP32, EIK_MODE_MIXED = 0, 1, 2
-EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL = 1, 2, 3
+EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL, EIK_INNER_PAIR = 1, 2, 3, 4
 EIK_CELL_VALUE_NEW, EIK_CELL_VALUE_OLD = 0, 1
 EIK_SCHED_AUTO, EIK_SCHED_COOPERATIVE, EIK_SCHED_HOST_LOOP, EIK_SCHED_ASYNC = 0, 1, 2, 3
 

@@ -18,7 +18,7 @@ from paper_1306_4743_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 REL_TOL = 1e-10
-INNERS = [1, 2, 3]  # EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL
+INNERS = [1, 2, 3, 4]  # EIK_INNER_SWEEP, EIK_INNER_LIST, EIK_INNER_DUAL, EIK_INNER_PAIR
 
 
 @pytest.fixture(scope="module")

@@ -59,6 +59,18 @@ def test_random_configuration_cell16_matches_oracle(orc, case):
     run_case(orc, *draw16(case))
 
 
+def draw_pair(case: int):
+    """A case of the same recipe swept two cells per wave (cells of 4 and 8)."""
+    p, cfg = draw(80_000 + case)
+    cfg["inner"] = 4
+    return p, cfg
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_random_configuration_pair_matches_oracle(orc, case):
+    run_case(orc, *draw_pair(case))
+
+
 def run_case(orc, p, cfg):
     import torch
     from paper_1306_4743_amd import eik
