@@ -177,6 +177,10 @@ typedef struct eik_options {
     int cell_value;       /* EIK_CELL_VALUE_NEW (default) or EIK_CELL_VALUE_OLD; only the
                              priority band (delta) reads cell values                        */
     int schedule;         /* EIK_SCHED_*; default EIK_SCHED_AUTO                             */
+    uint64_t jitter;      /* 0 = none; otherwise seed of pseudo-random delays (0 to ~50 us)
+                             before every cell visit, which make the visits of a round, or of
+                             the ring, interleave in different orders (tests of the races that
+                             Section 5.1 declares benign); the result is the same             */
 } eik_options;
 
 /* Per-solve counters, filled by eik_stream_status(). */
@@ -273,6 +277,15 @@ int eik_problem_bytes(const int64_t dims[3], int cell, int f_dtype, int mode, si
  * enqueued on it (EIK_OK, EIK_EINVAL, EIK_ENOCONV, EIK_ECANCELLED) and, if stats != NULL,
  * its counters.  Returns EIK_EINVAL if no solve was ever enqueued on the stream. */
 int eik_stream_status(hipStream_t stream, eik_stats* stats);
+
+/* Asks every solve enqueued on `stream` so far (eik_solve, eik_solve_ex, eik_solve_batch) to
+ * stop: a running solve kernel stops at its next round boundary (or within a few visits without
+ * rounds) and the stream's status becomes EIK_ECANCELLED; u_out then holds an upper bound of
+ * the solution, as after any early stop.  Solves enqueued after the call are not affected.  The
+ * request is a store into host memory that the device reads; it does not wait.  Not for
+ * eik_solve_noalloc or servers.  Returns EIK_OK, or EIK_EINVAL if nothing was ever solved on
+ * the stream. */
+int eik_cancel(hipStream_t stream);
 
 /* Durations of the last n timed solves on `stream` (those enqueued with options.timing = 1),
  * oldest first: solve_ms[i] = the persistent solve kernel alone, total_ms[i] = the whole call

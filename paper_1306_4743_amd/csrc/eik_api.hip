@@ -178,6 +178,7 @@ int parse_options(const eik_options* options, int cell, eik_options* opt, SolveP
     P->cell_value = opt->cell_value;
     P->shuffle = opt->shuffle;
     P->watchdog_polls = 1ull << 23;  // several seconds of polling
+    P->jitter = opt->jitter;
     P->round_log = opt->round_log;
     P->round_log_len = opt->round_log ? opt->round_log_len : 0;
     return EIK_OK;
@@ -457,6 +458,12 @@ struct Workspace {
     std::vector<hipEvent_t> ring;  // 4 events per timed solve
     int64_t timed = 0;
     int64_t seq = 0;  // order of the last solve enqueued with this workspace (see g_seq)
+    // Cancel word in host memory mapped into the device (eik_cancel): solve k of this
+    // workspace stops once the word is >= k.  eik_cancel reads these without the workspace's
+    // mutex, which a host-driven solve holds for its whole duration.
+    std::atomic<uint32_t*> cancel_host{nullptr};
+    uint32_t* cancel_dev = nullptr;
+    std::atomic<uint32_t> cancel_seq{0};
 };
 
 // Sequence number of solves enqueued by the process: tells which of a stream's workspace solve
@@ -629,8 +636,22 @@ int solve_batch_impl(int n, const eik_problem* pbs, int f_dtype, int cell, hipSt
     std::lock_guard<std::mutex> lk(w->mu);
     rc = ensure_device(&w->base, &w->bytes, L.total + grid_bytes, stream);
     if (rc != EIK_OK) return rc;
+    if (!w->cancel_host.load()) {
+        uint32_t* hostw = nullptr;
+        hipError_t ec = hipHostMalloc((void**)&hostw, 64,
+                                      hipHostMallocMapped | hipHostMallocCoherent);
+        if (ec == hipSuccess) ec = hipHostGetDevicePointer((void**)&w->cancel_dev, hostw, 0);
+        if (ec != hipSuccess) {
+            if (hostw) (void)hipHostFree(hostw);
+            return hip_fail(ec);
+        }
+        __atomic_store_n(hostw, 0u, __ATOMIC_SEQ_CST);
+        w->cancel_host.store(hostw);
+    }
     unsigned char* base = (unsigned char*)w->base;
     bind_common(&P, base, L, cells);
+    P.cancel = w->cancel_dev;
+    P.cancel_seq = ++w->cancel_seq;
     P.slot_band = n > 1;  // a band per grid: the grids of a batch advance side by side
     int* slot_status = (int*)(base + L.off_slot_status);
 
@@ -1114,6 +1135,15 @@ int eik_batch_status(hipStream_t stream, int n, int* status) {
     return n;
 }
 
+int eik_cancel(hipStream_t stream) {
+    Workspace* w = find_workspace(stream);
+    if (!w) return EIK_EINVAL;
+    uint32_t* word = w->cancel_host.load();
+    if (!word) return EIK_EINVAL;
+    __atomic_store_n(word, w->cancel_seq.load(), __ATOMIC_SEQ_CST);
+    return EIK_OK;
+}
+
 int eik_kernel_times(hipStream_t stream, int n, double* solve_ms, double* total_ms) {
     if (n < 0) return EIK_EINVAL;
     Workspace* w = find_workspace(stream);
@@ -1163,6 +1193,7 @@ void eik_release(void) {
         (void)hipSetDevice(w->device);
         w->staging.release();
         if (w->base) (void)hipFree(w->base);
+        if (w->cancel_host.load()) (void)hipHostFree(w->cancel_host.load());
         for (auto& x : w->ring)
             if (x) (void)hipEventDestroy(x);
         delete w;

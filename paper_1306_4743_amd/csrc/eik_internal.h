@@ -116,6 +116,11 @@ struct SolveParams {
     unsigned long long* async_tail;     // next position to push
     unsigned long long* async_pending;  // cells queued or being visited
     uint32_t* async_done;               // set when async_pending reaches 0
+    // Race-detection aids: a host-mapped cancel word (a solve stops once it holds a sequence
+    // number >= cancel_seq) and a seed of pseudo-random delays before each visit (0 = none).
+    const uint32_t* cancel;
+    uint32_t cancel_seq;
+    uint64_t jitter;
     unsigned long long* bq_ctl;         // bucket heads, tails and the lowest bucket (or null)
     int32_t* bq_ring;                   // kBuckets rings of bq_cap 64-bit words (lap, cell)
     int64_t bq_cap;

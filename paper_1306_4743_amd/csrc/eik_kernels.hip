@@ -573,6 +573,26 @@ __device__ __forceinline__ void tag_lanes(const SolveParams& P, int nxt, RoundCt
 // cell can be popped, a visit subtracts only after its own pushes, so it reaches 0 exactly when
 // no work is left (the pHCM's active cell count, decremented after propagation).
 
+// Whether the host asked this solve to stop (eik_cancel): the cancel word lives in host memory
+// mapped into the device's address space, so it is read at system scope.
+__device__ __forceinline__ bool cancel_requested(const SolveParams& P) {
+    return P.cancel &&
+           __hip_atomic_load(P.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) >= P.cancel_seq;
+}
+
+// A pseudo-random delay of 0 to 31 short sleeps (up to about 50 us) before a visit when jitter is
+// on: the visits of a round and of a ring then interleave in ever different orders, as uneven
+// processor speeds do on a CPU.
+__device__ __forceinline__ void jitter_delay(const SolveParams& P, uint64_t salt) {
+    if (!P.jitter) return;
+    uint64_t z = P.jitter + salt * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const int n = (int)__builtin_amdgcn_readfirstlane((uint32_t)(z & 31u));
+    for (int i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(63);
+}
+
 __device__ __forceinline__ void async_cancel(const SolveParams& P) {
     atomicCAS(P.status, 0, EIK_ECANCELLED_DEV);
     __hip_atomic_store(P.async_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1662,6 +1682,8 @@ k_solve(SolveParams P) {
                                                   __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t was_halted = __hip_atomic_load(P.halted, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_AGENT);
+            if (blockIdx.x == 0 && threadIdx.x == 0 && !was_halted && cancel_requested(P))
+                atomicCAS(P.status, 0, EIK_ECANCELLED_DEV);  // seen by this or the next launch
             const int st0 = __hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const bool stop = was_halted || n0 == 0 || st0 != 0 || t >= P.max_rounds;
             if (blockIdx.x == 0 && threadIdx.x == 0 && !was_halted) {
@@ -1753,6 +1775,8 @@ k_solve(SolveParams P) {
                     const uint32_t fa = __shfl(my_fl, ja, 64), fb = __shfl(my_fl, jj, 64);
                     const double ka = bitsd(__shfl(my_kb, ja, 64));
                     const double kb2 = bitsd(__shfl(my_kb, jj, 64));
+                    jitter_delay(P, ((uint64_t)t << 40) ^ ((uint64_t)blockIdx.x << 20) ^
+                                        ((uint64_t)wave << 12) ^ visits);
                     const unsigned long long tv0 = cycles();
                     uint32_t nsw[2] = {0u, 0u};
                     visit_pair<R, FT, UT>(P, ca, sa, fa, ka, jb >= 0 ? cb : -1, sb, fb, kb2, L,
@@ -1774,6 +1798,8 @@ k_solve(SolveParams P) {
                 const uint32_t fl = __shfl(my_fl, (int)j, 64);
                 const double key = bitsd(__shfl(my_kb, (int)j, 64));
                 if ((defer_mask >> j) & 1ull) continue;
+                jitter_delay(P, ((uint64_t)t << 40) ^ ((uint64_t)blockIdx.x << 20) ^
+                                    ((uint64_t)wave << 12) ^ visits);
                 ++visits;
                 const unsigned long long sw0 = cnt.sweeps, tv0 = cycles();
                 visit_cell<R, FT, INNER, UT>(P, c, cs, fl, key, L, pr, lane, ctl_next, nxt, cnt,
@@ -1802,6 +1828,10 @@ k_solve(SolveParams P) {
             }
             break;
         }
+        // The host's cancel request is read by one thread before the barrier, so every
+        // workgroup sees the resulting status after it and all leave in the same round.
+        if (blockIdx.x == 0 && threadIdx.x == 0 && cancel_requested(P))
+            atomicCAS(P.status, 0, EIK_ECANCELLED_DEV);
         const bool ok = grid_barrier(P);
         cyc_wait += cycles() - tw0;
         if (blockIdx.x == 0 && threadIdx.x == 0 && t < P.round_log_len) {
@@ -1951,6 +1981,8 @@ k_solve_async(SolveParams P) {
             kb = __shfl(kb, 0, 64);
             mem_wait();  // the exchange has returned before the visit reads the cell
             cyc_pop += cycles() - tp0;
+            if (lane == 0 && (visits & 15) == 0 && cancel_requested(P)) async_cancel(P);
+            jitter_delay(P, ((uint64_t)blockIdx.x << 20) ^ ((uint64_t)wave << 12) ^ visits);
             ++visits;
             const unsigned long long sw0 = cnt.sweeps, tv0 = cycles();
             WaveQueue wq{0, __builtin_inf()};

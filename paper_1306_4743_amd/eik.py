@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
                 ("max_rounds", ctypes.c_int64), ("max_sweeps", ctypes.c_int),
                 ("workers", ctypes.c_int), ("shuffle", ctypes.c_uint64), ("timing", ctypes.c_int),
                 ("round_log", ctypes.c_void_p), ("round_log_len", ctypes.c_int64),
-                ("inner", ctypes.c_int), ("cell_value", ctypes.c_int), ("schedule", ctypes.c_int)]
+                ("inner", ctypes.c_int), ("cell_value", ctypes.c_int), ("schedule", ctypes.c_int),
+                ("jitter", ctypes.c_uint64)]
 
 
 class Problem(ctypes.Structure):
@@ -77,7 +78,7 @@ class Stats(ctypes.Structure):
 _lib = None
 
 # Every symbol declared in include/eik.h.
-EXPORTS = ("eik_solve", "eik_solve_ex", "eik_solve_noalloc", "eik_query_workspace", "eik_problem_bytes",
+EXPORTS = ("eik_solve", "eik_solve_ex", "eik_solve_noalloc", "eik_cancel", "eik_query_workspace", "eik_problem_bytes",
            "eik_stream_status", "eik_kernel_times", "eik_solve_batch", "eik_batch_status",
            "eik_server_create", "eik_server_submit", "eik_server_step", "eik_server_poll",
            "eik_server_load", "eik_server_destroy", "eik_server_polish_redone", "eik_autotune",
@@ -106,6 +107,8 @@ def load():
     lib.eik_query_workspace.restype = i32
     lib.eik_stream_status.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.eik_stream_status.restype = i32
+    lib.eik_cancel.argtypes = [vp]
+    lib.eik_cancel.restype = i32
     lib.eik_kernel_times.argtypes = [vp, i32, vp, vp]
     lib.eik_kernel_times.restype = i32
     lib.eik_strerror.argtypes = [i32]
@@ -247,7 +250,7 @@ def _sources(F, idx3, q, stream):
 
 def _options(delta=0.0, max_rounds=0, max_sweeps=0, workers=0, shuffle=0, timing=False,
              round_log=None, inner=0, mode=EIK_MODE_FP64, cell_value=EIK_CELL_VALUE_NEW,
-             schedule=EIK_SCHED_AUTO):
+             schedule=EIK_SCHED_AUTO, jitter=0):
     rl_ptr, rl_len = None, 0
     if round_log is not None:
         import torch
@@ -256,7 +259,7 @@ def _options(delta=0.0, max_rounds=0, max_sweeps=0, workers=0, shuffle=0, timing
         rl_ptr, rl_len = round_log.data_ptr(), round_log.numel() // 2
     return Options(int(mode), float(delta), int(max_rounds), int(max_sweeps), int(workers),
                    int(shuffle), int(bool(timing)), rl_ptr, rl_len, int(inner),
-                   int(cell_value), int(schedule))
+                   int(cell_value), int(schedule), int(jitter))
 
 
 def _approx(F, u_approx):
@@ -285,7 +288,7 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
           delta: float = 0.0, max_rounds: int = 0, max_sweeps: int = 0, workers: int = 0,
           shuffle: int = 0, timing: bool = False, round_log=None, inner: int = 0,
           mode: int = EIK_MODE_FP64, cell_value: int = EIK_CELL_VALUE_NEW,
-          check: bool = True, u_approx=None, schedule: int = EIK_SCHED_AUTO):
+          check: bool = True, u_approx=None, schedule: int = EIK_SCHED_AUTO, jitter: int = 0):
     """Enqueue one solve of eq. (2) on ``stream`` (torch stream; default: current stream).
 
     F: torch CUDA tensor [nz, ny, nx] of float32 or float64 speeds (contiguous).
@@ -301,14 +304,15 @@ def solve(F, h: float, idx3, q, cell: int = 8, tol: float = 0.0, u_out=None, str
                                  u_approx=u_approx)], cell=cell, stream=stream, check=check,
                            delta=delta, max_rounds=max_rounds, max_sweeps=max_sweeps,
                            workers=workers, shuffle=shuffle, timing=timing, round_log=round_log,
-                           inner=inner, mode=mode, cell_value=cell_value, schedule=schedule)
+                           inner=inner, mode=mode, cell_value=cell_value, schedule=schedule,
+                           jitter=jitter)
         return outs[0]
     lib = load()
     f_dtype = _f_dtype(F)
     u_out = _out_tensor(F, u_out)
     src, keep = _sources(F, idx3, q, stream)
     opts = _options(delta, max_rounds, max_sweeps, workers, shuffle, timing, round_log, inner,
-                    mode, cell_value, schedule)
+                    mode, cell_value, schedule, jitter)
     nz, ny, nx = F.shape
     dims = _dims_array((nx, ny, nz))
     rc = lib.eik_solve_ex(ctypes.cast(dims, ctypes.c_void_p), float(h),
@@ -515,6 +519,11 @@ def kernel_times(n: int, stream=None):
     if got < 0:
         raise EikError(got, "eik_kernel_times: ")
     return a[:got], b[:got]
+
+
+def cancel(stream=None) -> int:
+    """Ask every solve enqueued on ``stream`` so far to stop (eik_cancel); does not wait."""
+    return int(load().eik_cancel(_stream_handle(stream)))
 
 
 def release():

@@ -54,7 +54,8 @@ int main(void) {
     CHECK(strcmp(eik_strerror(EIK_OK), "EIK_OK") == 0);
     CHECK(strncmp(eik_version(), "eik-mi355x", 10) == 0);
     CHECK(sizeof(eik_problem) == 96);
-    CHECK(sizeof(eik_options) == 80 && offsetof(eik_options, schedule) == 72);
+    CHECK(sizeof(eik_options) == 88 && offsetof(eik_options, schedule) == 72 &&
+          offsetof(eik_options, jitter) == 80);
     printf("%s: %d failures\n", eik_version(), fails);
     return fails != 0;
 }

@@ -165,9 +165,10 @@ def test_problem_struct_layout():
 
 
 def test_options_struct_layout():
-    """The binding's eik_options matches the C layout (80 bytes, schedule last at 72; the C
-    side is checked in tests/c_abi_smoke.c)."""
-    assert eik.Options.schedule.offset == 72 and ctypes.sizeof(eik.Options) == 80
+    """The binding's eik_options matches the C layout (88 bytes, schedule at 72, jitter last at
+    80; the C side is checked in tests/c_abi_smoke.c)."""
+    assert eik.Options.schedule.offset == 72 and eik.Options.jitter.offset == 80
+    assert ctypes.sizeof(eik.Options) == 88
 
 
 def test_schedule_option_checked():

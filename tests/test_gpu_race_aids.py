@@ -1,0 +1,85 @@
+"""Race-detection aids on the GPU: pseudo-random delays before every visit (eik_options.jitter)
+reorder the visits of a round and of the ring, as uneven processor speeds reorder the pHCM's
+(Section 5.1 argues that the resulting races are benign); every such order must give the
+oracle's solution.  And the host's cancel request (eik_cancel) must stop a running solve with
+EIK_ECANCELLED, leaving an upper bound of the solution, without affecting the next solve."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_1306_4743_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1306_4743_amd import eik
+    eik.load()
+    return torch.device("cuda:0")
+
+
+def compare(got, want, p, tol=1e-10):
+    assert np.array_equal(np.isinf(got), np.isinf(want)), "+inf masks differ"
+    s = p.src
+    assert np.array_equal(got[s[:, 2], s[:, 1], s[:, 0]], want[s[:, 2], s[:, 1], s[:, 0]])
+    fin = np.isfinite(want) & (want > 0)
+    rel = float(np.max(np.abs(got[fin] - want[fin]) / want[fin]))
+    assert rel <= tol, rel
+    return rel
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("sched,cell,inner", [(0, 8, 1), (0, 4, 2), (0, 8, 4), (0, 8, 3),
+                                              (3, 8, 1), (2, 8, 1)])
+def test_jittered_orders_match_oracle(orc, dev, seed, sched, cell, inner):
+    import torch
+    from paper_1306_4743_amd import eik
+    for p in (W.maze(65, seed=3), W.oscillatory(49, periods=3)):
+        F = torch.from_numpy(np.ascontiguousarray(p.F)).to(dev)
+        u = eik.solve(F, p.h, p.src, p.q, cell=cell, inner=inner, schedule=sched,
+                      jitter=1000 * seed + 17)
+        rc, st = eik.status()
+        assert rc == 0, st
+        compare(u.cpu().numpy(), orc.fmm(p.F, p.h, p.src, p.q), p)
+
+
+@pytest.mark.parametrize("sched", [0, 3, 2])
+def test_cancel_stops_a_running_solve(dev, sched):
+    """One worker on a 161^3 maze takes long enough to be caught running; the cancelled result
+    is an upper bound of the complete one, and the stream's next solve is not cancelled."""
+    import torch
+    from paper_1306_4743_amd import eik
+    p = W.maze(161, seed=3)
+    F = torch.from_numpy(p.F).to(dev)
+    full = eik.solve(F, p.h, p.src, p.q, cell=8)
+    assert eik.status()[0] == 0
+    full = full.cpu().numpy()
+    stream = torch.cuda.current_stream()
+    timer = threading.Timer(0.03, lambda: eik.cancel(stream))
+    t0 = time.perf_counter()
+    timer.start()   # the host loop (schedule 2) blocks this thread inside the call
+    u = eik.solve(F, p.h, p.src, p.q, cell=8, workers=1, schedule=sched)
+    rc, st = eik.status()
+    timer.join()
+    dt = time.perf_counter() - t0
+    print(f"schedule {sched}: status {rc} after {dt * 1000:.0f} ms, visits {st['visits']}",
+          flush=True)
+    assert rc == eik.EIK_ECANCELLED
+    got = u.cpu().numpy()
+    assert np.all(got >= full * (1 - 1e-12))
+    assert np.isinf(got).sum() > 0 or np.any(got > full * (1 + 1e-9))
+    u2 = eik.solve(F, p.h, p.src, p.q, cell=8, schedule=sched)
+    assert eik.status()[0] == 0
+    compare(u2.cpu().numpy(), full, p, tol=1e-13)
+
+
+def test_cancel_without_a_solve_is_refused(dev):
+    import torch
+    from paper_1306_4743_amd import eik
+    s = torch.cuda.Stream()
+    assert eik.cancel(s) == eik.EIK_EINVAL
