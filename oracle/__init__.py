@@ -53,6 +53,8 @@ def _load():
     i64, dbl, p = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
     lib.oracle_fmm.argtypes = [i64, i64, i64, dbl, p, i64, p, p, p]
     lib.oracle_fmm.restype = ctypes.c_int
+    lib.oracle_fmm_progress.argtypes = [i64, i64, i64, dbl, p, i64, p, p, p, i64]
+    lib.oracle_fmm_progress.restype = ctypes.c_int
     lib.oracle_fmm_planted.argtypes = [i64, i64, i64, dbl, p, i64, p, p, p, ctypes.c_int]
     lib.oracle_fmm_planted.restype = ctypes.c_int
     lib.oracle_jacobi.argtypes = [i64, i64, i64, dbl, p, i64, p, p, i64, p]
@@ -82,12 +84,18 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def fmm(F, h, idx3, q) -> np.ndarray:
-    """Serial FP64 FMM; returns U with the shape of F ([nz][ny][nx])."""
+def fmm(F, h, idx3, q, progress: int = 0) -> np.ndarray:
+    """Serial FP64 FMM; returns U with the shape of F ([nz][ny][nx]).  With progress > 0 a line
+    goes to stderr after every `progress` accepted nodes (same arithmetic)."""
     lib = _load()
     F, idx3, q, nx, ny, nz = _prep(F, idx3, q)
     u = np.empty_like(F)
-    rc = lib.oracle_fmm(nx, ny, nz, float(h), _ptr(F), idx3.shape[0], _ptr(idx3), _ptr(q), _ptr(u))
+    if progress > 0:
+        rc = lib.oracle_fmm_progress(nx, ny, nz, float(h), _ptr(F), idx3.shape[0], _ptr(idx3),
+                                     _ptr(q), _ptr(u), int(progress))
+    else:
+        rc = lib.oracle_fmm(nx, ny, nz, float(h), _ptr(F), idx3.shape[0], _ptr(idx3), _ptr(q),
+                            _ptr(u))
     if rc != 0:
         raise ValueError(f"oracle_fmm rejected the input (code {rc})")
     return u

@@ -36,6 +36,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -183,7 +184,7 @@ static double known_min(const double* u, const uint8_t* st, int64_t x, int64_t s
 
 static int fmm_impl(int64_t nx, int64_t ny, int64_t nz, double h, const double* F,
                     int64_t nsrc, const int64_t* idx3, const double* q, double* u,
-                    int variant) {
+                    int variant, int64_t progress) {
     if (!check_grid(nx, ny, nz, h) || nsrc < 0) return ORC_EINVAL;
     const int64_t M = nx * ny * nz, sy = nx, sz = nx * ny;
     for (int64_t x = 0; x < M; ++x)
@@ -204,9 +205,15 @@ static int fmm_impl(int64_t nx, int64_t ny, int64_t nz, double h, const double* 
     if (rc == ORC_OK) {
         for (int64_t x = 0; x < M; ++x)
             if (fixed[x]) { st[x] = TRIAL; heap_push_or_decrease(&H, x); }
+        int64_t accepted = 0;
         while (H.size > 0) {
             int64_t x = heap_pop(&H);
             st[x] = KNOWN;
+            if (progress > 0 && ++accepted % progress == 0) {
+                fprintf(stderr, "oracle FMM: %lld of %lld nodes accepted\n",
+                        (long long)accepted, (long long)M);
+                fflush(stderr);
+            }
             int64_t i = x % nx, j = (x / nx) % ny, k = x / sz;
             int64_t nb[6];
             int nn = 0;
@@ -240,7 +247,15 @@ static int fmm_impl(int64_t nx, int64_t ny, int64_t nz, double h, const double* 
  * Returns 0, ORC_EINVAL for invalid input (u then unspecified), ORC_ENOMEM. */
 int oracle_fmm(int64_t nx, int64_t ny, int64_t nz, double h, const double* F, int64_t nsrc,
                const int64_t* idx3, const double* q, double* u) {
-    return fmm_impl(nx, ny, nz, h, F, nsrc, idx3, q, u, 0);
+    return fmm_impl(nx, ny, nz, h, F, nsrc, idx3, q, u, 0, 0);
+}
+
+/* oracle_fmm that prints a line to stderr after every `progress` accepted nodes (for grids
+ * whose solve takes minutes); the arithmetic is that of oracle_fmm. */
+int oracle_fmm_progress(int64_t nx, int64_t ny, int64_t nz, double h, const double* F,
+                        int64_t nsrc, const int64_t* idx3, const double* q, double* u,
+                        int64_t progress) {
+    return fmm_impl(nx, ny, nz, h, F, nsrc, idx3, q, u, 0, progress);
 }
 
 /* Same as oracle_fmm but with a deliberately wrong local solve (variant 1..3, see
@@ -249,7 +264,7 @@ int oracle_fmm_planted(int64_t nx, int64_t ny, int64_t nz, double h, const doubl
                        int64_t nsrc, const int64_t* idx3, const double* q, double* u,
                        int variant) {
     if (variant < 1 || variant > 3) return ORC_EINVAL;
-    return fmm_impl(nx, ny, nz, h, F, nsrc, idx3, q, u, variant);
+    return fmm_impl(nx, ny, nz, h, F, nsrc, idx3, q, u, variant, 0);
 }
 
 /* ---------------------------------------- Jacobi ----------------------------------------- */

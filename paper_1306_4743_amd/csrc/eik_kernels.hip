@@ -152,6 +152,10 @@ __device__ __forceinline__ uint32_t pref_mask_for_face(int g) {
 // ------------------------------------------------------------------------------------------
 // Small helpers.
 
+// Whether any lane of the wave has p: the ballot's scalar mask compared on the scalar unit
+// (HIP's __any goes through a per-lane 0/1 select and a compare).
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0ull; }
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -220,10 +224,13 @@ __device__ __forceinline__ void st_val(T* p, T v) {
 __device__ __forceinline__ void mem_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // ------------------------------------------------------------------------------------------
-// Square root of d >= 0 for the local solve: hardware reciprocal square root refined by one
-// Goldschmidt step (which squares its relative error to ~2^-50) and one Newton correction
+// Square root of a discriminant of the local solve: hardware reciprocal square root refined by
+// one Goldschmidt step (which squares its relative error to ~2^-50) and one Newton correction
 // (without the rescaling for subnormal or huge arguments that the discriminants here never
-// need).  Within about one ulp.
+// need).  Within about one ulp for d > 0.  The callers use the root only in the case whose
+// discriminant exceeds s^2 > 0 (two terms: 2 s^2 - (b - a)^2 with b - a < s; three terms:
+// 3 s^2 minus three squared gaps, two of them together below s^2 and the third below s^2), so
+// there is no guard for d <= 0: the value then (NaN or inf) is discarded by the caller's select.
 __device__ __forceinline__ double disc_sqrt(double d) {
     const double r = __builtin_amdgcn_rsq(d);
     double g = d * r, hh = 0.5 * r;
@@ -231,8 +238,7 @@ __device__ __forceinline__ double disc_sqrt(double d) {
     g = fma(g, e, g);
     hh = fma(hh, e, hh);
     const double res = fma(-g, g, d);
-    g = fma(res, hh, g);
-    return d > 0.0 ? g : 0.0;
+    return fma(res, hh, g);
 }
 
 // IEEE minimum / maximum of two doubles as single instructions.  (The library fmin/fmax first
@@ -388,11 +394,14 @@ constexpr int log2_side(int R) { return R == 16 ? 4 : (R == 8 ? 3 : 2); }
 
 // Box index of the cell node with index l = x + R y + R^2 z: (x + 1) + B (y + 1) + B^2 (z + 1)
 // = l + (B - R) y + (B^2 - R^2) z + (1 + B + B^2).
+// The products use the 24-bit multiplier (full rate; y, z < R), and the constant folds into the
+// LDS offsets.
 template <int R>
 __device__ __forceinline__ int box_of_cell_index(uint32_t l) {
     constexpr int B = R + 2, LG = log2_side(R);
-    const int y = (int)((l >> LG) & (uint32_t)(R - 1)), z = (int)(l >> (2 * LG));
-    return (int)l + (B - R) * y + (B * B - R * R) * z + (1 + B + B * B);
+    const uint32_t y = (l >> LG) & (uint32_t)(R - 1), z = l >> (2 * LG);
+    return (int)(__umul24(z, (uint32_t)(B * B - R * R)) + __umul24(y, (uint32_t)(B - R)) + l) +
+           (1 + B + B * B);
 }
 
 // XOR mask that reflects a cell index for sweep direction d (bit a set: descending along a).
@@ -1098,7 +1107,7 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                 asm volatile("" : "+v"(raw), "+v"(s), "+v"(xm), "+v"(xp), "+v"(ym), "+v"(yp),
                              "+v"(zm), "+v"(zp));
                 const bool act = pr.has(p) && is_active(raw);
-                if (__any(act)) {
+                if (wave_any(act)) {
                     // An active lane stores its value back (|raw| clears the flag); a decrease
                     // activates every neighbour that is inactive (sign clear) and larger than
                     // the new value, which the raw value tells in one comparison.  Neighbour
@@ -1115,13 +1124,16 @@ __device__ __forceinline__ void visit_cell(const SolveParams& P, int c, int slot
                     UT* const ub = &L.U[b];
                     if (act) ub[0] = dec ? g : old;
                     changed |= dec;
-                    if (track_dec && dec) maxdec = vmax(maxdec, old - g);
-                    if (dec && xm > g) mark_active(ub - 1, xm);
-                    if (dec && xp > g) mark_active(ub + 1, xp);
-                    if (dec && ym > g) mark_active(ub - B, ym);
-                    if (dec && yp > g) mark_active(ub + B, yp);
-                    if (dec && zm > g) mark_active(ub - B * B, zm);
-                    if (dec && zp > g) mark_active(ub + B * B, zp);
+                    // A step in which no lane decreased activates nothing (one wave vote).
+                    if (wave_any(dec)) {
+                        if (track_dec && dec) maxdec = vmax(maxdec, old - g);
+                        if (dec && xm > g) mark_active(ub - 1, xm);
+                        if (dec && xp > g) mark_active(ub + 1, xp);
+                        if (dec && ym > g) mark_active(ub - B, ym);
+                        if (dec && yp > g) mark_active(ub + B, yp);
+                        if (dec && zm > g) mark_active(ub - B * B, zm);
+                        if (dec && zp > g) mark_active(ub + B * B, zp);
+                    }
                 }
                 wave_sync();
             }
@@ -1967,7 +1979,7 @@ k_solve_async(SolveParams P) {
                 break;
             }
             uint32_t fl = 0;
-            int slot = 0;
+            int slot = 0, st = 0;
             unsigned long long kb = 0;
             if (lane == 0) {
                 fl = atomicExch(&P.flags[0][c], FL_RUNNING);
@@ -1975,13 +1987,20 @@ k_solve_async(SolveParams P) {
                     kb = atomicExch((unsigned long long*)&P.key[0][c],
                                     (unsigned long long)dbits(__builtin_inf()));
                 slot = P.cell_slot[c];
+                // The host's cancel request (every 16 visits: a read of host memory), then the
+                // launch status, in the same memory round trip as the exchange.
+                if ((visits & 15) == 0 && cancel_requested(P)) async_cancel(P);
+                st = __hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             fl = __shfl(fl, 0, 64) & ~FL_QUEUED;
             slot = __shfl(slot, 0, 64);
             kb = __shfl(kb, 0, 64);
             mem_wait();  // the exchange has returned before the visit reads the cell
             cyc_pop += cycles() - tp0;
-            if (lane == 0 && (visits & 15) == 0 && cancel_requested(P)) async_cancel(P);
+            // A cancelled launch (by the host or a watchdog) stops popping although cells are
+            // still queued; the cell just taken stays RUNNING, which the next solve's
+            // initialisation clears.
+            if (__shfl(st, 0, 64) != 0) break;
             jitter_delay(P, ((uint64_t)blockIdx.x << 20) ^ ((uint64_t)wave << 12) ^ visits);
             ++visits;
             const unsigned long long sw0 = cnt.sweeps, tv0 = cycles();

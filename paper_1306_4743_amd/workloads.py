@@ -227,28 +227,38 @@ def bumps(n: int = 1025, seed: int = 4, n_bumps: int = 32, cell: int = 8, tol: f
           dtype=np.float32, device=None) -> Problem:
     """F = clamp(1 + sum_m A_m exp(-|x - c_m|^2 / (2 w_m^2)), 0.2, 2) with c_m ~ U[0,1]^3,
     A_m ~ U[-0.5, 0.5], w_m ~ U[0.02, 0.1]; centre source.  Evaluated in FP64 and stored in
-    ``dtype``.  With ``device`` set (a torch device) the field is evaluated there with torch
-    and returned as a numpy array; the bump parameters come from the same numpy generator."""
+    ``dtype``.  The Gaussian is separable: its per-axis factors are evaluated on the host with
+    numpy; the 3-D sum then takes, for each bump, the products (g_z g_y) g_x, the scaling by A_m
+    and the addition, each correctly rounded, in that order -- with numpy on the host, or with
+    torch on ``device`` (returned as a numpy array) -- so both give the same field bit for bit."""
     rng = np.random.default_rng(seed)
     c = rng.uniform(0.0, 1.0, size=(n_bumps, 3))
     A = rng.uniform(-0.5, 0.5, size=n_bumps)
     w = rng.uniform(0.02, 0.1, size=n_bumps)
     x = _axis_coords(n)
+    g = [[np.exp(-(x - c[m, a]) ** 2 / (2 * w[m] ** 2)) for a in range(3)]
+         for m in range(n_bumps)]
     if device is None:
         F = np.ones((n, n, n), dtype=np.float64)
+        buf = np.empty_like(F)
         for m in range(n_bumps):
-            gx = np.exp(-(x - c[m, 0]) ** 2 / (2 * w[m] ** 2))
-            gy = np.exp(-(x - c[m, 1]) ** 2 / (2 * w[m] ** 2))
-            gz = np.exp(-(x - c[m, 2]) ** 2 / (2 * w[m] ** 2))
-            F += A[m] * (gz[:, None, None] * gy[None, :, None]) * gx[None, None, :]
-        F = np.clip(F, 0.2, 2.0).astype(dtype)
+            gx, gy, gz = g[m]
+            np.multiply(gz[:, None, None] * gy[None, :, None], gx[None, None, :], out=buf)
+            buf *= A[m]
+            F += buf
+        del buf
+        np.clip(F, 0.2, 2.0, out=F)
+        F = F.astype(dtype)
     else:
         import torch
-        xt = torch.tensor(x, dtype=torch.float64, device=device)
         Ft = torch.ones((n, n, n), dtype=torch.float64, device=device)
+        buf = torch.empty_like(Ft)
         for m in range(n_bumps):
-            g = [torch.exp(-(xt - float(c[m, a])) ** 2 / (2 * float(w[m]) ** 2)) for a in range(3)]
-            Ft += float(A[m]) * (g[2][:, None, None] * g[1][None, :, None]) * g[0][None, None, :]
+            gx, gy, gz = (torch.from_numpy(v).to(device) for v in g[m])
+            torch.mul(gz[:, None, None] * gy[None, :, None], gx[None, None, :], out=buf)
+            buf.mul_(float(A[m]))
+            Ft.add_(buf)
+        del buf
         Ft.clamp_(0.2, 2.0)
         F = Ft.to(torch.float32 if dtype == np.float32 else torch.float64).cpu().numpy()
         del Ft

@@ -241,11 +241,11 @@ def test_autotune_picks_a_valid_configuration(orc, torch_dev):
     p = W.maze(65, seed=4, n_sources=2)
     F = torch.from_numpy(p.F).to(torch_dev)
     best, table = eik.autotune(F, p.h, p.src, p.q, reps=1)
-    # r in {8, 4} x three in-cell solvers, r = 16 x two (no dual sweeps), x two worker counts,
-    # then three bands
-    assert len(table) == 19
+    # r in {8, 4} x four in-cell solvers, r = 16 x two (no dual or paired sweeps), x two
+    # worker counts, then three bands
+    assert len(table) == 23
     assert {(t["cell"], t["inner"]) for t in table} == (
-        {(c, i) for c in (8, 4) for i in (1, 2, 3)} | {(16, 1), (16, 2)})
+        {(c, i) for c in (8, 4) for i in (1, 2, 3, 4)} | {(16, 1), (16, 2)})
     assert all(t["status"] == 0 and 0 < t["ms"] < 1e4 for t in table)
     assert best["ms"] == min(t["ms"] for t in table)
     u = eik.solve(F, p.h, p.src, p.q, cell=best["cell"], inner=best["inner"],

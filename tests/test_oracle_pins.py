@@ -264,3 +264,16 @@ def test_duplicate_sources_keep_min(orc):
     src = np.array([[4, 4, 4], [4, 4, 4], [0, 0, 0]])
     U = orc.fmm(p.F, p.h, src, [0.5, 0.25, 0.0])
     assert U[4, 4, 4] == 0.25 and U[0, 0, 0] == 0.0
+
+
+def test_progress_variant_is_the_same_fmm(orc, capfd):
+    """The FMM with progress lines returns the plain FMM's array bit for bit and reports every
+    `progress` accepted nodes on stderr."""
+    p = W.oscillatory(33)
+    want = orc.fmm(p.F, p.h, p.src, p.q)
+    got = orc.fmm(p.F, p.h, p.src, p.q, progress=4096)
+    assert np.array_equal(got, want)
+    err = capfd.readouterr().err
+    lines = [ln for ln in err.splitlines() if ln.startswith("oracle FMM:")]
+    assert len(lines) == 33 ** 3 // 4096
+    assert lines[-1] == f"oracle FMM: {len(lines) * 4096} of {33 ** 3} nodes accepted"
