@@ -129,6 +129,7 @@ void bind_common(SolveParams* P, unsigned char* base, const CommonLayout& L, int
     P->list[0] = (int32_t*)(base + L.off_list);
     P->list[1] = P->list[0] + cells;
     P->ctl = (eik::RoundCtl*)(base + L.off_small + kSmallCtl);
+    P->seg_cursor = (uint32_t*)(base + L.off_small + eik::kSmallSegCursor);
     P->bar = (uint32_t*)(base + L.off_small + kSmallBar);
     P->status = (int*)(base + L.off_small + kSmallStatus);
     P->stats = (unsigned long long*)(base + L.off_small + kSmallStats);

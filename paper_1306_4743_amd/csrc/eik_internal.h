@@ -59,7 +59,12 @@ constexpr size_t kSmallAsyncHead = 3072;
 constexpr size_t kSmallAsyncTail = 3328;
 constexpr size_t kSmallAsyncPending = 3584;
 constexpr size_t kSmallAsyncDone = 3840;
-constexpr size_t kSmallBytes = 4096;
+// Pop cursors of the rounds' list segments: [4 rounds][kPopSegs], 128 bytes apart.
+constexpr size_t kSmallSegCursor = 4096;
+constexpr size_t kSmallBytes = 8192;
+// A round's list is popped through this many segments, one per XCD (each with its own cursor),
+// so that the pops of the 256 workgroups do not all meet on one atomic word.
+constexpr int kPopSegs = 8;
 constexpr int kBarGen = 64;            // index of the generation word in the barrier array
 
 // One grid of a (possibly batched) solve.  Its cells occupy the global cell ids
@@ -100,6 +105,7 @@ struct SolveParams {
     uint32_t* flags[2];
     int32_t* list[2];
     RoundCtl* ctl;         // [4] control blocks, slot = round & 3
+    uint32_t* seg_cursor;  // round t, segment g: seg_cursor[((t & 3) * kPopSegs + g) * 32]
     uint64_t* slot_minkey; // [4][nslots] smallest cell value queued per slot, row = round & 3
     uint32_t* bar;         // grid barrier: bar[0] arrivals, bar[kBarGen] generation
     int* status;           // device status word of the launch (watchdog, round cap)

@@ -1711,6 +1711,8 @@ k_solve(SolveParams P) {
             r2->cursor = 0;
             r2->minkey = dbits(__builtin_inf());
         }
+        if (blockIdx.x == 0 && threadIdx.x < kPopSegs)
+            P.seg_cursor[(((t + 2) & 3) * kPopSegs + threadIdx.x) * 32] = 0;
         // Per-slot bands: the row of round t + 2 is neither read nor written in round t.
         const bool slot_band = P.slot_band && P.delta > 0.0;
         if (slot_band) {
@@ -1723,26 +1725,54 @@ k_solve(SolveParams P) {
         const double thr = P.delta > 0.0 ? bitsd(ld_relaxed_u64(&ctl_cur->minkey)) + P.delta
                                          : __builtin_inf();
         const uint64_t* smk_cur = slot_band ? slot_minkeys(P, t) : nullptr;
-        // Cells per pop: one when the list is short (balance), more when it is long (fewer
-        // atomics on the shared cursor).
-        // Cells per pop: one when the list is short (balance), more when it is long (fewer
-        // atomics on the shared cursor); a wave sweeping two cells at once takes at least two.
+        // Pops.  The list is split into kPopSegs segments with a cursor each; a workgroup pops
+        // from the segment of its XCD (workgroups are dealt to the XCDs in turn), and once that
+        // is exhausted from any other that is not (found with one load per segment).  Cells per
+        // pop: one when the segment is short against its share of the waves (balance), more when
+        // it is long (fewer atomics); a wave sweeping two cells at once takes at least two.
         constexpr uint32_t kMinChunk = INNER == INNER_PAIR ? 2u : 1u;
-        uint32_t chunk = n >= (uint32_t)nwaves_total * 32u ? 8u
-                       : (n >= (uint32_t)nwaves_total * 8u ? 4u
-                       : (n >= (uint32_t)nwaves_total * 2u ? 2u : 1u));
-        if (chunk < kMinChunk) chunk = kMinChunk;
+        uint32_t* const segc = P.seg_cursor + (size_t)(t & 3) * kPopSegs * 32;
+        const uint32_t seg_len = (n + kPopSegs - 1) / kPopSegs;
+        const uint32_t waves_seg = (uint32_t)(nwaves_total + kPopSegs - 1) / kPopSegs;
+        int seg = (int)(blockIdx.x % kPopSegs);
+        uint32_t seg_lo = 0, seg_hi = 0;
+        auto seg_bounds = [&](int g) {
+            seg_lo = min((uint32_t)g * seg_len, n);
+            seg_hi = min(seg_lo + seg_len, n);
+        };
+        seg_bounds(seg);
+        const uint32_t len0 = seg_hi - seg_lo;
+        uint32_t chunk_now = len0 >= waves_seg * 32u ? 8u
+                           : (len0 >= waves_seg * 8u ? 4u : (len0 >= waves_seg * 2u ? 2u : 1u));
+        if (chunk_now < kMinChunk) chunk_now = kMinChunk;
         WaveQueue wq{0, __builtin_inf()};
-        uint32_t chunk_now = chunk;
         for (;;) {
             const unsigned long long tp0 = cycles();
             uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&ctl_cur->cursor, chunk_now);
+            if (lane == 0) base = seg_lo + atomicAdd(&segc[seg * 32], chunk_now);
             base = __shfl(base, 0, 64);
-            if (base >= n) { cyc_pop += cycles() - tp0; break; }
-            const uint32_t cnt_here = n - base < chunk_now ? n - base : chunk_now;
-            // The last cells of the round go one per pop, so that the round's tail is short.
-            if (n - base < (uint32_t)nwaves_total * 2u) chunk_now = kMinChunk;
+            if (base >= seg_hi) {
+                // Lane g reads segment g's cursor; the wave moves to the first open segment
+                // after the current one (so that the waves that steal spread out), or stops.
+                bool open = false;
+                if (lane < kPopSegs) {
+                    const uint32_t lo = min((uint32_t)lane * seg_len, n);
+                    const uint32_t hi = min(lo + seg_len, n);
+                    open = lo + __hip_atomic_load(&segc[lane * 32], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT) < hi;
+                }
+                const uint32_t om = (uint32_t)__builtin_amdgcn_ballot_w64(open);
+                if (om == 0u) { cyc_pop += cycles() - tp0; break; }
+                const uint32_t rot = (om >> (seg + 1)) | (om << (kPopSegs - 1 - seg));
+                seg = (seg + 1 + __builtin_ctz(rot & ((1u << kPopSegs) - 1u))) % kPopSegs;
+                seg_bounds(seg);
+                chunk_now = kMinChunk;
+                cyc_pop += cycles() - tp0;
+                continue;
+            }
+            const uint32_t cnt_here = seg_hi - base < chunk_now ? seg_hi - base : chunk_now;
+            // The last cells of a segment go one per pop, so that the round's tail is short.
+            if (seg_hi - base < waves_seg * 2u) chunk_now = kMinChunk;
             // Lanes j < cnt_here take cell j of the chunk: its flags and value are exchanged
             // for empty ones (the removal of Algorithm 3 with V^c <- +inf).
             int my_c = 0, my_slot = 0;
@@ -2178,6 +2208,7 @@ __global__ void k_init_global(SolveParams P) {
         P.ctl[g0].cursor = 0;
         P.ctl[g0].minkey = dbits(INF);
     }
+    if (g0 < 4 * kPopSegs) P.seg_cursor[g0 * 32] = 0;
     if (g0 < 2) P.bar[g0 * kBarGen] = 0;
     if (g0 == 0) {
         *P.status = 0;
@@ -2309,6 +2340,7 @@ __global__ void k_reset_rounds(SolveParams P) {
         P.ctl[g0].cursor = 0;
         P.ctl[g0].minkey = dbits(__builtin_inf());
     }
+    if (g0 < 4 * kPopSegs) P.seg_cursor[g0 * 32] = 0;
     if (g0 == 0) *P.next_round = 0;
     for (int g = g0; g < 4 * P.nslots; g += stride) P.slot_minkey[g] = dbits(__builtin_inf());
 }
