@@ -532,6 +532,30 @@ __device__ __forceinline__ void queue_flush(const SolveParams& P, int nxt, Round
     wave_sync();
 }
 
+// End-of-round form for a whole workgroup (every wave calls it): the W waves' buffers are
+// appended with one atomic, so that a round's end does not meet every wave's flush on the one
+// count word.
+template <int R, int INNER, typename UT, int W>
+__device__ __forceinline__ void queue_flush_group(const SolveParams& P, int nxt,
+                                                  RoundCtl* ctl_next, WaveLds<R, INNER, UT>& L,
+                                                  int lane, int wave, WaveQueue& wq) {
+    __shared__ uint32_t s_qn[W];
+    __shared__ uint32_t s_qbase;
+    if (lane == 0) s_qn[wave] = (uint32_t)wq.n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t total = 0;
+        for (int w = 0; w < W; ++w) total += s_qn[w];
+        s_qbase = total ? atomicAdd(&ctl_next->count, total) : 0u;
+    }
+    __syncthreads();
+    uint32_t off = s_qbase;
+    for (int w = 0; w < wave; ++w) off += s_qn[w];
+    if (lane < wq.n) P.list[nxt][off + lane] = L.q[lane];
+    wq.n = 0;
+    wave_sync();
+}
+
 // Every lane with do_tag set tags one cell (any lanes, in parallel): cell value <- min(value),
 // flags |= bits | QUEUED, and the cell joins the next round's list unless already queued.
 // band_slot: the slot of every tagged cell when they share one (a visit's neighbours), or -1.
@@ -1855,7 +1879,7 @@ k_solve(SolveParams P) {
             }
         }
         const unsigned long long tw0 = cycles();
-        queue_flush<R, INNER, UT>(P, nxt, ctl_next, L, lane, wq);
+        queue_flush_group<R, INNER, UT, W>(P, nxt, ctl_next, L, lane, wave, wq);
         if (P.delta > 0.0 && !slot_band) {
             const double mk = wave_min(wq.minkey);
             if (lane == 0 && mk < __builtin_inf())
