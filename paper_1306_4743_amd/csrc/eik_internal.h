@@ -34,11 +34,11 @@ enum {
     ST_HIST_SWEEPS = 16, ST_HIST_CYCLES = 48, ST_TOTAL = 80
 };
 
-// Per-round control block: pop cursor, list length and smallest cell value in the list, each
-// on its own cache line so that pops, appends and minimum updates do not contend.
+// Per-round control block: list length and smallest cell value in the list, each on its own
+// cache line so that appends and minimum updates do not contend (the pop cursors are
+// seg_cursor).
 struct RoundCtl {
-    uint32_t cursor;
-    uint32_t pad0[31];
+    uint32_t pad0[32];
     uint32_t count;
     uint32_t pad1[15];
     uint64_t minkey;
@@ -61,10 +61,10 @@ constexpr size_t kSmallAsyncPending = 3584;
 constexpr size_t kSmallAsyncDone = 3840;
 // Pop cursors of the rounds' list segments: [4 rounds][kPopSegs], 128 bytes apart.
 constexpr size_t kSmallSegCursor = 4096;
-constexpr size_t kSmallBytes = 8192;
-// A round's list is popped through this many segments, one per XCD (each with its own cursor),
+constexpr size_t kSmallBytes = 12288;
+// A round's list is popped through this many segments (two per XCD), each with its own cursor,
 // so that the pops of the 256 workgroups do not all meet on one atomic word.
-constexpr int kPopSegs = 8;
+constexpr int kPopSegs = 16;
 constexpr int kBarGen = 64;            // index of the generation word in the barrier array
 
 // One grid of a (possibly batched) solve.  Its cells occupy the global cell ids

@@ -1732,7 +1732,6 @@ k_solve(SolveParams P) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             RoundCtl* r2 = &P.ctl[(t + 2) & 3];
             r2->count = 0;
-            r2->cursor = 0;
             r2->minkey = dbits(__builtin_inf());
         }
         if (blockIdx.x == 0 && threadIdx.x < kPopSegs)
@@ -1750,14 +1749,14 @@ k_solve(SolveParams P) {
                                          : __builtin_inf();
         const uint64_t* smk_cur = slot_band ? slot_minkeys(P, t) : nullptr;
         // Pops.  The list is split into kPopSegs segments with a cursor each; a workgroup pops
-        // from the segment of its XCD (workgroups are dealt to the XCDs in turn), and once that
-        // is exhausted from any other that is not (found with one load per segment).  Cells per
-        // pop: one when the segment is short against its share of the waves (balance), more when
-        // it is long (fewer atomics); a wave sweeping two cells at once takes at least two.
-        constexpr uint32_t kMinChunk = INNER == INNER_PAIR ? 2u : 1u;
+        // from its own segment (workgroup index modulo kPopSegs: two segments per XCD, to which
+        // workgroups are dealt in turn), and once that is exhausted from any other that is not
+        // (found with one load per segment).  One cell per pop (two for a wave sweeping two cells
+        // at once): with the pops spread over the segments' cursors, taking more cells at a time
+        // saves little and leaves some waves with a second cell while others have none.
+        constexpr uint32_t chunk_now = INNER == INNER_PAIR ? 2u : 1u;
         uint32_t* const segc = P.seg_cursor + (size_t)(t & 3) * kPopSegs * 32;
         const uint32_t seg_len = (n + kPopSegs - 1) / kPopSegs;
-        const uint32_t waves_seg = (uint32_t)(nwaves_total + kPopSegs - 1) / kPopSegs;
         int seg = (int)(blockIdx.x % kPopSegs);
         uint32_t seg_lo = 0, seg_hi = 0;
         auto seg_bounds = [&](int g) {
@@ -1765,10 +1764,6 @@ k_solve(SolveParams P) {
             seg_hi = min(seg_lo + seg_len, n);
         };
         seg_bounds(seg);
-        const uint32_t len0 = seg_hi - seg_lo;
-        uint32_t chunk_now = len0 >= waves_seg * 32u ? 8u
-                           : (len0 >= waves_seg * 8u ? 4u : (len0 >= waves_seg * 2u ? 2u : 1u));
-        if (chunk_now < kMinChunk) chunk_now = kMinChunk;
         WaveQueue wq{0, __builtin_inf()};
         for (;;) {
             const unsigned long long tp0 = cycles();
@@ -1785,18 +1780,15 @@ k_solve(SolveParams P) {
                     open = lo + __hip_atomic_load(&segc[lane * 32], __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT) < hi;
                 }
-                const uint32_t om = (uint32_t)__builtin_amdgcn_ballot_w64(open);
+                const uint64_t om = __builtin_amdgcn_ballot_w64(open);
                 if (om == 0u) { cyc_pop += cycles() - tp0; break; }
-                const uint32_t rot = (om >> (seg + 1)) | (om << (kPopSegs - 1 - seg));
-                seg = (seg + 1 + __builtin_ctz(rot & ((1u << kPopSegs) - 1u))) % kPopSegs;
+                const uint64_t rot = (om >> (seg + 1)) | (om << (kPopSegs - 1 - seg));
+                seg = (seg + 1 + __builtin_ctzll(rot & ((1ull << kPopSegs) - 1ull))) % kPopSegs;
                 seg_bounds(seg);
-                chunk_now = kMinChunk;
                 cyc_pop += cycles() - tp0;
                 continue;
             }
             const uint32_t cnt_here = seg_hi - base < chunk_now ? seg_hi - base : chunk_now;
-            // The last cells of a segment go one per pop, so that the round's tail is short.
-            if (seg_hi - base < waves_seg * 2u) chunk_now = kMinChunk;
             // Lanes j < cnt_here take cell j of the chunk: its flags and value are exchanged
             // for empty ones (the removal of Algorithm 3 with V^c <- +inf).
             int my_c = 0, my_slot = 0;
@@ -2229,7 +2221,6 @@ __global__ void k_init_global(SolveParams P) {
     const double INF = __builtin_inf();
     if (g0 < 4) {
         P.ctl[g0].count = 0;
-        P.ctl[g0].cursor = 0;
         P.ctl[g0].minkey = dbits(INF);
     }
     if (g0 < 4 * kPopSegs) P.seg_cursor[g0 * 32] = 0;
@@ -2361,7 +2352,6 @@ __global__ void k_reset_rounds(SolveParams P) {
     const int g0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     if (g0 < 4) {
         P.ctl[g0].count = 0;
-        P.ctl[g0].cursor = 0;
         P.ctl[g0].minkey = dbits(__builtin_inf());
     }
     if (g0 < 4 * kPopSegs) P.seg_cursor[g0 * 32] = 0;
