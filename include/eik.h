@@ -9,7 +9,9 @@
  * of the boundary is non-inflow).  The solver follows the Heap-Cell Method (Section 4,
  * Algorithms 1 and 2) and its parallel form (Section 5, Algorithm 3): the grid is split into
  * cubic cells of `cell` nodes per side, cells are swept with Gauss-Seidel / locking-sweeping
- * updates, and a cell-priority worklist (cell values, eq. (3)) decides which cells are swept.
+ * updates, and a worklist of the cells whose boundary changed decides which cells are swept: by
+ * default every queued cell in each round; with a band (eik_options.delta) only those whose cell
+ * value (eq. (3)) lies within delta of the smallest queued one.
  * The discrete solution is unique, so the result does not depend on cell size, schedule or
  * processing order (Section 4, "Assigning Cell Values") beyond rounding.
  *
