@@ -63,7 +63,7 @@ Workload: barrier maze 513^3 (6 slabs/axis, thickness 4, 2 gaps 16x16, F = 1 / 0
 nodes, seed 3, cell side 8, FP64 values, in-cell sweeps (cap 8 per visit), tol 0; FP32 speeds
 resident in HBM; one workgroup of 12 workers per CU.
 
-Command (from the repository root on the GPU machine; rocprofv3 ends with a segmentation fault
+Command (from the repository root on an MI355X machine; rocprofv3 ends with a segmentation fault
 after the program's last line with this cooperative kernel, the database is complete):
 
 ```
