@@ -9,6 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeik.so")
+# The same solver with every write-back of a visit through an atomic minimum (a race check:
+# its results must equal libeik.so's).
+MINSTORE_LIB = os.path.join(HERE, "libeik_minstore.so")
 SOURCES = ["eik_api.hip", "eik_kernels.hip"]
 PROBE_LIB = os.path.join(HERE, "libeik_probe.so")
 PROBE_SOURCES = ["eik_probe.hip"]
@@ -24,9 +27,9 @@ FLAGS = [
 ]
 
 
-def _compile(out: str, sources, verbose: bool) -> str:
+def _compile(out: str, sources, verbose: bool, extra=()) -> str:
     tmp = out + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *[os.path.join(CSRC, s) for s in sources]]
+    cmd = [HIPCC, *FLAGS, *extra, "-o", tmp, *[os.path.join(CSRC, s) for s in sources]]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -35,10 +38,17 @@ def _compile(out: str, sources, verbose: bool) -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the solver into paper_1306_4743_amd/libeik.so and the bandwidth probes into
-    libeik_probe.so (always recompiles); returns the solver library's path."""
-    _compile(PROBE_LIB, PROBE_SOURCES, verbose)
-    return _compile(LIB, SOURCES, verbose)
+    """Compile the solver into paper_1306_4743_amd/libeik.so, its min-store debug build into
+    libeik_minstore.so and the bandwidth probes into libeik_probe.so (always recompiles, the two
+    solver builds in parallel); returns the solver library's path."""
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(3) as ex:
+        jobs = [ex.submit(_compile, PROBE_LIB, PROBE_SOURCES, verbose),
+                ex.submit(_compile, MINSTORE_LIB, SOURCES, verbose, ("-DEIK_DEBUG_MIN_STORES",)),
+                ex.submit(_compile, LIB, SOURCES, verbose)]
+        for j in jobs:
+            j.result()
+    return LIB
 
 
 if __name__ == "__main__":

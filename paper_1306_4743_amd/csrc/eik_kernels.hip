@@ -218,6 +218,31 @@ __device__ __forceinline__ void st_val(T* p, T v) {
     if constexpr (ASYNC) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else *p = v;
 }
+// Write-back of a visit's values (cell nodes and face copies).  The min-store build
+// (EIK_DEBUG_MIN_STORES, libeik_minstore.so) writes through an atomic minimum of the bit
+// patterns instead: values are >= +0, so their bit order is their order, and an active flag
+// carried in the sign bit is ORed in afterwards.  A minimum cannot lose a decrease to another
+// writer of the same word, so a result that differs from the plain build's shows that two
+// visits wrote one cell at once.
+template <bool ASYNC, typename T>
+__device__ __forceinline__ void st_writeback(T* p, T v) {
+#ifdef EIK_DEBUG_MIN_STORES
+    if constexpr (sizeof(T) == 8) {
+        unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        atomicMin(q, b & ~(1ull << 63));
+        if (b >> 63) atomicOr(q, 1ull << 63);
+    } else {
+        unsigned int* q = reinterpret_cast<unsigned int*>(p);
+        const unsigned int b = __float_as_uint(v);
+        atomicMin(q, b & 0x7FFFFFFFu);
+        if (b >> 31) atomicOr(q, 0x80000000u);
+    }
+#else
+    st_val<ASYNC>(p, v);
+#endif
+}
+
 // Waits until every earlier vector memory access of the wave has completed (stores are then
 // visible device-wide, atomics have returned), and keeps the compiler from moving memory
 // accesses across it.
@@ -957,7 +982,7 @@ __device__ __forceinline__ void publish_cell(const SolveParams& P, const Slot& S
     for (int l = lane; l < R3; l += 64) {
         const int x = l % R, y = (l / R) % R, z = l / R2;
         const UT v = U[box_index<R>(x, y, z)];
-        st_val<ASYNC>(&uw[l], keep_active ? v : fabs(v));
+        st_writeback<ASYNC>(&uw[l], keep_active ? v : fabs(v));
     }
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
@@ -985,7 +1010,7 @@ __device__ __forceinline__ void publish_cell(const SolveParams& P, const Slot& S
 #pragma unroll
             for (int j = 0; j < FPL; ++j)
                 if (lane + 64 * j < R2)
-                    st_val<ASYNC>(&fw[((size_t)lc * 6 + f) * R2 + lane + 64 * j], v[j]);
+                    st_writeback<ASYNC>(&fw[((size_t)lc * 6 + f) * R2 + lane + 64 * j], v[j]);
         }
         if (nb >= 0 && __any(inflow)) {
             double kv = (double)wave_min(in_min);

@@ -7,6 +7,7 @@ computes values itself and has no CPU fallback: if the library is missing it rai
 from __future__ import annotations
 
 import atexit
+import contextlib
 import ctypes
 import os
 import weakref
@@ -15,6 +16,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeik.so")
+# The same solver with every write-back through an atomic minimum (a race check, see library()).
+MINSTORE_LIB_PATH = os.path.join(_HERE, "libeik_minstore.so")
 
 EIK_OK, EIK_EINVAL, EIK_ENOMEM, EIK_EHIP, EIK_ENOCONV, EIK_ECANCELLED = 0, -1, -2, -3, -4, -5
 EIK_EBUSY = -6
@@ -90,10 +93,37 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+    _lib = _open(LIB_PATH)
+    atexit.register(_shutdown)
+    return _lib
+
+
+@contextlib.contextmanager
+def library(path: str):
+    """Inside the block, every call of this module goes to another build of the same ABI at
+    `path` (e.g. MINSTORE_LIB_PATH); the block waits for the device and releases that build's
+    workspaces at its end.  Not for use while servers of the default build are running."""
+    global _lib
+    saved = load()
+    other = _open(path)
+    _lib = other
+    try:
+        yield other
+    finally:
+        try:
+            import torch
+            if torch.cuda.is_initialized():  # no device work can be pending otherwise
+                torch.cuda.synchronize()
+        finally:
+            other.eik_release()
+            _lib = saved
+
+
+def _open(path: str):
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
                            "(the solver has no CPU fallback)")
-    lib = ctypes.CDLL(LIB_PATH)
+    lib = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     lib.eik_solve.argtypes = [vp, dbl, vp, i32, ctypes.POINTER(Sources), vp, i32, dbl, vp]
     lib.eik_solve.restype = i32
@@ -144,8 +174,6 @@ def load():
     lib.eik_server_destroy.restype = i32
     lib.eik_server_polish_redone.argtypes = [vp]
     lib.eik_server_polish_redone.restype = i64
-    _lib = lib
-    atexit.register(_shutdown)
     return lib
 
 

@@ -31,6 +31,19 @@ def test_library_exports_every_declared_symbol():
         assert re.search(rf"\bT {name}\b", out), name
 
 
+def test_min_store_build_exports_the_same_abi():
+    """libeik_minstore.so (the race-check build: write-backs through an atomic minimum) exports
+    every declared symbol, and the binding can route its calls there and back."""
+    out = os.popen(f"nm -D --defined-only {eik.MINSTORE_LIB_PATH}").read()
+    for name in _declared_symbols():
+        assert re.search(rf"\bT {name}\b", out), name
+    base = eik.load()
+    with eik.library(eik.MINSTORE_LIB_PATH) as other:
+        assert eik.load() is other and other is not base
+        assert eik.strerror(0) == "EIK_OK"
+    assert eik.load() is base
+
+
 def test_strerror_and_version():
     assert eik.strerror(0) == "EIK_OK"
     for code in (-1, -2, -3, -4, -5):

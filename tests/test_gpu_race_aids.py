@@ -1,8 +1,10 @@
 """Race-detection aids on the GPU: pseudo-random delays before every visit (eik_options.jitter)
 reorder the visits of a round and of the ring, as uneven processor speeds reorder the pHCM's
 (Section 5.1 argues that the resulting races are benign); every such order must give the
-oracle's solution.  And the host's cancel request (eik_cancel) must stop a running solve with
-EIK_ECANCELLED, leaving an upper bound of the solution, without affecting the next solve."""
+oracle's solution.  The min-store build (libeik_minstore.so: every write-back of a visit through an
+atomic minimum, which cannot lose a decrease to another writer of the same word) must give the
+plain build's results.  And the host's cancel request (eik_cancel) must stop a running solve
+with EIK_ECANCELLED, leaving an upper bound of the solution, without affecting the next solve."""
 import threading
 import time
 
@@ -83,3 +85,29 @@ def test_cancel_without_a_solve_is_refused(dev):
     from paper_1306_4743_amd import eik
     s = torch.cuda.Stream()
     assert eik.cancel(s) == eik.EIK_EINVAL
+
+
+@pytest.mark.parametrize("sched,cell,inner,jitter", [(0, 8, 1, 0), (0, 4, 2, 0), (0, 8, 4, 0),
+                                                     (3, 8, 1, 0), (2, 8, 1, 0), (0, 8, 1, 77),
+                                                     (3, 8, 1, 78)])
+def test_min_store_build_matches_plain_build(orc, dev, sched, cell, inner, jitter):
+    """The same problems through both builds, in the same schedule: +inf masks identical, values
+    equal to rounding (the visit order, and so the rounding, differs from run to run) and both
+    equal to the oracle.  If two visits ever wrote one cell at once, the plain build could keep
+    the later, larger value where the min-store build keeps the smaller."""
+    import torch
+    from paper_1306_4743_amd import eik
+    for p in (W.maze(65, seed=3), W.oscillatory(49, periods=3), W.random_small(29, seed=5),
+              W.maze(129, seed=6, n_sources=2)):
+        F = torch.from_numpy(np.ascontiguousarray(p.F)).to(dev)
+        kw = dict(cell=cell, inner=inner, schedule=sched, jitter=jitter)
+        plain = eik.solve(F, p.h, p.src, p.q, **kw)
+        rc, _ = eik.status()
+        assert rc == 0
+        with eik.library(eik.MINSTORE_LIB_PATH):
+            mins = eik.solve(F, p.h, p.src, p.q, **kw)
+            rc, st = eik.status()
+        assert rc == 0, st
+        a, b = plain.cpu().numpy(), mins.cpu().numpy()
+        compare(b, a, p, tol=1e-13)
+        compare(b, orc.fmm(p.F, p.h, p.src, p.q), p)
