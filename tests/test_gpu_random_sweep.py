@@ -3,7 +3,8 @@
 Each case draws grid extents (2..40 per axis, so ragged and degenerate cells appear), i.i.d.
 speeds over one of three ranges, 1-6 exits with random q, and a solver configuration (cell size,
 in-cell solver, priority band, shuffled pop order, sweep cap, speed dtype, precision mode or a
-polish of the FP32 result).  The discrete solution of eq. (2) is unique and reached by every
+polish of the FP32 result), and larger grids in a random schedule with or without jittered visit
+orders.  The discrete solution of eq. (2) is unique and reached by every
 configuration (Section 4), so every case is compared node by node with the serial FMM: same
 +inf mask, exits exact, relative error <= 1e-10 (FP32 mode: 4 n 2^-24)."""
 import numpy as np
@@ -71,13 +72,43 @@ def test_random_configuration_pair_matches_oracle(orc, case):
     run_case(orc, *draw_pair(case))
 
 
+def draw_sched(case: int):
+    """A larger grid (40..120 nodes per axis, FP32 speeds over [0.2, 2], 1-4 exits) in a random
+    schedule -- rounds in one launch, rounds driven from the host, or the round-free ring --
+    with or without jittered visit orders, so that the rounds' lists span many lengths against
+    the pop segments."""
+    rng = np.random.default_rng(300_000 + case)
+    nx, ny, nz = (int(v) for v in rng.integers(40, 121, size=3))
+    F = rng.uniform(0.2, 2.0, size=(nz, ny, nx)).astype(np.float32)
+    ns = int(rng.integers(1, 5))
+    src = {(int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))) for _ in range(ns)}
+    src = np.array(sorted(src), dtype=np.int64)
+    q = rng.uniform(0.0, 0.2, size=len(src))
+    sched = int(rng.choice([0, 0, 2, 3]))
+    cfg = {
+        "cell": int(rng.choice([4, 8, 8])),
+        "inner": int(rng.choice([1, 1, 2, 4])) if sched != 3 else int(rng.choice([1, 2])),
+        "delta": 0.0, "shuffle": 0, "max_sweeps": 0, "f32": True, "mode": "fp64",
+        "schedule": sched, "jitter": int(rng.choice([0, 0, 1 + case])),
+    }
+    p = W.Problem(f"sched{case}", F, 1.0 / 64, src, q, cfg["cell"], 0.0,
+                  {"workload": "random sweep, schedules"})
+    return p, cfg
+
+
+@pytest.mark.parametrize("case", range(60))
+def test_random_schedule_matches_oracle(orc, case):
+    run_case(orc, *draw_sched(case))
+
+
 def run_case(orc, p, cfg):
     import torch
     from paper_1306_4743_amd import eik
     dev = torch.device("cuda:0")
     F = torch.from_numpy(np.ascontiguousarray(p.F)).to(dev)
     kw = dict(cell=cfg["cell"], inner=cfg["inner"], delta=cfg["delta"], shuffle=cfg["shuffle"],
-              max_sweeps=cfg["max_sweeps"])
+              max_sweeps=cfg["max_sweeps"], schedule=cfg.get("schedule", 0),
+              jitter=cfg.get("jitter", 0))
     mode = cfg["mode"]
     if mode == "polish":
         u = eik.solve(F, p.h, p.src, p.q, mode=eik.EIK_MODE_FP32, **kw)
