@@ -46,12 +46,14 @@ def solve(dev, p, **kw):
     return u.cpu().numpy(), rc, st
 
 
-@pytest.mark.parametrize("inner", [1, 2, 3])
-@pytest.mark.parametrize("cell", [8, 4, 16])
+# Every in-cell solver the round-free schedule runs at each cell size (two sweep streams stop
+# at cells of 8).
+CELL_INNER = [(c, i) for c in (8, 4, 16) for i in (1, 2, 3) if not (c == 16 and i == 3)]
+
+
+@pytest.mark.parametrize("cell,inner", CELL_INNER)
 @pytest.mark.parametrize("name", ["maze", "osc", "random", "shell", "checker"])
 def test_async_matches_oracle(orc, dev, name, cell, inner):
-    if inner == 3 and cell == 16:
-        pytest.skip("two sweep streams stop at cells of 8")
     p = {"maze": lambda: W.maze(97, seed=3),
          "osc": lambda: W.oscillatory(65, periods=4),
          "random": lambda: W.random_small(23, 5, n_sources=3, nx=37, ny=13),
