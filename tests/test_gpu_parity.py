@@ -406,6 +406,35 @@ def test_bumps_1025_precision_modes(orc, torch_dev):
         del got
 
 
+@pytest.mark.parametrize("inner", INNERS)
+@pytest.mark.parametrize("cell", [8, 4])
+def test_diagonal_plane_source(orc, torch_dev, cell, inner):
+    """Exits on the whole plane i + j + k = n - 1 (F = 1, q = 0; 33^3, 561 exits): the oracle,
+    and, away from the cube's faces, the closed form |m| h / sqrt(3) m layers off the plane (three
+    equal upwind values in every local solve along the chain)."""
+    import torch
+    from paper_1306_4743_amd import eik
+    n = 33
+    K = n - 1
+    src = np.array([(i, j, K - i - j) for i in range(n) for j in range(n) if 0 <= K - i - j < n],
+                   dtype=np.int64)
+    h, F = 1.0 / (n - 1), np.ones((n, n, n))
+    u = eik.solve(torch.from_numpy(F).to(torch_dev), h, src, np.zeros(len(src)), cell=cell,
+                  inner=inner)
+    rc, _ = eik.status()
+    assert rc == 0
+    got = u.cpu().numpy()
+    want = orc.fmm(F, h, src, np.zeros(len(src)))
+    p = W.Problem("diag", F, h, src, np.zeros(len(src)), cell, 0.0, {})
+    compare(got, want, p)
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    m = i + j + k - K
+    sel = ((m > 0) & (np.minimum(np.minimum(i, j), k) >= m)) | \
+          ((m < 0) & (np.maximum(np.maximum(i, j), k) <= n - 1 + m))
+    closed = np.abs(m[sel]) * h / math.sqrt(3.0)
+    assert float(np.max(np.abs(got[sel] - closed) / closed)) <= 1e-13
+
+
 SAMPLES_1025 = os.path.join(os.path.dirname(__file__), "golden", "bumps1025_oracle_samples.npz")
 
 

@@ -277,3 +277,40 @@ def test_progress_variant_is_the_same_fmm(orc, capfd):
     lines = [ln for ln in err.splitlines() if ln.startswith("oracle FMM:")]
     assert len(lines) == 33 ** 3 // 4096
     assert lines[-1] == f"oracle FMM: {len(lines) * 4096} of {33 ** 3} nodes accepted"
+
+
+def _diagonal_plane_source(n: int):
+    """F = 1, h = 1/(n - 1), exits with q = 0 on every node of the plane i + j + k = n - 1."""
+    K = n - 1
+    src = np.array([(i, j, K - i - j) for i in range(n) for j in range(n) if 0 <= K - i - j < n],
+                   dtype=np.int64)
+    return np.ones((n, n, n)), 1.0 / (n - 1), src, np.zeros(len(src)), K
+
+
+def _diagonal_layer_error(U, h, K, n):
+    """Largest relative deviation from |m| h / sqrt(3) over the nodes m layers off the plane
+    whose three upwind neighbours lie one layer closer (far side: i, j, k >= m; near side:
+    i, j, k <= n - 1 - |m|), and how many such nodes there are."""
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    m = i + j + k - K
+    far = (m > 0) & (np.minimum(np.minimum(i, j), k) >= m)
+    near = (m < 0) & (np.maximum(np.maximum(i, j), k) <= n - 1 + m)
+    sel = far | near
+    want = np.abs(m[sel]) * h / math.sqrt(3.0)
+    return float(np.max(np.abs(U[sel] - want) / want)), int(sel.sum())
+
+
+def test_diagonal_plane_source_closed_form(orc):
+    """A node m layers off an exit plane i + j + k = const whose three upwind neighbours all lie
+    one layer closer has three equal axis values a, so eq. (2) gives U = a + h/(F sqrt(3)) (the
+    three-term case), and by induction U = |m| h / sqrt(3) exactly up to the square root's
+    rounding: the three-term branch along chains of up to 16 nodes, on both sides of the plane.
+    A dropped three-term branch or the wrong root fails it (pinned below)."""
+    n = 17
+    F, h, src, q, K = _diagonal_plane_source(n)
+    err, count = _diagonal_layer_error(orc.fmm(F, h, src, q), h, K, n)
+    assert count > 500
+    assert err <= 2.0 ** -50, err
+    for variant in (1, 2):
+        bad, _ = _diagonal_layer_error(orc.fmm_planted(F, h, src, q, variant), h, K, n)
+        assert bad > 1e-3, (variant, bad)
