@@ -406,18 +406,24 @@ def test_bumps_1025_precision_modes(orc, torch_dev):
         del got
 
 
+@pytest.mark.parametrize("plane", ["xyz", "xy"])
 @pytest.mark.parametrize("inner", INNERS)
 @pytest.mark.parametrize("cell", [8, 4])
-def test_diagonal_plane_source(orc, torch_dev, cell, inner):
-    """Exits on the whole plane i + j + k = n - 1 (F = 1, q = 0; 33^3, 561 exits): the oracle,
-    and, away from the cube's faces, the closed form |m| h / sqrt(3) m layers off the plane (three
-    equal upwind values in every local solve along the chain)."""
+def test_diagonal_plane_source(orc, torch_dev, cell, inner, plane):
+    """Exits on a whole diagonal plane (F = 1, q = 0, 33^3): i + j + k = n - 1 (561 exits) or
+    i + j = n - 1 through every k (1089 exits).  The oracle, and, away from the cube's faces, the
+    closed form |m| h / sqrt(3) (three equal upwind values in every local solve along the chain)
+    or |m| h / sqrt(2) (two, with the z neighbours in the node's own layer: the tie between two
+    and three terms) m layers off the plane."""
     import torch
     from paper_1306_4743_amd import eik
     n = 33
     K = n - 1
-    src = np.array([(i, j, K - i - j) for i in range(n) for j in range(n) if 0 <= K - i - j < n],
-                   dtype=np.int64)
+    if plane == "xyz":
+        src = np.array([(i, j, K - i - j) for i in range(n) for j in range(n)
+                        if 0 <= K - i - j < n], dtype=np.int64)
+    else:
+        src = np.array([(i, K - i, k) for i in range(n) for k in range(n)], dtype=np.int64)
     h, F = 1.0 / (n - 1), np.ones((n, n, n))
     u = eik.solve(torch.from_numpy(F).to(torch_dev), h, src, np.zeros(len(src)), cell=cell,
                   inner=inner)
@@ -428,10 +434,14 @@ def test_diagonal_plane_source(orc, torch_dev, cell, inner):
     p = W.Problem("diag", F, h, src, np.zeros(len(src)), cell, 0.0, {})
     compare(got, want, p)
     k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
-    m = i + j + k - K
-    sel = ((m > 0) & (np.minimum(np.minimum(i, j), k) >= m)) | \
-          ((m < 0) & (np.maximum(np.maximum(i, j), k) <= n - 1 + m))
-    closed = np.abs(m[sel]) * h / math.sqrt(3.0)
+    if plane == "xyz":
+        m = i + j + k - K
+        lo, hi, terms = np.minimum(np.minimum(i, j), k), np.maximum(np.maximum(i, j), k), 3.0
+    else:
+        m = i + j - K
+        lo, hi, terms = np.minimum(i, j), np.maximum(i, j), 2.0
+    sel = ((m > 0) & (lo >= m)) | ((m < 0) & (hi <= n - 1 + m))
+    closed = np.abs(m[sel]) * h / math.sqrt(terms)
     assert float(np.max(np.abs(got[sel] - closed) / closed)) <= 1e-13
 
 

@@ -314,3 +314,24 @@ def test_diagonal_plane_source_closed_form(orc):
     for variant in (1, 2):
         bad, _ = _diagonal_layer_error(orc.fmm_planted(F, h, src, q, variant), h, K, n)
         assert bad > 1e-3, (variant, bad)
+
+
+def test_axis_pair_plane_source_closed_form(orc):
+    """Exits on the plane i + j = n - 1 through every k (F = 1, q = 0): a node m layers off it
+    whose x and y upwind neighbours both lie one layer closer has two equal axis values a, and
+    its z neighbours lie in its own layer, so they add nothing (they sit exactly where eq. (2)
+    switches from two to three terms): U = a + h/(F sqrt(2)), and by induction |m| h / sqrt(2)
+    up to rounding -- the two-term branch and the tie between two and three terms."""
+    n = 17
+    K, h = n - 1, 1.0 / (n - 1)
+    src = np.array([(i, K - i, k) for i in range(n) for k in range(n)], dtype=np.int64)
+    F, q = np.ones((n, n, n)), np.zeros(len(src))
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    m = i + j - K
+    sel = ((m > 0) & (np.minimum(i, j) >= m)) | ((m < 0) & (np.maximum(i, j) <= n - 1 + m))
+    want = np.abs(m[sel]) * h / math.sqrt(2.0)
+    U = orc.fmm(F, h, src, q)
+    assert sel.sum() > 4000
+    assert float(np.max(np.abs(U[sel] - want) / want)) <= 2.0 ** -50
+    bad = orc.fmm_planted(F, h, src, q, 2)  # the wrong root
+    assert float(np.max(np.abs(bad[sel] - want) / want)) > 1e-3
