@@ -1732,9 +1732,12 @@ k_solve(SolveParams P) {
     load_plane_regs<R, INNER>(pr, lane);
     unsigned long long visits = 0, deferred = 0;
     int rounds_done = 0;
-    // Per-workgroup histograms of visits (sweeps; log2 of cycles), flushed at the end.
+    // Per-workgroup histograms of visits (sweeps; log2 of cycles) and counters, flushed at the
+    // end.
     __shared__ unsigned int s_hist[64];
+    __shared__ unsigned long long s_cnt[ST_COUNT];
     if (threadIdx.x < 64) s_hist[threadIdx.x] = 0u;
+    if (threadIdx.x < ST_COUNT) s_cnt[threadIdx.x] = 0ull;
     __syncthreads();
 
     const int nwaves_total = (int)gridDim.x * W;
@@ -1942,23 +1945,26 @@ k_solve(SolveParams P) {
             break;
         }
     }
-    // Counters.
+    // Counters: summed over the workgroup's waves in LDS, then one device atomic per counter and
+    // workgroup (a launch per round in the host-driven loop makes this flush per round).
     if (lane == 0) {
-        atomicAdd(&P.stats[ST_VISITS], visits);
-        atomicAdd(&P.stats[ST_SWEEPS], cnt.sweeps);
-        atomicAdd(&P.stats[ST_UPDATES], cnt.updates);
-        atomicAdd(&P.stats[ST_DEFERRED], deferred);
-        atomicAdd(&P.stats[ST_REQUEUED], cnt.requeued);
-        atomicAdd(&P.stats[ST_CYC_POP], cyc_pop);
-        atomicAdd(&P.stats[ST_CYC_STAGE], cnt.cyc_stage);
-        atomicAdd(&P.stats[ST_CYC_SWEEP], cnt.cyc_sweep);
-        atomicAdd(&P.stats[ST_CYC_WRITE], cnt.cyc_write);
-        atomicAdd(&P.stats[ST_CYC_WAIT], cyc_wait);
-        if (P.count_workers) atomicAdd(&P.stats[ST_WORKERS], 1ull);
-        if (blockIdx.x == 0 && wave == 0) atomicAdd(&P.stats[ST_ROUNDS], (unsigned long long)rounds_done);
+        atomicAdd(&s_cnt[ST_VISITS], visits);
+        atomicAdd(&s_cnt[ST_SWEEPS], cnt.sweeps);
+        atomicAdd(&s_cnt[ST_UPDATES], cnt.updates);
+        atomicAdd(&s_cnt[ST_DEFERRED], deferred);
+        atomicAdd(&s_cnt[ST_REQUEUED], cnt.requeued);
+        atomicAdd(&s_cnt[ST_CYC_POP], cyc_pop);
+        atomicAdd(&s_cnt[ST_CYC_STAGE], cnt.cyc_stage);
+        atomicAdd(&s_cnt[ST_CYC_SWEEP], cnt.cyc_sweep);
+        atomicAdd(&s_cnt[ST_CYC_WRITE], cnt.cyc_write);
+        atomicAdd(&s_cnt[ST_CYC_WAIT], cyc_wait);
+        if (P.count_workers) atomicAdd(&s_cnt[ST_WORKERS], 1ull);
+        if (blockIdx.x == 0 && wave == 0) atomicAdd(&s_cnt[ST_ROUNDS], (unsigned long long)rounds_done);
     }
     // Every workgroup leaves the round loop in the same round, so all its waves get here.
     __syncthreads();
+    if (threadIdx.x < ST_COUNT && s_cnt[threadIdx.x])
+        atomicAdd(&P.stats[threadIdx.x], s_cnt[threadIdx.x]);
     if (threadIdx.x < 64 && s_hist[threadIdx.x])
         atomicAdd(&P.stats[ST_HIST_SWEEPS + threadIdx.x], (unsigned long long)s_hist[threadIdx.x]);
 }
